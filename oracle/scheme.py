@@ -1,0 +1,443 @@
+"""RHS assembly, constrained transport, SSP-RK3 and CFL step (oracle, FP64).
+
+Paper, Introduction: 3-D finite differences with high-order reconstruction,
+after ECHO.  One right-hand-side evaluation, in order:
+  1. ghost fill of the 8 centred primitives;
+  2. for each direction d: MP5 states of rho, p, u^1..3 and the two
+     transverse centred B at d-faces f in [-3, n_d + 1] over the whole
+     transverse ghosted range; normal B = B_face / sqrt(gamma_face);
+     pointwise fluxes, conserved variables and speeds of both states; HLL
+     flux (0 on faces where sqrt(gamma) = 0); the per-face data for the
+     edge field: v^d and v^c (c = d+1 mod 3) of both states and a+-;
+  3. edge fields (upwind constrained transport, Londrillo & Del Zanna 2004),
+     family e with d = e+1, c = e+2 (mod 3), at edges offset by 1/2 in d
+     and c:
+       - v^d, v^c of both d-face states and B^d (d-faces) reconstructed
+         along c with MP5 (side b), B^c (c-faces) along d (side a);
+       - vt = alpha_edge v - beta_edge; E^{ab} = vt^c_{ab} B^{d,b} - vt^d_{ab} B^{c,a};
+       - a_d^pm = max over the two d-faces next to the edge, a_c^pm likewise;
+       - E_e = sum_ab w^d_a w^c_b E^{ab} + a_d^+ a_d^-/(a_d^+ + a_d^-) (B^{c,R} - B^{c,L})
+               - a_c^+ a_c^-/(a_c^+ + a_c^-) (B^{d,R} - B^{d,L}),
+         w_L = a^+/(a^+ + a^-), w_R = a^-/(a^+ + a^-) (1/2 and 0 if a^+ + a^- < 1e-300);
+  4. L[hydro] = -sum_d D_d F_d + s (metric sources) at interior cells;
+     L[B^n] = -D_{n+1} E_{n+2} + D_{n+2} E_{n+1} at owned faces (indices mod 3).
+SSP-RK3 (Shu & Osher 1988): U^(s) = a_s U^n + b_s (U^(s-1) + dt L(U^(s-1)))
+with (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3), every stage followed by the
+ghost fill of the face fields and the inversion (with floors) at interior
+cells.  dt = C / max_cells sum_d max(|lambda+_d|, |lambda-_d|)/Delta_d from
+P^n with the centre metric.
+"""
+import math
+import numpy as np
+
+from . import fd
+from .fd import take, deriv, interp
+from .mp5 import face_states
+from .physics import state, flux, cons, speeds, prim2cons
+from .hll import hll_speeds, hll_flux
+from .c2p import newton, warm_guess
+from .boundary import fill_centred, fill_faces
+from .sources import sources
+
+PRIM = ("rho", "u1", "u2", "u3", "p", "B1", "B2", "B3")
+HYDRO = ("D", "S1", "S2", "S3", "tau")
+FACE = ("Bf1", "Bf2", "Bf3")
+LOCS = ("C", "F1", "F2", "E3")
+GEOM = ("alpha", "beta1", "beta2", "beta3", "g11", "g12", "g13", "g22", "g23", "g33",
+        "gu11", "gu12", "gu13", "gu22", "gu23", "gu33", "sqrtg")
+DERIV = (["d1_alpha", "d2_alpha", "d1_beta1", "d1_beta2", "d1_beta3",
+          "d2_beta1", "d2_beta2", "d2_beta3"]
+         + ["d1_" + c for c in ("g11", "g12", "g13", "g22", "g23", "g33")]
+         + ["d2_" + c for c in ("g11", "g12", "g13", "g22", "g23", "g33")])
+FACE_LOC = ("F1", "F2", "C")     # metric location of d-faces
+EDGE_LOC = ("F2", "F1", "E3")    # metric location of edge family e
+
+
+class Metric:
+    """Metric tables as {loc: {name: array (1, N2, N1)}} plus centre
+    derivatives; parsed from the documented table layout."""
+
+    def __init__(self, tables):
+        t = np.asarray(tables, dtype=np.float64)
+        assert t.shape[0] == 4 * len(GEOM) + len(DERIV)
+        self.loc = {}
+        for li, loc in enumerate(LOCS):
+            self.loc[loc] = {nm: t[li * len(GEOM) + q][None]
+                             for q, nm in enumerate(GEOM)}
+        base = 4 * len(GEOM)
+        self.der = {nm: t[base + q][None] for q, nm in enumerate(DERIV)}
+
+    @staticmethod
+    def sel(m, d, lo, hi, g):
+        """Restrict a location dict along direction d (x^3 is broadcast)."""
+        if d == 2:
+            return m
+        return {k: take(v, d, lo, hi, g) for k, v in m.items()}
+
+    @staticmethod
+    def interior(m, g):
+        return {k: v[:, g:-g, g:-g] for k, v in m.items()}
+
+
+def minkowski_tables(grid):
+    g = grid.ng
+    t = np.zeros((4 * len(GEOM) + len(DERIV), grid.n[1] + 2 * g, grid.n[0] + 2 * g))
+    for li in range(4):
+        for nm in ("alpha", "g11", "g22", "g33", "gu11", "gu22", "gu33", "sqrtg"):
+            t[li * len(GEOM) + GEOM.index(nm)] = 1.0
+    return t
+
+
+SSPRK3 = ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))
+
+
+def rk_combine(un, u, l, a, b, dt):
+    """One SSP-RK3 stage: a U^n + b (U + dt L)."""
+    return a * un + b * (u + dt * l)
+
+
+def _nan(shape):
+    return np.full(shape, np.nan)
+
+
+class Solver:
+    def __init__(self, grid, tables=None):
+        self.grid = grid
+        self.g = grid.ng
+        self.gam = grid.gamma_ad
+        self.met = Metric(minkowski_tables(grid) if tables is None else tables)
+        shp = grid.shape
+        self.P = {k: _nan(shp) for k in PRIM}
+        self.U = {k: _nan(shp) for k in HYDRO + FACE}
+        self.stats = {}
+        # radius at centres (interior), for the floors
+        g = self.g
+        if grid.coord == 1:
+            x1 = grid.x0[0] + (np.arange(grid.n[0]) + 0.5) * grid.dx[0]
+            self.r_int = np.exp(x1)[None, None, :]
+        else:
+            self.r_int = None
+
+    # ---------------------------------------------------------- helpers
+    def interior(self, a):
+        return fd.interior(a, self.g)
+
+    def set_interior(self, a, val):
+        g = self.g
+        a[g:-g, g:-g, g:-g] = val
+
+    def centre_metric(self):
+        return Metric.interior(self.met.loc["C"], self.g)
+
+    # ---------------------------------------------------------- initial data
+    def curl_potential(self, A):
+        """B_face = curl_D A at owned faces: B^n = D_{n+1} A_{n+2} - D_{n+2} A_{n+1}."""
+        g, gr = self.g, self.grid
+        for nd in range(3):
+            d1, d2 = (nd + 1) % 3, (nd + 2) % 3
+            t1 = deriv(A["A%d" % (d2 + 1)], d1, 0, gr.n[d1], gr.dx[d1], g)
+            t2 = deriv(A["A%d" % (d1 + 1)], d2, 0, gr.n[d2], gr.dx[d2], g)
+            t1 = _restrict_others(t1, d1, g, gr)
+            t2 = _restrict_others(t2, d2, g, gr)
+            f = _nan(gr.shape)
+            self.set_interior(f, t1 - t2)
+            self.U["Bf%d" % (nd + 1)] = f
+        fill_faces(self.U, gr)
+
+    def set_face_fields(self, data):
+        for k in FACE:
+            self.U[k] = np.array(data["B%sf" % k[-1]], dtype=np.float64)
+        fill_faces(self.U, self.grid)
+
+    def centred_b(self):
+        """B^i = I_i(B_face^i) / sqrt(gamma) at interior cells."""
+        g, gr = self.g, self.grid
+        sg = self.centre_metric()["sqrtg"]
+        out = []
+        for d in range(3):
+            bi = interp(self.U["Bf%d" % (d + 1)], d, 0, gr.n[d], g)
+            bi = _restrict_others(bi, d, g, gr)
+            out.append(bi / sg)
+        return out
+
+    def set_primitives(self, data):
+        """Interior rho, u^i, p from data; B from the face fields; U from P."""
+        for k in ("rho", "u1", "u2", "u3", "p"):
+            self.set_interior(self.P[k], data[k])
+        self.prim2cons()
+
+    def prim2cons(self):
+        b = self.centred_b()
+        for i in range(3):
+            self.set_interior(self.P["B%d" % (i + 1)], b[i])
+        P = {k: self.interior(v) for k, v in self.P.items()}
+        c = prim2cons(P["rho"], (P["u1"], P["u2"], P["u3"]), P["p"], tuple(b),
+                      self.centre_metric(), self.gam)
+        for k, v in zip(HYDRO, c):
+            self.set_interior(self.U[k], v)
+        fill_centred(self.P, self.grid)
+
+    # ---------------------------------------------------------- RHS pieces
+    def sweep(self, d):
+        g, gr, gam = self.g, self.grid, self.gam
+        n = gr.n[d]
+        lo, hi = -3, n + 2
+        c = (d + 1) % 3
+        P = self.P
+        rec = {}
+        for k in ("rho", "p", "u1", "u2", "u3"):
+            rec[k] = face_states(P[k], d, lo, hi, g, take)
+        for t in range(3):
+            if t != d:
+                rec["B%d" % (t + 1)] = face_states(P["B%d" % (t + 1)], d, lo, hi, g, take)
+        mf = Metric.sel(self.met.loc[FACE_LOC[d]], d, lo, hi, g)
+        sg = mf["sqrtg"]
+        bn_face = take(self.U["Bf%d" % (d + 1)], d, lo, hi, g)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            bn = np.where(sg != 0.0, bn_face / np.where(sg != 0.0, sg, 1.0), 0.0)
+        sts = []
+        for side in (0, 1):
+            u = tuple(rec["u%d" % (t + 1)][side] for t in range(3))
+            b = tuple(bn if t == d else rec["B%d" % (t + 1)][side] for t in range(3))
+            sts.append(state(rec["rho"][side], u, rec["p"][side], b, mf, gam))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            fl, fr = flux(sts[0], mf, d), flux(sts[1], mf, d)
+            ul, ur = cons(sts[0], mf), cons(sts[1], mf)
+        lpl, lml = speeds(sts[0], mf, d, gam)
+        lpr, lmr = speeds(sts[1], mf, d, gam)
+        ap, am = hll_speeds(lpl, lml, lpr, lmr)
+        axis = np.broadcast_to(sg == 0.0, ap.shape)
+        out = {}
+        with np.errstate(divide="ignore", invalid="ignore"):
+            for q, name in enumerate(HYDRO):
+                fh = hll_flux(fl[q], fr[q], ul[q], ur[q], ap, am)
+                out["F_" + name] = np.where(axis, 0.0, fh)
+        out["vdL"], out["vdR"] = sts[0]["v"][d], sts[1]["v"][d]
+        out["vcL"], out["vcR"] = sts[0]["v"][c], sts[1]["v"][c]
+        out["ap"], out["am"] = ap, am
+        full = {}
+        for k, v in out.items():
+            a = _nan(gr.shape)
+            fd.put(a, d, lo, hi, g, np.broadcast_to(v, take(a, d, lo, hi, g).shape))
+            full[k] = a
+        return full
+
+    def edge(self, e, fdat):
+        """Edge field E_e from the face data of the d and c sweeps."""
+        g, gr = self.g, self.grid
+        d, c = (e + 1) % 3, (e + 2) % 3
+        nd, nc = gr.n[d], gr.n[c]
+        D, C = fdat[d], fdat[c]
+        # reconstruct d-face data along c to the edge (side b)
+        def along_c(q):
+            l, r = face_states(q, c, -3, nc + 2, g, take)
+            return take(l, d, -3, nd + 2, g), take(r, d, -3, nd + 2, g)
+        vd = {("L", b): x for b, x in zip("LR", along_c(D["vdL"]))}
+        vd.update({("R", b): x for b, x in zip("LR", along_c(D["vdR"]))})
+        vc = {("L", b): x for b, x in zip("LR", along_c(D["vcL"]))}
+        vc.update({("R", b): x for b, x in zip("LR", along_c(D["vcR"]))})
+        bd = dict(zip("LR", along_c(self.U["Bf%d" % (d + 1)])))
+        # reconstruct B^c (c-faces) along d (side a)
+        l, r = face_states(self.U["Bf%d" % (c + 1)], d, -3, nd + 2, g, take)
+        bc = {"L": take(l, c, -3, nc + 2, g), "R": take(r, c, -3, nc + 2, g)}
+        # speeds: max over the two faces adjacent to the edge
+        def adj(q, along, other, n_along, n_other):
+            x0 = take(q, along, -3, n_along + 2, g)
+            x1 = take(q, along, -2, n_along + 3, g)
+            m = np.maximum(x0, x1)
+            return take(m, other, -3, n_other + 2, g)
+        apd = adj(D["ap"], c, d, nc, nd)
+        amd = adj(D["am"], c, d, nc, nd)
+        apc = adj(C["ap"], d, c, nd, nc)
+        amc = adj(C["am"], d, c, nd, nc)
+        me = Metric.sel(Metric.sel(self.met.loc[EDGE_LOC[e]], d, -3, nd + 2, g),
+                        c, -3, nc + 2, g)
+        al = me["alpha"]
+        betd, betc = me["beta%d" % (d + 1)], me["beta%d" % (c + 1)]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            sd = apd + amd
+            sc = apc + amc
+            tiny_d, tiny_c = sd < 1e-300, sc < 1e-300
+            wd = {"L": np.where(tiny_d, 0.5, apd / sd), "R": np.where(tiny_d, 0.5, amd / sd)}
+            wc = {"L": np.where(tiny_c, 0.5, apc / sc), "R": np.where(tiny_c, 0.5, amc / sc)}
+            kd = np.where(tiny_d, 0.0, apd * amd / sd)
+            kc = np.where(tiny_c, 0.0, apc * amc / sc)
+        ee = 0.0
+        for a_ in "LR":
+            for b_ in "LR":
+                vtd = al * vd[(a_, b_)] - betd
+                vtc = al * vc[(a_, b_)] - betc
+                eab = vtc * bd[b_] - vtd * bc[a_]
+                ee = ee + wd[a_] * wc[b_] * eab
+        ee = ee + kd * (bc["R"] - bc["L"]) - kc * (bd["R"] - bd["L"])
+        out = _nan(gr.shape)
+        sl = [slice(None)] * 3
+        sl[fd.AXIS[d]] = slice(-3 + g, nd + 2 + g)
+        sl[fd.AXIS[c]] = slice(-3 + g, nc + 2 + g)
+        out[tuple(sl)] = ee
+        return out
+
+    def rhs_parts(self):
+        """Returns (L_hydro dict at interior cells, L_face dict at owned faces,
+        face data, edges).  P ghosts must be filled."""
+        g, gr = self.g, self.grid
+        fdat = [self.sweep(d) for d in range(3)]
+        edges = [self.edge(e, fdat) for e in range(3)]
+        lh = {}
+        for name in HYDRO:
+            tot = 0.0
+            for d in range(3):
+                t = deriv(fdat[d]["F_" + name], d, 0, gr.n[d], gr.dx[d], g)
+                tot = tot - _restrict_others(t, d, g, gr)
+            lh[name] = tot
+        src = sources({k: self.interior(v) for k, v in self.P.items()},
+                      self.centre_metric(), Metric.interior(self.met.der, g), self.gam)
+        for name in HYDRO:
+            lh[name] = lh[name] + src[name]
+        lf = {}
+        for nd in range(3):
+            d1, d2 = (nd + 1) % 3, (nd + 2) % 3
+            t1 = _restrict_others(deriv(edges[d2], d1, 0, gr.n[d1], gr.dx[d1], g), d1, g, gr)
+            t2 = _restrict_others(deriv(edges[d1], d2, 0, gr.n[d2], gr.dx[d2], g), d2, g, gr)
+            lf["Bf%d" % (nd + 1)] = -t1 + t2
+        return lh, lf, fdat, edges
+
+    def rhs(self):
+        fill_centred(self.P, self.grid)
+        lh, lf, _, _ = self.rhs_parts()
+        out = dict(lh)
+        out.update(lf)
+        return out
+
+    # ---------------------------------------------------------- inversion
+    def cons2prim(self, guess="warm"):
+        g, gr, gam = self.g, self.grid, self.gam
+        m = self.centre_metric()
+        b = self.centred_b()
+        sg = m["sqrtg"]
+        U = {k: self.interior(v) for k, v in self.U.items()}
+        P = {k: self.interior(v) for k, v in self.P.items()}
+        dd, tau = U["D"] / sg, U["tau"] / sg
+        s = (U["S1"] / sg, U["S2"] / sg, U["S3"] / sg)
+        if guess == "warm":
+            y0 = warm_guess(P["rho"], (P["u1"], P["u2"], P["u3"]), P["p"], m, gam)
+        else:
+            y0 = gam * (tau + dd)
+        res = newton(dd, s, tau, b, m, gam, y0, tol=gr.newton_tol, maxit=gr.newton_maxit)
+        ok = res["ok"]
+        rho = np.where(ok, res["rho"], P["rho"])
+        p = np.where(ok, res["p"], P["p"])
+        u = [np.where(ok, res["u"][i], P["u%d" % (i + 1)]) for i in range(3)]
+        nfl_rho = nfl_p = nwcap = 0
+        floored = np.zeros(ok.shape, dtype=bool)
+        if gr.rho_fl_a > 0.0 or gr.p_fl_a > 0.0 or gr.w_max > 0.0:
+            r = self.r_int if self.r_int is not None else 1.0
+            if gr.rho_fl_a > 0.0:
+                rfl = gr.rho_fl_a * r ** gr.rho_fl_n
+                low = rho < rfl
+                rho = np.where(low, rfl, rho)
+                floored |= low
+                nfl_rho = int(low.sum())
+            if gr.p_fl_a > 0.0:
+                pfl = gr.p_fl_a * r ** gr.p_fl_n
+                low = p < pfl
+                p = np.where(low, pfl, p)
+                floored |= low
+                nfl_p = int(low.sum())
+            if gr.w_max > 0.0:
+                from .physics import lower
+                ul = lower(m, tuple(u))
+                uu = ul[0] * u[0] + ul[1] * u[1] + ul[2] * u[2]
+                wcur = np.sqrt(1.0 + uu)
+                cap = wcur > gr.w_max
+                fac = np.sqrt((gr.w_max ** 2 - 1.0) / np.where(cap, uu, 1.0))
+                u = [np.where(cap, fac * x, x) for x in u]
+                floored |= cap
+                nwcap = int(cap.sum())
+        vals = {"rho": rho, "u1": u[0], "u2": u[1], "u3": u[2], "p": p,
+                "B1": b[0], "B2": b[1], "B3": b[2]}
+        for k, v in vals.items():
+            self.set_interior(self.P[k], np.broadcast_to(v, ok.shape))
+        if floored.any():
+            c = prim2cons(rho, tuple(u), p, tuple(b), m, gam)
+            for k, v in zip(HYDRO, c):
+                self.set_interior(self.U[k], np.where(floored, v, U[k]))
+        it = res["iters"]
+        self.stats = {"n_fail": int((~ok).sum()), "iters_sum": int(it.sum()),
+                      "iters_max": int(it.max()) if it.size else 0,
+                      "n_floor_rho": nfl_rho, "n_floor_p": nfl_p, "n_wcap": nwcap}
+        return self.stats
+
+    # ---------------------------------------------------------- time step
+    def cfl_dt(self):
+        gr, gam = self.grid, self.gam
+        m = self.centre_metric()
+        P = {k: self.interior(v) for k, v in self.P.items()}
+        st = state(P["rho"], (P["u1"], P["u2"], P["u3"]), P["p"],
+                   (P["B1"], P["B2"], P["B3"]), m, gam)
+        tot = 0.0
+        for d in range(3):
+            lp, lm = speeds(st, m, d, gam)
+            tot = tot + np.maximum(np.abs(lp), np.abs(lm)) / gr.dx[d]
+        return gr.cfl / float(np.max(tot))
+
+    def stage(self, un, a, b, dt):
+        g = self.g
+        fill_centred(self.P, self.grid)
+        lh, lf, _, _ = self.rhs_parts()
+        for name in HYDRO:
+            cur = self.interior(self.U[name])
+            self.set_interior(self.U[name], rk_combine(self.interior(un[name]), cur, lh[name], a, b, dt))
+        for name in FACE:
+            cur = self.interior(self.U[name])
+            self.set_interior(self.U[name], rk_combine(self.interior(un[name]), cur, lf[name], a, b, dt))
+        fill_faces(self.U, self.grid)
+        return self.cons2prim()
+
+    def rk_step(self, dt=None):
+        if dt is None or dt <= 0.0:
+            dt = self.cfl_dt()
+        un = {k: v.copy() for k, v in self.U.items()}
+        stats = []
+        for a, b in SSPRK3:
+            stats.append(self.stage(un, a, b, dt))
+        self.last_stage_stats = stats
+        return dt
+
+    # ---------------------------------------------------------- diagnostics
+    def div_b(self):
+        g, gr = self.g, self.grid
+        tot = 0.0
+        for d in range(3):
+            t = deriv(self.U["Bf%d" % (d + 1)], d, 0, gr.n[d], gr.dx[d], g)
+            tot = tot + _restrict_others(t, d, g, gr)
+        return tot
+
+    def diagnostics(self):
+        out = {}
+        for k in HYDRO + FACE:
+            out["sum_" + k] = float(np.sum(self.interior(self.U[k])))
+        dv = self.div_b()
+        out["max_divb"] = float(np.max(np.abs(dv)))
+        P = {k: self.interior(v) for k, v in self.P.items()}
+        out["rho_min"], out["rho_max"] = float(P["rho"].min()), float(P["rho"].max())
+        out["p_min"], out["p_max"] = float(P["p"].min()), float(P["p"].max())
+        return out
+
+
+def _restrict_others(a, d, g, grid):
+    """Restrict an array that is interior along d to the interior along the
+    other two directions."""
+    sl = [slice(None)] * 3
+    for t in range(3):
+        if t != d:
+            n = grid.n[t]
+            ax = fd.AXIS[t]
+            if a.shape[ax] == 1:
+                continue
+            sl[ax] = slice(g, g + n)
+    return a[tuple(sl)]
+
+
+def new_solver(grid, tables=None):
+    return Solver(grid, tables)
