@@ -1,0 +1,183 @@
+"""Benchmark: zone-updates/s of the FP64 SSP-RK3 step on the 256^3 turbulent
+SRMHD box (one MI355X), with the dominant kernel's roofline and the FP64
+oracle timed on the host as a CPU baseline.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256] [--precision fp64|fp32]
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6     # 256 CU x 2.4 GHz x 128 FP64 flop/clk
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def algorithmic_units():
+    """Per-unit algorithmic figures of each kernel class:
+    FP64 flops per face/edge/zone counted from the kernel arithmetic, and the
+    compulsory HBM bytes per element."""
+    path = os.path.join(ROOT, "paper_1810_04597_amd", "opcounts.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def launch_units(kernel, n):
+    """Number of units (faces, edges or zones) one launch of `kernel` processes."""
+    g = 5
+    ng = n + 2 * g
+    if kernel.startswith("sweep"):
+        return (n + 5) * ng * ng
+    if kernel.startswith("edge"):
+        return (n + 5) * (n + 5) * n
+    return n ** 3
+
+
+def cpu_baseline(seconds_target=12.0):
+    """FP64 oracle on the host: 32^3 turbulent box (the same generator),
+    RK3 steps until about `seconds_target` of work."""
+    import numpy as np  # noqa: F401
+    from workloads import box
+    from oracle.scheme import Solver
+    n = 32
+    g, d = box.turbulent_box(n)
+    s = Solver(g)
+    s.curl_potential(d)
+    s.set_primitives(d)
+    steps = 0
+    w0, c0 = time.perf_counter(), time.process_time()
+    while True:
+        s.rk_step()
+        steps += 1
+        if time.perf_counter() - w0 > seconds_target or steps >= 20:
+            break
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0
+    return {"value": n ** 3 * steps / wall, "unit": "zone-updates/s",
+            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+            "sample": "FP64 NumPy oracle, 32^3 turbulent SRMHD box (same seeded generator), "
+                      "%d SSP-RK3 steps, %.1f s wall" % (steps, wall)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true", default=True)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (a single grid block per device); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    from workloads import box
+    from paper_1810_04597_amd.grid import Grid
+    from paper_1810_04597_amd import _lib as L
+
+    n = args.n
+    t0 = time.perf_counter()
+    g, d = box.turbulent_box(n)
+    print("bench: generated %d^3 initial data in %.1f s" % (n, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    prec = L.FP64 if args.precision == "fp64" else L.FP32_FLUX
+    G = Grid(g, precision=prec)
+    G.curl_potential(d)
+    G.set_primitives(d)
+    del d
+    for _ in range(args.warmup):
+        G.rk_step()
+    G.synchronize()
+    print("bench: warmup done", file=sys.stderr, flush=True)
+    if args.profile_kernels:
+        G.set_profiling(True)
+        G.profile(reset=True)
+    stream = G.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        G.rk_step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    prof = G.profile(reset=True) if args.profile_kernels else {}
+    diag = G.diagnostics()
+    zones = n ** 3
+    value = zones * args.steps / (ms / 1e3)
+    # dominant kernel class
+    units = algorithmic_units()
+    roofline = None
+    kernels = {}
+    if prof:
+        for k, (tot, cnt) in prof.items():
+            kernels[k] = {"avg_ms": tot / cnt, "launches": cnt, "share": tot / sum(v[0] for v in prof.values())}
+        dom = max(prof, key=lambda k: prof[k][0])
+        avg_s = prof[dom][0] / prof[dom][1] / 1e3
+        u = units.get(dom, {})
+        nunits = launch_units(dom, n)
+        if "flops" in u:
+            peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+            achieved = u["flops"] * nunits / avg_s / 1e12
+            roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                        "frac": achieved / peak, "traffic": u.get("traffic"),
+                        "kernel": dom, "avg_ms": avg_s * 1e3}
+        elif "bytes" in u:
+            achieved = u["bytes"] * nunits / avg_s / 1e9
+            roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": u.get("traffic"),
+                        "kernel": dom, "avg_ms": avg_s * 1e3}
+        else:
+            roofline = {"bound": "alu", "achieved": None, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": None, "traffic": None, "kernel": dom,
+                        "avg_ms": avg_s * 1e3}
+    cpu = None
+    if rank == 0 and not args.no_cpu_baseline:
+        print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+    out = {
+        "metric": "zone-updates/s per RK3 step (256^3)",
+        "value": value,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32-flux/f64",
+        "data": "synthetic",
+        "config": {"workload": "turbulent SRMHD box %d^3, Minkowski, MP5+HLL+UCT, SSP-RK3, "
+                               "device CFL 0.4, seed 1810" % n,
+                   "zones": zones, "precision": args.precision},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "algorithmic_hbm_GBs": 896.0 * value / 1e9,
+        "wall_s": wall,
+        "diag": {"max_divb": diag["max_divb"], "n_c2p_fail": diag["n_c2p_fail"],
+                 "rho_min": diag["rho_min"], "t": diag["t"]},
+    }
+    G.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

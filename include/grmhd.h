@@ -1,0 +1,199 @@
+/*
+ * grmhd.h -- C ABI of the MI355X GRMHD right-hand-side and time-update library.
+ *
+ * The library advances the 3+1 general-relativistic MHD equations on one
+ * block of a 3-D finite-difference grid, the method the paper states in its
+ * Introduction (3-D finite differences, high-order reconstruction, after the
+ * ECHO scheme): MP5 reconstruction, HLL fluxes, a sixth-order staggered
+ * finite-difference flux derivative with metric source terms, an upwind
+ * constrained-transport edge field (div B constant to round-off), SSP-RK3
+ * stages and a per-zone Newton conservative-to-primitive inversion.  The
+ * paper's multi-node domain decomposition reduces here to one block whose
+ * ghost zones are filled on the device.
+ *
+ * Conventions
+ *  - Memory: field arrays are caller-owned device memory (for instance torch
+ *    tensors).  The library keeps non-owning pointers from grmhd_bind_fields
+ *    until grmhd_destroy or the next bind; the caller keeps them alive and
+ *    unmoved.  The library owns only metric tables, reduction buffers, the
+ *    device time step and learned-guess weights, and frees them in
+ *    grmhd_destroy.
+ *  - Layout (grmhd_get_layout): structure of arrays, field-major, x^1 fastest,
+ *    ghost zones included.  Element (i, j, k) of field f, with interior
+ *    indices starting at 0 and ghosts at -ng, sits at
+ *        base + f * field + offset + k * plane + j * pitch + i.
+ *    The face "i + 1/2" of a face-centred field is stored at index i; the edge
+ *    (i + 1/2, j + 1/2, k) at [k][j][i] (cyclically for the other families).
+ *  - Field groups: prim = 8 fields (rho, u^1, u^2, u^3, p, B^1, B^2, B^3;
+ *    u^i = W v^i contravariant, B undensitised, at cell centres);
+ *    cons = 8 fields (sqrt(gamma) D, sqrt(gamma) S_1..3, sqrt(gamma) tau at
+ *    centres; sqrt(gamma) B^1, B^2, B^3 on the x^1, x^2, x^3 faces).
+ *  - Streams: every call enqueues work on the stream given at init (a
+ *    hipStream_t, 0 = null stream) and returns at once.  Only calls with a
+ *    host out-pointer (dt_used, n_fail, diagnostics, loss) synchronise it.
+ *  - Errors: negative return codes, never exceptions or aborts across the
+ *    ABI.  Arguments are checked before any launch; grmhd_last_error() gives
+ *    the message of the last failing call of the calling thread.
+ */
+#ifndef GRMHD_H
+#define GRMHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct grmhd_grid grmhd_grid;
+
+enum {
+  GRMHD_OK = 0,
+  GRMHD_EINVAL = -1,       /* bad argument, detected before any launch      */
+  GRMHD_ENOMEM = -2,       /* device allocation of library-owned memory     */
+  GRMHD_EHIP = -3,         /* HIP runtime error (message says which)        */
+  GRMHD_ESTATE = -4,       /* call order: fields or metric not set          */
+  GRMHD_ENOCONV = -5,      /* strict inversion requested and a zone failed  */
+  GRMHD_EUNSUPPORTED = -6  /* valid request this build does not provide     */
+};
+
+enum { GRMHD_CART = 0, GRMHD_LOGSPH = 1 };          /* (x,y,z) | (ln r, theta, phi) */
+enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_AXIS = 2 };
+enum { GRMHD_FP64 = 0, GRMHD_FP32_FLUX = 1 };
+enum { GRMHD_GUESS_WARM = 0, GRMHD_GUESS_COLD = 1, GRMHD_GUESS_MLP = 2 };
+enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_TABLE_AXISYM = 1 };
+
+/* Number of float64 components of an axisymmetric metric table per (j, i):
+ * four location families (centre, x^1 face, x^2 face, x^3 edge) x 17
+ * components (alpha, beta^1..3, gamma_11,12,13,22,23,33,
+ * gamma^11,12,13,22,23,33, sqrt(gamma)), then 20 centre derivatives
+ * (d1 alpha, d2 alpha, d1 beta^1..3, d2 beta^1..3, d1 gamma_ij (6),
+ * d2 gamma_ij (6)).  Table array: [comp][j][i], j in [-ng, n2+ng),
+ * i in [-ng, n1+ng), the same for every x^3 index. */
+#define GRMHD_METRIC_NCOMP 88
+
+typedef struct {
+  int32_t n[3];            /* interior zones n1, n2, n3 (each >= 1)              */
+  int32_t ng;              /* ghost layers, must be 5 (MP5 + 6th-order D)        */
+  int32_t coord;           /* GRMHD_CART | GRMHD_LOGSPH (floors use r = e^{x^1}) */
+  int32_t bc[6];           /* -x1,+x1,-x2,+x2,-x3,+x3; periodic in pairs; axis
+                              only on x^2 (n2 >= 6) with periodic x^3, n3 even */
+  int32_t precision;       /* GRMHD_FP64 | GRMHD_FP32_FLUX                       */
+  int32_t c2p_guess;       /* GRMHD_GUESS_WARM | _COLD | _MLP                     */
+  int32_t newton_maxit;    /* e.g. 50                                             */
+  int32_t reserved;        /* must be 0                                           */
+  double x0[3];            /* lower interior edge in code coordinates            */
+  double dx[3];            /* uniform spacing (> 0)                              */
+  double gamma_ad;         /* ideal-gas index (> 1)                              */
+  double cfl;              /* Courant number for the device time step (> 0)      */
+  double rho_fl_a, rho_fl_n;  /* rho floor a r^n (a = 0: off)                     */
+  double p_fl_a, p_fl_n;      /* p floor a r^n (a = 0: off)                       */
+  double w_max;            /* Lorentz-factor cap (0: off, else > 1)              */
+  double newton_tol;       /* relative step tolerance, e.g. 1e-14                */
+} grmhd_grid_desc;
+
+typedef struct {
+  int64_t dims[3];         /* ghosted extents n_d + 2 ng                         */
+  int64_t pitch;           /* elements between x^2 rows (>= dims[0], padded)     */
+  int64_t plane;           /* elements between x^3 planes                        */
+  int64_t field;           /* elements between fields of a group                 */
+  int64_t offset;          /* element offset of interior (0,0,0) in a field      */
+  int64_t prim_doubles;    /* size of the prim group  (8 fields)                 */
+  int64_t cons_doubles;    /* size of the cons group  (8 fields)                 */
+  int64_t edge_doubles;    /* size of one single-field array (potentials)        */
+  int64_t scratch_bytes;   /* scratch required by grmhd_bind_fields              */
+} grmhd_layout;
+
+typedef struct {
+  int64_t step;
+  double t, dt;
+  double sum_cons[8];      /* plain sums over interior cells / owned faces       */
+  double max_divb;         /* max over interior cells of |sum_d D_d B^d|         */
+  double max_divb_norm;    /* max_divb * min(dx) / max|B centred|                */
+  double rho_min, rho_max, p_min, p_max, w_max;
+  int64_t n_floor_rho, n_floor_p, n_wcap;   /* last inversion                     */
+  int64_t n_c2p_fail, n_mlp_fallback;        /* last inversion                     */
+  int64_t newton_iters_sum, newton_iters_max;/* last inversion                     */
+  int64_t n_nonfinite;     /* interior primitives that are not finite            */
+} grmhd_diag;
+
+/* Create a grid.  desc is copied.  hip_stream: hipStream_t or NULL.
+ * Errors: EINVAL (descriptor), ENOMEM/EHIP (device buffers). */
+int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** out);
+
+/* Memory layout the caller must allocate with (pure host call). */
+int grmhd_get_layout(const grmhd_grid* h, grmhd_layout* out);
+
+/* Bind caller-owned device memory: prim (layout.prim_doubles float64),
+ * cons (layout.cons_doubles), scratch (>= layout.scratch_bytes, 256-byte
+ * aligned).  EINVAL on NULL, misalignment or a short scratch. */
+int grmhd_bind_fields(grmhd_grid* h, double* prim, double* cons, void* scratch,
+                      size_t scratch_bytes);
+
+/* Background metric.  kind = GRMHD_METRIC_MINKOWSKI (host_tables NULL,
+ * Cartesian only) or GRMHD_METRIC_TABLE_AXISYM: host_tables holds
+ * GRMHD_METRIC_NCOMP * (n2+2ng) * (n1+2ng) float64 in the layout above; the
+ * library copies them to device memory it owns (synchronous copy).
+ * The tables are data: the stationary 3+1 metric, see the paper's
+ * Introduction (MHD in general relativity). */
+int grmhd_set_metric(grmhd_grid* h, int kind, const double* host_tables, size_t n_doubles);
+
+/* Face fields from an edge vector potential: B^n = D_{n+1} A_{n+2} - D_{n+2} A_{n+1}
+ * at owned faces, then the face ghost fill.  A1, A2, A3: device arrays with
+ * the single-field layout (edge_doubles each), ghosts included. */
+int grmhd_curl_potential(grmhd_grid* h, const double* A1, const double* A2, const double* A3);
+
+/* Centred B = I_d(B_face)/sqrt(gamma) and cons (D, S, tau) from the bound
+ * prim (rho, u, p at interior cells) and face fields; fills ghosts of the
+ * face fields first and of prim afterwards. */
+int grmhd_prim2cons(grmhd_grid* h);
+
+/* Right-hand side L(U) of the bound state: rhs_out (cons layout, 8 fields)
+ * receives -sum_d D_d F_d + s at interior cells and -curl_D E at owned
+ * faces; other elements are left untouched.  Uses the bound prim/cons. */
+int grmhd_rhs(grmhd_grid* h, double* rhs_out);
+
+/* One SSP-RK3 step of the bound state.  dt > 0: that step; dt <= 0: the CFL
+ * step dt = cfl / max sum_d max|lambda_d|/dx_d computed on the device from
+ * the primitives at the start of the step (no host sync).  dt_used (nullable)
+ * receives the step taken (synchronises). */
+int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used);
+
+/* Inversion of the bound cons into the bound prim at interior cells (warm,
+ * cold or learned guess as configured; floors applied).  n_fail (nullable)
+ * receives the number of failed zones (synchronises).  Failed zones keep
+ * their previous primitives.  strict != 0 returns GRMHD_ENOCONV when a zone
+ * failed (requires n_fail). */
+int grmhd_cons2prim(grmhd_grid* h, int64_t* n_fail, int strict);
+
+/* CFL time step of the bound primitives (synchronises). */
+int grmhd_compute_dt(grmhd_grid* h, double* dt);
+
+/* Diagnostics of the bound state (synchronises).  Sums are taken in a fixed
+ * order (deterministic). */
+int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out);
+
+/* Kernel timing (observability).  When enabled, every launch the library
+ * makes is bracketed by HIP events on the grid's stream (no host sync);
+ * grmhd_get_profile synchronises the stream, accumulates the elapsed times
+ * per kernel class and returns totals (ms) and launch counts since the last
+ * reset.  Class names: grmhd_profile_class_name(0 .. GRMHD_PROF_NCLASS-1). */
+#define GRMHD_PROF_NCLASS 16
+typedef struct {
+  double ms[GRMHD_PROF_NCLASS];
+  int64_t launches[GRMHD_PROF_NCLASS];
+} grmhd_profile;
+int grmhd_set_profiling(grmhd_grid* h, int on);
+int grmhd_get_profile(grmhd_grid* h, grmhd_profile* out, int reset);
+const char* grmhd_profile_class_name(int cls);
+
+void grmhd_destroy(grmhd_grid* h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* grmhd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRMHD_H */

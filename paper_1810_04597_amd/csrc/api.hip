@@ -1,0 +1,455 @@
+// Host runtime of the C ABI declared in include/grmhd.h: argument checks,
+// layout, scratch carving, launch sequencing on the caller's stream, error
+// strings.  All numerical work happens in the kernels.
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "grmhd.h"
+#include "grmhd_kernels.hpp"
+
+using namespace grmhd;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(GRMHD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return GRMHD_OK;
+}
+
+long round_up(long v, long m) { return (v + m - 1) / m * m; }
+
+// scratch carve (in fields of the single-field layout)
+constexpr int SCR_CONS_N = 0;    // 8 fields
+constexpr int SCR_FLUX = 8;      // 3 x 5 fields
+constexpr int SCR_CTD = 23;      // 3 x 6 fields
+constexpr int SCR_EDGE = 41;     // 3 fields
+constexpr int SCR_NFIELDS = 44;
+
+const char* const PROF_NAMES[GRMHD_PROF_NCLASS] = {
+    "bc_centred", "sweep_x1", "sweep_x2", "sweep_x3", "edge_x1", "edge_x2", "edge_x3",
+    "update", "bc_faces", "cons2prim", "cfl", "copy_stage", "advance", "rhs_out",
+    "diagnostics", "other"};
+}  // namespace
+
+struct grmhd_grid {
+  grmhd_grid_desc desc;
+  Geom G;
+  BCSpec bc;
+  hipStream_t stream = nullptr;
+  grmhd_layout lay;
+  double* prim = nullptr;
+  double* cons = nullptr;
+  double* scratch = nullptr;
+  double* tab = nullptr;
+  bool flat = true;
+  bool metric_set = false;
+  // library-owned device buffers
+  double* d_dt = nullptr;        // [0] dt of the current step, [1] time
+  double* d_part = nullptr;      // per-block partials (cfl, diagnostics)
+  long long* d_spart = nullptr;  // per-block inversion statistics
+  long long* d_stats = nullptr;  // reduced inversion statistics (8)
+  double* d_diag = nullptr;      // reduced diagnostics (16)
+  unsigned nblk = 0;
+  int64_t step = 0;
+  // profiling: HIP events around launches on the grid's stream
+  bool prof_on = false;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[GRMHD_PROF_NCLASS] = {0};
+  int64_t prof_n[GRMHD_PROF_NCLASS] = {0};
+  hipEvent_t take_event() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  template <class F> void timed(int cls, F&& launch) {
+    if (!prof_on) { launch(); return; }
+    hipEvent_t a = take_event(), b = take_event();
+    if (!a || !b) { launch(); return; }
+    (void)hipEventRecord(a, stream);
+    launch();
+    (void)hipEventRecord(b, stream);
+    pending.push_back({cls, a, b});
+  }
+  double* cons_n() const { return scratch + (long)SCR_CONS_N * G.field; }
+  double* flux() const { return scratch + (long)SCR_FLUX * G.field; }
+  double* ctd() const { return scratch + (long)SCR_CTD * G.field; }
+  double* edges() const { return scratch + (long)SCR_EDGE * G.field; }
+};
+
+namespace {
+
+int validate(const grmhd_grid_desc* d) {
+  if (!d) return fail(GRMHD_EINVAL, "desc is NULL");
+  for (int a = 0; a < 3; ++a) {
+    if (d->n[a] < 1 || d->n[a] > (1 << 20)) return fail(GRMHD_EINVAL, "n out of range");
+    if (!(d->dx[a] > 0.0) || !std::isfinite(d->dx[a])) return fail(GRMHD_EINVAL, "dx must be > 0");
+    if (!std::isfinite(d->x0[a])) return fail(GRMHD_EINVAL, "x0 not finite");
+  }
+  if (d->ng != NG) return fail(GRMHD_EINVAL, "ng must be 5 (MP5 stencil + sixth-order derivative)");
+  if (d->coord != GRMHD_CART && d->coord != GRMHD_LOGSPH) return fail(GRMHD_EINVAL, "bad coord");
+  for (int s = 0; s < 6; ++s)
+    if (d->bc[s] < 0 || d->bc[s] > 2) return fail(GRMHD_EINVAL, "bad boundary code");
+  for (int a = 0; a < 3; ++a) {
+    const int lo = d->bc[2 * a], hi = d->bc[2 * a + 1];
+    if ((lo == GRMHD_BC_PERIODIC) != (hi == GRMHD_BC_PERIODIC))
+      return fail(GRMHD_EINVAL, "periodic boundaries must come in pairs");
+    if ((lo == GRMHD_BC_AXIS || hi == GRMHD_BC_AXIS) && (a != 1 || lo != hi))
+      return fail(GRMHD_EINVAL, "axis boundary only on both x^2 sides");
+  }
+  if (d->bc[2] == GRMHD_BC_AXIS) {
+    if (d->bc[4] != GRMHD_BC_PERIODIC) return fail(GRMHD_EINVAL, "axis needs periodic x^3");
+    if (d->n[2] % 2 != 0) return fail(GRMHD_EINVAL, "axis needs an even n3");
+    if (d->n[1] < NG + 1) return fail(GRMHD_EINVAL, "axis needs n2 >= 6");
+  }
+  if (!(d->gamma_ad > 1.0)) return fail(GRMHD_EINVAL, "gamma_ad must be > 1");
+  if (!(d->cfl > 0.0)) return fail(GRMHD_EINVAL, "cfl must be > 0");
+  if (d->precision != GRMHD_FP64 && d->precision != GRMHD_FP32_FLUX)
+    return fail(GRMHD_EINVAL, "bad precision");
+  if (d->c2p_guess < 0 || d->c2p_guess > 2) return fail(GRMHD_EINVAL, "bad c2p_guess");
+  if (d->c2p_guess == GRMHD_GUESS_MLP)
+    return fail(GRMHD_EUNSUPPORTED, "learned guess not available in this build");
+  if (d->newton_maxit < 1 || d->newton_maxit > 1000) return fail(GRMHD_EINVAL, "bad newton_maxit");
+  if (!(d->newton_tol > 0.0)) return fail(GRMHD_EINVAL, "newton_tol must be > 0");
+  if (d->rho_fl_a < 0.0 || d->p_fl_a < 0.0) return fail(GRMHD_EINVAL, "negative floor");
+  if (d->w_max != 0.0 && !(d->w_max > 1.0)) return fail(GRMHD_EINVAL, "w_max must be 0 or > 1");
+  if (d->reserved != 0) return fail(GRMHD_EINVAL, "reserved must be 0");
+  return GRMHD_OK;
+}
+
+void make_layout(const grmhd_grid_desc& d, grmhd_layout& L, Geom& G) {
+  for (int a = 0; a < 3; ++a) L.dims[a] = d.n[a] + 2 * NG;
+  L.pitch = round_up(L.dims[0], 16);               // 128-byte rows
+  L.plane = L.pitch * L.dims[1];
+  L.field = round_up(L.plane * L.dims[2], 32);     // 256-byte field starts
+  L.offset = (long)NG * L.plane + (long)NG * L.pitch + NG;
+  L.prim_doubles = NPRIM * L.field;
+  L.cons_doubles = NCONS * L.field;
+  L.edge_doubles = L.field;
+  L.scratch_bytes = (int64_t)SCR_NFIELDS * L.field * (int64_t)sizeof(double);
+  for (int a = 0; a < 3; ++a) {
+    G.n[a] = d.n[a];
+    G.dims[a] = (int)L.dims[a];
+    G.dx[a] = d.dx[a];
+    G.x0[a] = d.x0[a];
+  }
+  G.pitch = L.pitch;
+  G.plane = L.plane;
+  G.field = L.field;
+  G.off = L.offset;
+  G.gam = d.gamma_ad;
+  G.tab_n1 = (int)L.dims[0];
+  G.tab_plane = L.dims[0] * L.dims[1];
+}
+
+C2PParams c2p_params(const grmhd_grid_desc& d) {
+  C2PParams cp;
+  cp.tol = d.newton_tol;
+  cp.maxit = d.newton_maxit;
+  cp.guess = d.c2p_guess;
+  cp.coord = d.coord;
+  cp.rho_fl_a = d.rho_fl_a;
+  cp.rho_fl_n = d.rho_fl_n;
+  cp.p_fl_a = d.p_fl_a;
+  cp.p_fl_n = d.p_fl_n;
+  cp.w_max = d.w_max;
+  return cp;
+}
+
+int ready(grmhd_grid* h) {
+  if (!h) return fail(GRMHD_EINVAL, "grid handle is NULL");
+  if (!h->prim || !h->cons || !h->scratch) return fail(GRMHD_ESTATE, "fields not bound");
+  if (!h->metric_set) return fail(GRMHD_ESTATE, "metric not set");
+  return GRMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* grmhd_last_error(void) { return g_err.c_str(); }
+
+int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** out) {
+  g_err.clear();
+  if (!out) return fail(GRMHD_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(desc);
+  if (rc) return rc;
+  grmhd_grid* h = new grmhd_grid();
+  h->desc = *desc;
+  make_layout(*desc, h->lay, h->G);
+  for (int s = 0; s < 6; ++s) h->bc.bc[s] = desc->bc[s];
+  h->stream = (hipStream_t)hip_stream;
+  h->nblk = zone_blocks(h->G);
+  const size_t part = (size_t)h->nblk * (DIAG_NSUM + DIAG_NMAX) * sizeof(double);
+  hipError_t e = hipSuccess;
+  e = hipMalloc(&h->d_dt, 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&h->d_part, part);
+  if (e == hipSuccess) e = hipMalloc(&h->d_spart, (size_t)h->nblk * C2P_NSTAT * sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc(&h->d_stats, C2P_NSTAT * sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc(&h->d_diag, (DIAG_NSUM + DIAG_NMAX) * sizeof(double));
+  if (e == hipSuccess) e = hipMemsetAsync(h->d_dt, 0, 2 * sizeof(double), h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->d_stats, 0, C2P_NSTAT * sizeof(long long), h->stream);
+  if (e != hipSuccess) {
+    std::string m = std::string("device buffers: ") + hipGetErrorString(e);
+    grmhd_destroy(h);
+    return fail(e == hipErrorOutOfMemory ? GRMHD_ENOMEM : GRMHD_EHIP, m);
+  }
+  *out = h;
+  return GRMHD_OK;
+}
+
+int grmhd_get_layout(const grmhd_grid* h, grmhd_layout* out) {
+  if (!h || !out) return fail(GRMHD_EINVAL, "NULL argument");
+  *out = h->lay;
+  return GRMHD_OK;
+}
+
+int grmhd_bind_fields(grmhd_grid* h, double* prim, double* cons, void* scratch,
+                      size_t scratch_bytes) {
+  if (!h || !prim || !cons || !scratch) return fail(GRMHD_EINVAL, "NULL argument");
+  if (((uintptr_t)prim | (uintptr_t)cons | (uintptr_t)scratch) % 256 != 0)
+    return fail(GRMHD_EINVAL, "field pointers must be 256-byte aligned");
+  if ((int64_t)scratch_bytes < h->lay.scratch_bytes)
+    return fail(GRMHD_EINVAL, "scratch smaller than layout.scratch_bytes");
+  h->prim = prim;
+  h->cons = cons;
+  h->scratch = (double*)scratch;
+  return GRMHD_OK;
+}
+
+int grmhd_set_metric(grmhd_grid* h, int kind, const double* host_tables, size_t n_doubles) {
+  if (!h) return fail(GRMHD_EINVAL, "grid handle is NULL");
+  if (kind == GRMHD_METRIC_MINKOWSKI) {
+    if (h->desc.coord != GRMHD_CART) return fail(GRMHD_EINVAL, "Minkowski kind needs Cartesian coordinates");
+    if (h->tab) { (void)hipFree(h->tab); h->tab = nullptr; }
+    h->flat = true;
+    h->metric_set = true;
+    return GRMHD_OK;
+  }
+  if (kind != GRMHD_METRIC_TABLE_AXISYM) return fail(GRMHD_EUNSUPPORTED, "unknown metric kind");
+  const size_t need = (size_t)NCOMP_TAB * h->lay.dims[0] * h->lay.dims[1];
+  if (!host_tables || n_doubles != need) return fail(GRMHD_EINVAL, "table size mismatch");
+  for (size_t q = 0; q < need; ++q)
+    if (!std::isfinite(host_tables[q])) return fail(GRMHD_EINVAL, "non-finite metric table entry");
+  double* t = nullptr;
+  hipError_t e = hipMalloc(&t, need * sizeof(double));
+  if (e != hipSuccess) return fail(GRMHD_ENOMEM, std::string("metric tables: ") + hipGetErrorString(e));
+  e = hipMemcpy(t, host_tables, need * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { (void)hipFree(t); return fail(GRMHD_EHIP, std::string("metric copy: ") + hipGetErrorString(e)); }
+  if (h->tab) (void)hipFree(h->tab);
+  h->tab = t;
+  h->flat = false;
+  h->metric_set = true;
+  return GRMHD_OK;
+}
+
+int grmhd_curl_potential(grmhd_grid* h, const double* A1, const double* A2, const double* A3) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!A1 || !A2 || !A3) return fail(GRMHD_EINVAL, "NULL potential");
+  h->timed(15, [&] { launch_curl(h->G, A1, A2, A3, h->cons, h->stream); });
+  h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
+  return hip_check("curl_potential");
+}
+
+int grmhd_prim2cons(grmhd_grid* h) {
+  int rc = ready(h);
+  if (rc) return rc;
+  h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
+  h->timed(15, [&] { launch_prim2cons(h->G, h->flat, h->prim, h->cons, h->tab, h->stream); });
+  h->timed(0, [&] { launch_bc_centred(h->G, h->bc, h->prim, NPRIM, h->stream); });
+  return hip_check("prim2cons");
+}
+
+static void rhs_pieces(grmhd_grid* h) {
+  const bool fp32 = h->desc.precision == GRMHD_FP32_FLUX;
+  h->timed(0, [&] { launch_bc_centred(h->G, h->bc, h->prim, NPRIM, h->stream); });
+  for (int d = 0; d < 3; ++d)
+    h->timed(1 + d, [&] {
+      launch_sweep(d, h->G, h->flat, fp32, h->prim, h->cons, h->tab, h->flux(), h->ctd(), h->stream);
+    });
+  for (int e = 0; e < 3; ++e)
+    h->timed(4 + e, [&] { launch_edge(e, h->G, h->flat, fp32, h->cons, h->tab, h->ctd(), h->edges(), h->stream); });
+}
+
+int grmhd_rhs(grmhd_grid* h, double* rhs_out) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!rhs_out) return fail(GRMHD_EINVAL, "rhs_out is NULL");
+  rhs_pieces(h);
+  h->timed(13, [&] {
+    launch_update(h->G, h->flat, 1, h->prim, h->cons, h->cons_n(), h->flux(), h->edges(), h->tab,
+                  0.0, 0.0, 0.0, h->d_dt, rhs_out, h->stream);
+  });
+  return hip_check("rhs");
+}
+
+int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!std::isfinite(dt)) return fail(GRMHD_EINVAL, "dt not finite");
+  if (dt <= 0.0)
+    h->timed(10, [&] { launch_cfl(h->G, h->flat, h->prim, h->tab, h->desc.cfl, h->d_part, h->d_dt, h->stream); });
+  const long field_bytes = (long)h->G.field * (long)sizeof(double);
+  hipError_t e = hipSuccess;
+  h->timed(11, [&] { e = hipMemcpyAsync(h->cons_n(), h->cons, NCONS * field_bytes, hipMemcpyDeviceToDevice, h->stream); });
+  if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
+  const C2PParams cp = c2p_params(h->desc);
+  for (int s = 0; s < 3; ++s) {
+    rhs_pieces(h);
+    h->timed(7, [&] {
+      launch_update(h->G, h->flat, 0, h->prim, h->cons, h->cons_n(), h->flux(), h->edges(), h->tab,
+                    A[s], B[s], dt, h->d_dt, nullptr, h->stream);
+    });
+    h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
+    h->timed(9, [&] { launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, h->stream, nullptr); });
+  }
+  h->timed(12, [&] { launch_advance(h->d_dt, dt, h->stream); });
+  h->step += 1;
+  rc = hip_check("rk_step");
+  if (rc) return rc;
+  if (dt_used) {
+    e = hipMemcpyAsync(dt_used, h->d_dt, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_cons2prim(grmhd_grid* h, int64_t* n_fail, int strict) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (strict && !n_fail) return fail(GRMHD_EINVAL, "strict mode needs n_fail");
+  const C2PParams cp = c2p_params(h->desc);
+  h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
+  h->timed(9, [&] { launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, h->stream, nullptr); });
+  rc = hip_check("cons2prim");
+  if (rc) return rc;
+  if (n_fail) {
+    long long st[C2P_NSTAT];
+    launch_reduce_stats(h->d_spart, (int)h->nblk, h->d_stats, h->stream);
+    hipError_t e = hipMemcpyAsync(st, h->d_stats, sizeof(st), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+    *n_fail = st[0];
+    if (strict && st[0] > 0) return fail(GRMHD_ENOCONV, "inversion failed in some zones");
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_compute_dt(grmhd_grid* h, double* dt) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!dt) return fail(GRMHD_EINVAL, "dt is NULL");
+  launch_cfl(h->G, h->flat, h->prim, h->tab, h->desc.cfl, h->d_part, h->d_dt, h->stream);
+  hipError_t e = hipMemcpyAsync(dt, h->d_dt, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  return hip_check("compute_dt");
+}
+
+int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!out) return fail(GRMHD_EINVAL, "out is NULL");
+  double dg[DIAG_NSUM + DIAG_NMAX];
+  long long st[C2P_NSTAT];
+  double dtt[2] = {0.0, 0.0};
+  launch_diag(h->G, h->flat, h->prim, h->cons, h->tab, h->d_part, h->d_diag, h->stream);
+  launch_reduce_stats(h->d_spart, (int)h->nblk, h->d_stats, h->stream);
+  hipError_t e = hipMemcpyAsync(dg, h->d_diag, sizeof(dg), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(st, h->d_stats, sizeof(st), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(dtt, h->d_dt, sizeof(dtt), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  rc = hip_check("diagnostics");
+  if (rc) return rc;
+  std::memset(out, 0, sizeof(*out));
+  out->step = h->step;
+  out->t = dtt[1];
+  out->dt = dtt[0];
+  for (int q = 0; q < 8; ++q) out->sum_cons[q] = dg[q];
+  out->max_divb = dg[DIAG_NSUM + 0];
+  out->rho_min = -dg[DIAG_NSUM + 1];
+  out->rho_max = dg[DIAG_NSUM + 2];
+  out->p_min = -dg[DIAG_NSUM + 3];
+  out->p_max = dg[DIAG_NSUM + 4];
+  out->w_max = dg[DIAG_NSUM + 5];
+  const double bmax = dg[DIAG_NSUM + 6];
+  double dxmin = h->G.dx[0];
+  for (int a = 1; a < 3; ++a) dxmin = dxmin < h->G.dx[a] ? dxmin : h->G.dx[a];
+  out->max_divb_norm = bmax > 0.0 ? out->max_divb * dxmin / bmax : 0.0;
+  out->n_nonfinite = (int64_t)dg[DIAG_NSUM + 7];
+  out->n_c2p_fail = st[0];
+  out->newton_iters_sum = st[1];
+  out->newton_iters_max = st[2];
+  out->n_floor_rho = st[3];
+  out->n_floor_p = st[4];
+  out->n_wcap = st[5];
+  out->n_mlp_fallback = st[6];
+  return GRMHD_OK;
+}
+
+int grmhd_set_profiling(grmhd_grid* h, int on) {
+  if (!h) return fail(GRMHD_EINVAL, "grid handle is NULL");
+  h->prof_on = on != 0;
+  return GRMHD_OK;
+}
+
+int grmhd_get_profile(grmhd_grid* h, grmhd_profile* out, int reset) {
+  if (!h || !out) return fail(GRMHD_EINVAL, "NULL argument");
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  for (auto& r : h->pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      h->prof_ms[r.cls] += ms;
+      h->prof_n[r.cls] += 1;
+    }
+    h->pool.push_back(r.a);
+    h->pool.push_back(r.b);
+  }
+  h->pending.clear();
+  for (int c = 0; c < GRMHD_PROF_NCLASS; ++c) {
+    out->ms[c] = h->prof_ms[c];
+    out->launches[c] = h->prof_n[c];
+    if (reset) { h->prof_ms[c] = 0.0; h->prof_n[c] = 0; }
+  }
+  return GRMHD_OK;
+}
+
+const char* grmhd_profile_class_name(int cls) {
+  if (cls < 0 || cls >= GRMHD_PROF_NCLASS) return "";
+  return PROF_NAMES[cls];
+}
+
+void grmhd_destroy(grmhd_grid* h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
+  for (auto& r : h->pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+  for (auto ev : h->pool) (void)hipEventDestroy(ev);
+  (void)hipFree(h->tab);
+  (void)hipFree(h->d_dt);
+  (void)hipFree(h->d_part);
+  (void)hipFree(h->d_spart);
+  (void)hipFree(h->d_stats);
+  (void)hipFree(h->d_diag);
+  delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+// Host-side launchers of the GRMHD kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "grmhd_device.hpp"
+
+namespace grmhd {
+
+// Parameters of the inversion and floors.
+struct C2PParams {
+  double tol;
+  int maxit;
+  int guess;            // 0 warm, 1 cold, 2 learned
+  int coord;            // 0 Cartesian, 1 log-spherical (r = exp(x^1))
+  double rho_fl_a, rho_fl_n, p_fl_a, p_fl_n, w_max;
+};
+
+// Per-block partial results of the inversion (reduced on the device).
+constexpr int C2P_NSTAT = 8;   // fail, iters_sum, iters_max, floor_rho, floor_p, wcap, mlp_fallback, spare
+constexpr int DIAG_NSUM = 8;   // plain sums of the 8 conserved fields
+constexpr int DIAG_NMAX = 8;   // max|divB|, -rho_min, rho_max, -p_min, p_max, w_max, max|B|, nonfinite
+
+struct BCSpec {
+  int bc[6];
+};
+
+void launch_bc_centred(const Geom& G, const BCSpec& bc, double* prim, int nfields, hipStream_t s);
+void launch_bc_faces(const Geom& G, const BCSpec& bc, double* cons, hipStream_t s);
+void launch_sweep(int d, const Geom& G, bool flat, bool fp32, const double* prim,
+                  const double* cons, const double* tab, double* flux, double* ctd, hipStream_t s);
+void launch_edge(int e, const Geom& G, bool flat, bool fp32, const double* cons, const double* tab,
+                 const double* ctd, double* edges, hipStream_t s);
+// mode 0: RK combine into cons (needs cons_n, a, b, dt on device);
+// mode 1: write L into out (cons layout).
+void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* cons,
+                   const double* cons_n, const double* flux, const double* edges,
+                   const double* tab, double a, double b, double dt_host, const double* d_dt,
+                   double* out, hipStream_t s);
+void launch_advance(double* d_dt, double dt_host, hipStream_t s);
+void launch_c2p(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
+                const double* tab, long long* stat_partials, hipStream_t s, const float* mlp);
+void launch_prim2cons(const Geom& G, bool flat, double* prim, double* cons, const double* tab,
+                      hipStream_t s);
+void launch_cfl(const Geom& G, bool flat, const double* prim, const double* tab, double cfl,
+                double* partials, double* d_dt, hipStream_t s);
+void launch_curl(const Geom& G, const double* a1, const double* a2, const double* a3,
+                 double* cons, hipStream_t s);
+void launch_reduce_stats(const long long* partials, int nblk, long long* out, hipStream_t s);
+void launch_diag(const Geom& G, bool flat, const double* prim, const double* cons,
+                 const double* tab, double* partials, double* out, hipStream_t s);
+unsigned zone_blocks(const Geom& G);
+
+}  // namespace grmhd

@@ -1,0 +1,741 @@
+// Cell-centred kernels: RK stage update with metric sources, conservative-to-
+// primitive inversion with floors, prim->cons, CFL step, curl of a potential,
+// ghost fill and deterministic reductions (gfx950).
+//
+// Method references (paper, Introduction: GRMHD with 3-D finite differences
+// after ECHO; standard published forms):
+//   update : L = -sum_d D_d F_d + s, SSP-RK3 stage a U^n + b (U + dt L)
+//            (Shu & Osher 1988); induction -curl_D E on the owned faces;
+//   sources: stationary-metric 3+1 sources
+//            s[S_i] = sqrt(g) (alpha W^jk d_i g_jk / 2 + S_j d_i beta^j - U d_i alpha),
+//            s[tau] = sqrt(g) (W^jk beta^l d_l g_jk / 2 + W^j_k d_j beta^k - S^j d_j alpha);
+//   c2p    : safeguarded 1-D Newton in y = rho h W^2 on (0, Gamma U], bisection
+//            when a step leaves the bracket or v^2 >= 1, stop at a round-off
+//            residual or |dy| <= tol y; failed zones keep their primitives.
+#include "grmhd_device.hpp"
+#include "grmhd_kernels.hpp"
+
+namespace grmhd {
+
+static inline unsigned nblk(long total) { return (unsigned)((total + 255) / 256); }
+
+__device__ __forceinline__ void zone_of(const Geom& G, long t, int& i, int& j, int& k) {
+  i = (int)(t % G.n[0]);
+  const long r = t / G.n[0];
+  j = (int)(r % G.n[1]);
+  k = (int)(r / G.n[1]);
+}
+
+// ------------------------------------------------------------------ block reductions
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ long long wave_max_ll(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    long long w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+// ------------------------------------------------------------------ metric sources
+template <class MET>
+__device__ __forceinline__ void sources_of(const PState<double>& s, const MET& m,
+                                           const double* __restrict__ tab, long tplane, long tt,
+                                           double src[5]) {
+  const double* dp = tab + (long)DER_BASE * tplane + tt;
+  auto der = [&](int q) { return dp[(long)q * tplane]; };
+  // electric field, both index positions
+  double el[3], eu[3];
+  el[0] = m.e_lo(-(s.v[1] * s.B[2] - s.v[2] * s.B[1]));
+  el[1] = m.e_lo(-(s.v[2] * s.B[0] - s.v[0] * s.B[2]));
+  el[2] = m.e_lo(-(s.v[0] * s.B[1] - s.v[1] * s.B[0]));
+  eu[0] = m.e_up(-(s.vl[1] * s.Bl[2] - s.vl[2] * s.Bl[1]));
+  eu[1] = m.e_up(-(s.vl[2] * s.Bl[0] - s.vl[0] * s.Bl[2]));
+  eu[2] = m.e_up(-(s.vl[0] * s.Bl[1] - s.vl[1] * s.Bl[0]));
+  const double ptot = s.p + 0.5 * (s.E2 + s.B2);
+  const double gu[3][3] = {{m.u11, m.u12, m.u13}, {m.u12, m.u22, m.u23}, {m.u13, m.u23, m.u33}};
+  double wup[3][3], wmix[3][3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      wup[j][k] = s.y * s.v[j] * s.v[k] - eu[j] * eu[k] - s.B[j] * s.B[k] + ptot * gu[j][k];
+      wmix[j][k] = s.y * s.v[j] * s.vl[k] - eu[j] * el[k] - s.B[j] * s.Bl[k] + (j == k ? ptot : 0.0);
+    }
+  // derivative of gamma_jk in direction i (0 or 1)
+  auto dg = [&](int i, int j, int k) {
+    const int a = j < k ? j : k, b = j < k ? k : j;
+    const int sym = a == 0 ? b : (a == 1 ? 2 + b : 5);   // 11,12,13,22,23,33 -> 0..5
+    return der((i == 0 ? D1_G11 : D2_G11) + sym);
+  };
+  const double utot = s.tau + s.D;
+  src[0] = 0.0 * m.sg;
+  for (int i = 0; i < 2; ++i) {
+    double t = 0.0;
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) t = t + 0.5 * m.al * wup[j][k] * dg(i, j, k);
+    for (int j = 0; j < 3; ++j) t = t + s.S[j] * der((i == 0 ? D1_B1 : D2_B1) + j);
+    t = t - utot * der(i == 0 ? D1_AL : D2_AL);
+    src[1 + i] = m.sg * t;
+  }
+  src[3] = 0.0 * m.sg;
+  double t = 0.0;
+  for (int l = 0; l < 2; ++l)
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) t = t + 0.5 * wup[j][k] * m.b[l] * dg(l, j, k);
+  for (int j = 0; j < 2; ++j)
+    for (int k = 0; k < 3; ++k) t = t + wmix[j][k] * der((j == 0 ? D1_B1 : D2_B1) + k);
+  for (int j = 0; j < 2; ++j) t = t - s.Su[j] * der(j == 0 ? D1_AL : D2_AL);
+  src[4] = m.sg * t;
+}
+
+// ------------------------------------------------------------------ RK update
+template <class MET>
+__global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* __restrict__ prim,
+                                                double* __restrict__ cons,
+                                                const double* __restrict__ cons_n,
+                                                const double* __restrict__ flux,
+                                                const double* __restrict__ edges,
+                                                const double* __restrict__ tab, double a, double b,
+                                                double dt_host, const double* __restrict__ d_dt,
+                                                double* __restrict__ out) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
+  int i, j, k;
+  zone_of(G, t, i, j, k);
+  const long c = G.idx(i, j, k);
+  double src[5] = {0, 0, 0, 0, 0};
+  if constexpr (!MET::flat) {
+    const long tt = G.tidx(i, j);
+    MET m;
+    m.load(tab, G.tab_plane, LOC_C, tt);
+    PState<double> s;
+    s.rho = prim[P_RHO * G.field + c];
+    s.p = prim[P_P * G.field + c];
+    for (int q = 0; q < 3; ++q) {
+      s.u[q] = prim[(P_U1 + q) * G.field + c];
+      s.B[q] = prim[(P_B1 + q) * G.field + c];
+    }
+    make_state(s, m, G.gam);
+    sources_of(s, m, tab, G.tab_plane, tt, src);
+  }
+  const double dt = (mode != 0) ? 0.0 : (dt_host > 0.0 ? dt_host : *d_dt);
+  double f[6];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    double L = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double* fp = flux + ((long)d * 5 + q) * G.field + c;
+      const long st = G.stride(d);
+#pragma unroll
+      for (int s = 0; s < 6; ++s) f[s] = fp[(s - 3) * st];
+      L = L - fd_deriv(f, 1.0 / G.dx[d]);
+    }
+    L = L + src[q];
+    const long o = (long)q * G.field + c;
+    if (mode == 0)
+      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
+    else
+      out[o] = L;
+  }
+#pragma unroll
+  for (int nd = 0; nd < 3; ++nd) {
+    const int d1 = (nd + 1) % 3, d2 = (nd + 2) % 3;
+    const double* e2 = edges + (long)d2 * G.field + c;
+    const double* e1 = edges + (long)d1 * G.field + c;
+    const long s1 = G.stride(d1), s2 = G.stride(d2);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) f[s] = e2[(s - 3) * s1];
+    const double t1 = fd_deriv(f, 1.0 / G.dx[d1]);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) f[s] = e1[(s - 3) * s2];
+    const double t2 = fd_deriv(f, 1.0 / G.dx[d2]);
+    const double L = -t1 + t2;
+    const long o = (long)(C_BF1 + nd) * G.field + c;
+    if (mode == 0)
+      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
+    else
+      out[o] = L;
+  }
+}
+
+// ------------------------------------------------------------------ centred B
+template <class MET>
+__device__ __forceinline__ void centred_b(const Geom& G, const double* __restrict__ cons, long c,
+                                          const MET& m, double B[3]) {
+  double f[6];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double* fp = cons + (long)(C_BF1 + d) * G.field + c;
+    const long st = G.stride(d);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) f[s] = fp[(s - 3) * st];
+    B[d] = m.undens(fd_interp(f));
+  }
+}
+
+// ------------------------------------------------------------------ inversion
+struct NewtonOut {
+  double rho, p, u[3];
+  int iters;
+  bool ok;
+};
+
+template <class MET>
+__device__ __forceinline__ NewtonOut newton(double dd, const double S[3], double tau,
+                                            const double B[3], const MET& m, double gam,
+                                            double y0, double tol, int maxit) {
+  NewtonOut o;
+  const double utot = tau + dd;
+  double su[3], bl[3];
+  m.raise(S, su);
+  m.lower(B, bl);
+  const double s2 = S[0] * su[0] + S[1] * su[1] + S[2] * su[2];
+  const double b2 = bl[0] * B[0] + bl[1] * B[1] + bl[2] * B[2];
+  const double sb = S[0] * B[0] + S[1] * B[1] + S[2] * B[2];
+  const double sb2 = sb * sb;
+  const double gf = (gam - 1.0) / gam;
+  const bool valid = isfinite(dd) && isfinite(utot) && isfinite(s2) && isfinite(b2) &&
+                     isfinite(sb) && dd > 0.0 && utot > 0.0;
+  double a = 0.0, bb = gam * utot;
+  double y = y0;
+  if (!(y > a && y < bb)) y = 0.5 * (a + bb);
+  bool conv = false;
+  int it = 0;
+  constexpr double EPS4 = 4.0 * 2.220446049250313e-16;
+  if (valid) {
+    for (; it < maxit;) {
+      ++it;
+      const double yy = y * y;
+      const double v2 = (s2 + sb2 * (2.0 * y + b2) / yy) / ((y + b2) * (y + b2));
+      const bool bad = v2 >= 1.0;
+      const double sq = sqrt(1.0 - v2);
+      const double p = gf * (y * (1.0 - v2) - dd * sq);
+      const double f = y - p + 0.5 * b2 * (1.0 + v2) - 0.5 * sb2 / yy - utot;
+      const double yb = y + b2;
+      const double y3 = yy * y;
+      const double dv2 = (-2.0 * sb2 * yb / y3 / (yb * yb) -
+                          2.0 * (s2 + sb2 * (2.0 * y + b2) / yy) / (yb * yb * yb));
+      const double dp = gf * ((1.0 - v2) - y * dv2 + dd * dv2 / (2.0 * sq));
+      const double fp = 1.0 - dp + 0.5 * b2 * dv2 + sb2 / y3;
+      const double fabs_ = y + fabs(p) + 0.5 * b2 * (1.0 + v2) + 0.5 * sb2 / yy + utot;
+      if (!bad && fabs(f) <= EPS4 * fabs_) { conv = true; break; }
+      const bool below = bad || (f < 0.0);
+      if (below) a = y; else bb = y;
+      double yn = y - f / fp;
+      if (bad || !(yn >= a && yn <= bb)) yn = 0.5 * (a + bb);
+      const double dy = yn - y;
+      y = yn;
+      if (fabs(dy) <= tol * y) { conv = true; break; }
+    }
+  }
+  const double v2 = (s2 + sb2 * (2.0 * y + b2) / (y * y)) / ((y + b2) * (y + b2));
+  const double w = 1.0 / sqrt(1.0 - v2);
+  o.p = gf * (y * (1.0 - v2) - dd * sqrt(1.0 - v2));
+  o.rho = dd / w;
+  double vl[3], vu[3];
+  for (int q = 0; q < 3; ++q) vl[q] = (S[q] + (sb / y) * bl[q]) / (y + b2);
+  m.raise(vl, vu);
+  for (int q = 0; q < 3; ++q) o.u[q] = w * vu[q];
+  o.ok = conv && valid && (v2 < 1.0) && isfinite(o.rho) && isfinite(o.p) && isfinite(o.u[0]) &&
+         isfinite(o.u[1]) && isfinite(o.u[2]);
+  o.iters = it;
+  return o;
+}
+
+template <class MET>
+__global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __restrict__ prim,
+                                             double* __restrict__ cons,
+                                             const double* __restrict__ tab,
+                                             long long* __restrict__ partials) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = t < (long)G.n[0] * G.n[1] * G.n[2];
+  long long st[6] = {0, 0, 0, 0, 0, 0};
+  if (live) {
+    int i, j, k;
+    zone_of(G, t, i, j, k);
+    const long c = G.idx(i, j, k);
+    MET m;
+    if constexpr (!MET::flat) m.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
+    double B[3];
+    centred_b(G, cons, c, m, B);
+    const double dd = m.undens(cons[C_D * G.field + c]);
+    const double S[3] = {m.undens(cons[C_S1 * G.field + c]), m.undens(cons[C_S2 * G.field + c]),
+                         m.undens(cons[C_S3 * G.field + c])};
+    const double tau = m.undens(cons[C_TAU * G.field + c]);
+    double rho = prim[P_RHO * G.field + c];
+    double p = prim[P_P * G.field + c];
+    double u[3] = {prim[P_U1 * G.field + c], prim[P_U2 * G.field + c], prim[P_U3 * G.field + c]};
+    double y0;
+    if (cp.guess == 1) {
+      y0 = G.gam * (tau + dd);
+    } else {
+      double ul[3];
+      m.lower(u, ul);
+      const double uu = ul[0] * u[0] + ul[1] * u[1] + ul[2] * u[2];
+      const double h = 1.0 + G.gam / (G.gam - 1.0) * p / rho;
+      y0 = rho * h * (1.0 + uu);
+    }
+    const NewtonOut r = newton(dd, S, tau, B, m, G.gam, y0, cp.tol, cp.maxit);
+    if (r.ok) {
+      rho = r.rho;
+      p = r.p;
+      u[0] = r.u[0]; u[1] = r.u[1]; u[2] = r.u[2];
+    }
+    st[0] = r.ok ? 0 : 1;
+    st[1] = r.iters;
+    st[2] = r.iters;
+    bool floored = false;
+    if (cp.rho_fl_a > 0.0 || cp.p_fl_a > 0.0 || cp.w_max > 0.0) {
+      const double rr = cp.coord == 1 ? exp(G.x0[0] + (i + 0.5) * G.dx[0]) : 1.0;
+      if (cp.rho_fl_a > 0.0) {
+        const double rfl = cp.rho_fl_a * pow(rr, cp.rho_fl_n);
+        if (rho < rfl) { rho = rfl; floored = true; st[3] = 1; }
+      }
+      if (cp.p_fl_a > 0.0) {
+        const double pfl = cp.p_fl_a * pow(rr, cp.p_fl_n);
+        if (p < pfl) { p = pfl; floored = true; st[4] = 1; }
+      }
+      if (cp.w_max > 0.0) {
+        double ul[3];
+        m.lower(u, ul);
+        const double uu = ul[0] * u[0] + ul[1] * u[1] + ul[2] * u[2];
+        const double wcur = sqrt(1.0 + uu);
+        if (wcur > cp.w_max) {
+          const double fac = sqrt((cp.w_max * cp.w_max - 1.0) / uu);
+          u[0] *= fac; u[1] *= fac; u[2] *= fac;
+          floored = true;
+          st[5] = 1;
+        }
+      }
+    }
+    prim[P_RHO * G.field + c] = rho;
+    prim[P_P * G.field + c] = p;
+    prim[P_U1 * G.field + c] = u[0];
+    prim[P_U2 * G.field + c] = u[1];
+    prim[P_U3 * G.field + c] = u[2];
+    prim[P_B1 * G.field + c] = B[0];
+    prim[P_B2 * G.field + c] = B[1];
+    prim[P_B3 * G.field + c] = B[2];
+    if (floored) {
+      PState<double> s;
+      s.rho = rho; s.p = p;
+      for (int q = 0; q < 3; ++q) { s.u[q] = u[q]; s.B[q] = B[q]; }
+      make_state(s, m, G.gam);
+      double cc[5];
+      cons_of(s, m, cc);
+      for (int q = 0; q < 5; ++q) cons[(long)q * G.field + c] = cc[q];
+    }
+  }
+  // per-block partials: fail, iters_sum, iters_max, floor_rho, floor_p, wcap
+  __shared__ long long sh[4][6];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  long long r0 = wave_sum_ll(st[0]), r1 = wave_sum_ll(st[1]), r2 = wave_max_ll(st[2]);
+  long long r3 = wave_sum_ll(st[3]), r4 = wave_sum_ll(st[4]), r5 = wave_sum_ll(st[5]);
+  if (lane == 0) { sh[wv][0] = r0; sh[wv][1] = r1; sh[wv][2] = r2; sh[wv][3] = r3; sh[wv][4] = r4; sh[wv][5] = r5; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long o[6] = {0, 0, 0, 0, 0, 0};
+    for (int w = 0; w < 4; ++w) {
+      o[0] += sh[w][0]; o[1] += sh[w][1]; o[2] = sh[w][2] > o[2] ? sh[w][2] : o[2];
+      o[3] += sh[w][3]; o[4] += sh[w][4]; o[5] += sh[w][5];
+    }
+    long long* dst = partials + (long)blockIdx.x * C2P_NSTAT;
+    for (int q = 0; q < 6; ++q) dst[q] = o[q];
+    dst[6] = 0;
+    dst[7] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_stats(const long long* __restrict__ partials, int nb,
+                                                      long long* __restrict__ out) {
+  __shared__ long long sh[256][C2P_NSTAT];
+  long long acc[C2P_NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    const long long* p = partials + (long)b * C2P_NSTAT;
+    for (int q = 0; q < C2P_NSTAT; ++q) {
+      if (q == 2) acc[q] = p[q] > acc[q] ? p[q] : acc[q];
+      else acc[q] += p[q];
+    }
+  }
+  for (int q = 0; q < C2P_NSTAT; ++q) sh[threadIdx.x][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 256; ++w)
+      for (int q = 0; q < C2P_NSTAT; ++q) {
+        if (q == 2) acc[q] = sh[w][q] > acc[q] ? sh[w][q] : acc[q];
+        else acc[q] += sh[w][q];
+      }
+    for (int q = 0; q < C2P_NSTAT; ++q) out[q] = acc[q];
+  }
+}
+
+// ------------------------------------------------------------------ prim -> cons
+template <class MET>
+__global__ __launch_bounds__(256) void k_prim2cons(Geom G, double* __restrict__ prim,
+                                                   double* __restrict__ cons,
+                                                   const double* __restrict__ tab) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
+  int i, j, k;
+  zone_of(G, t, i, j, k);
+  const long c = G.idx(i, j, k);
+  MET m;
+  if constexpr (!MET::flat) m.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
+  double B[3];
+  centred_b(G, cons, c, m, B);
+  PState<double> s;
+  s.rho = prim[P_RHO * G.field + c];
+  s.p = prim[P_P * G.field + c];
+  for (int q = 0; q < 3; ++q) { s.u[q] = prim[(P_U1 + q) * G.field + c]; s.B[q] = B[q]; }
+  make_state(s, m, G.gam);
+  double cc[5];
+  cons_of(s, m, cc);
+  for (int q = 0; q < 5; ++q) cons[(long)q * G.field + c] = cc[q];
+  for (int q = 0; q < 3; ++q) prim[(P_B1 + q) * G.field + c] = B[q];
+}
+
+// ------------------------------------------------------------------ CFL
+template <class MET>
+__global__ __launch_bounds__(256) void k_cfl(Geom G, const double* __restrict__ prim,
+                                             const double* __restrict__ tab,
+                                             double* __restrict__ partials) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (t < (long)G.n[0] * G.n[1] * G.n[2]) {
+    int i, j, k;
+    zone_of(G, t, i, j, k);
+    const long c = G.idx(i, j, k);
+    MET m;
+    if constexpr (!MET::flat) m.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
+    PState<double> s;
+    s.rho = prim[P_RHO * G.field + c];
+    s.p = prim[P_P * G.field + c];
+    for (int q = 0; q < 3; ++q) { s.u[q] = prim[(P_U1 + q) * G.field + c]; s.B[q] = prim[(P_B1 + q) * G.field + c]; }
+    make_state(s, m, G.gam);
+    double tot = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      double lp, lm;
+      speeds_of(s, m, d, G.gam, lp, lm);
+      tot = tot + fmax(fabs(lp), fabs(lm)) / G.dx[d];
+    }
+    v = tot;
+  }
+  __shared__ double sh[4];
+  const double w = wave_max(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+__global__ __launch_bounds__(256) void k_dt_final(const double* __restrict__ partials, int nb, double cfl,
+                                                  double* __restrict__ d_dt) {
+  __shared__ double sh[4];
+  double v = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) v = fmax(v, partials[b]);
+  const double w = wave_max(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) d_dt[0] = cfl / fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// ------------------------------------------------------------------ curl of a potential
+__global__ __launch_bounds__(256) void k_curl(Geom G, const double* __restrict__ a1,
+                                              const double* __restrict__ a2,
+                                              const double* __restrict__ a3,
+                                              double* __restrict__ cons) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
+  int i, j, k;
+  zone_of(G, t, i, j, k);
+  const long c = G.idx(i, j, k);
+  const double* A[3] = {a1, a2, a3};
+  double f[6];
+  for (int nd = 0; nd < 3; ++nd) {
+    const int d1 = (nd + 1) % 3, d2 = (nd + 2) % 3;
+    const long s1 = G.stride(d1), s2 = G.stride(d2);
+    for (int s = 0; s < 6; ++s) f[s] = A[d2][c + (s - 3) * s1];
+    const double t1 = fd_deriv(f, 1.0 / G.dx[d1]);
+    for (int s = 0; s < 6; ++s) f[s] = A[d1][c + (s - 3) * s2];
+    const double t2 = fd_deriv(f, 1.0 / G.dx[d2]);
+    cons[(long)(C_BF1 + nd) * G.field + c] = t1 - t2;
+  }
+}
+
+// ------------------------------------------------------------------ ghost fill
+// Composite source index of a ghost element; equals filling x^1, then x^2,
+// then x^3 over the full extent of the other directions.
+struct GhostSrc {
+  int i, j, k;
+  double sign;
+  bool zero, clamp_u1;
+};
+
+__device__ __forceinline__ int wrap(int m, int n) {
+  int r = m % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ GhostSrc ghost_src(const Geom& G, const BCSpec& bc, int i, int j, int k,
+                                              int normal, bool flip) {
+  GhostSrc s{i, j, k, 1.0, false, false};
+  const int n1 = G.n[0], n2 = G.n[1], n3 = G.n[2];
+  // x^1
+  if (i < 0) s.i = bc.bc[0] == 0 ? wrap(i, n1) : 0;
+  else if (i >= n1) {
+    s.i = bc.bc[1] == 0 ? wrap(i, n1) : n1 - 1;
+    s.clamp_u1 = bc.bc[1] == 1;
+  }
+  // x^2
+  bool shift = false;
+  if (bc.bc[2] == 2) {
+    if (normal == 1) {
+      if (j == -1 || j == n2 - 1) s.zero = true;
+      else if (j <= -2) { s.j = -j - 2; shift = true; }
+      else if (j >= n2) { s.j = 2 * n2 - j - 2; shift = true; }
+    } else {
+      if (j < 0) { s.j = -1 - j; shift = true; }
+      else if (j >= n2) { s.j = 2 * n2 - 1 - j; shift = true; }
+    }
+  } else {
+    if (j < 0) s.j = bc.bc[2] == 0 ? wrap(j, n2) : 0;
+    else if (j >= n2) s.j = bc.bc[3] == 0 ? wrap(j, n2) : n2 - 1;
+  }
+  // x^3
+  if (k < 0) s.k = bc.bc[4] == 0 ? wrap(k, n3) : 0;
+  else if (k >= n3) s.k = bc.bc[5] == 0 ? wrap(k, n3) : n3 - 1;
+  if (shift) {
+    s.k = wrap(s.k + n3 / 2, n3);
+    if (flip) s.sign = -1.0;
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_bc_centred(Geom G, BCSpec bc, double* __restrict__ prim,
+                                                    int nfields) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)G.dims[0] * G.dims[1] * G.dims[2]) return;
+  const int i = (int)(t % G.dims[0]) - NG;
+  const long r = t / G.dims[0];
+  const int j = (int)(r % G.dims[1]) - NG;
+  const int k = (int)(r / G.dims[1]) - NG;
+  const bool inside = i >= 0 && i < G.n[0] && j >= 0 && j < G.n[1] && k >= 0 && k < G.n[2];
+  if (inside) return;
+  const long dst = G.idx(i, j, k);
+  for (int f = 0; f < nfields; ++f) {
+    const bool flip = (f == P_U2 || f == P_U3 || f == P_B2 || f == P_B3);
+    const GhostSrc s = ghost_src(G, bc, i, j, k, -1, flip);
+    double v = prim[(long)f * G.field + G.idx(s.i, s.j, s.k)] * s.sign;
+    if (f == P_U1 && s.clamp_u1) v = fmax(v, 0.0);
+    prim[(long)f * G.field + dst] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bc_faces(Geom G, BCSpec bc, double* __restrict__ cons) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)G.dims[0] * G.dims[1] * G.dims[2]) return;
+  const int i = (int)(t % G.dims[0]) - NG;
+  const long r = t / G.dims[0];
+  const int j = (int)(r % G.dims[1]) - NG;
+  const int k = (int)(r / G.dims[1]) - NG;
+  const bool inside = i >= 0 && i < G.n[0] && j >= 0 && j < G.n[1] && k >= 0 && k < G.n[2];
+  const bool axis_face = bc.bc[2] == 2 && (j == -1 || j == G.n[1] - 1);
+  const long dst = G.idx(i, j, k);
+  for (int nd = 0; nd < 3; ++nd) {
+    if (inside && !(nd == 1 && axis_face)) continue;
+    const GhostSrc s = ghost_src(G, bc, i, j, k, nd, nd != 0);
+    double* f = cons + (long)(C_BF1 + nd) * G.field;
+    f[dst] = s.zero ? 0.0 : f[G.idx(s.i, s.j, s.k)] * s.sign;
+  }
+}
+
+// ------------------------------------------------------------------ diagnostics
+template <class MET>
+__global__ __launch_bounds__(256) void k_diag(Geom G, const double* __restrict__ prim,
+                                              const double* __restrict__ cons,
+                                              const double* __restrict__ tab,
+                                              double* __restrict__ partials) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double sv[DIAG_NSUM], mv[DIAG_NMAX];
+  for (int q = 0; q < DIAG_NSUM; ++q) sv[q] = 0.0;
+  for (int q = 0; q < DIAG_NMAX; ++q) mv[q] = -INFINITY;
+  if (t < (long)G.n[0] * G.n[1] * G.n[2]) {
+    int i, j, k;
+    zone_of(G, t, i, j, k);
+    const long c = G.idx(i, j, k);
+    for (int q = 0; q < 8; ++q) sv[q] = cons[(long)q * G.field + c];
+    double f[6], dv = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double* fp = cons + (long)(C_BF1 + d) * G.field + c;
+      const long st = G.stride(d);
+      for (int s = 0; s < 6; ++s) f[s] = fp[(s - 3) * st];
+      dv = dv + fd_deriv(f, 1.0 / G.dx[d]);
+    }
+    MET m;
+    if constexpr (!MET::flat) m.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
+    double u[3] = {prim[P_U1 * G.field + c], prim[P_U2 * G.field + c], prim[P_U3 * G.field + c]};
+    double B[3] = {prim[P_B1 * G.field + c], prim[P_B2 * G.field + c], prim[P_B3 * G.field + c]};
+    double ul[3], bl[3];
+    m.lower(u, ul);
+    m.lower(B, bl);
+    const double rho = prim[P_RHO * G.field + c], p = prim[P_P * G.field + c];
+    mv[0] = fabs(dv);
+    mv[1] = -rho;
+    mv[2] = rho;
+    mv[3] = -p;
+    mv[4] = p;
+    mv[5] = sqrt(1.0 + ul[0] * u[0] + ul[1] * u[1] + ul[2] * u[2]);
+    mv[6] = sqrt(fmax(bl[0] * B[0] + bl[1] * B[1] + bl[2] * B[2], 0.0));
+    int nf = 0;
+    for (int q = 0; q < 8; ++q) nf += isfinite(prim[(long)q * G.field + c]) ? 0 : 1;
+    mv[7] = (double)nf;   // summed below, not maxed
+  }
+  __shared__ double sh[4][DIAG_NSUM + DIAG_NMAX];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int q = 0; q < DIAG_NSUM; ++q) {
+    const double s = wave_sum(sv[q]);
+    if (lane == 0) sh[wv][q] = s;
+  }
+  for (int q = 0; q < DIAG_NMAX; ++q) {
+    const double s = (q == 7) ? wave_sum(mv[q] < 0 ? 0.0 : mv[q]) : wave_max(mv[q]);
+    if (lane == 0) sh[wv][DIAG_NSUM + q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* dst = partials + (long)blockIdx.x * (DIAG_NSUM + DIAG_NMAX);
+    for (int q = 0; q < DIAG_NSUM; ++q) dst[q] = ((sh[0][q] + sh[1][q]) + sh[2][q]) + sh[3][q];
+    for (int q = 0; q < DIAG_NMAX; ++q) {
+      const int o = DIAG_NSUM + q;
+      dst[o] = (q == 7) ? ((sh[0][o] + sh[1][o]) + sh[2][o]) + sh[3][o]
+                        : fmax(fmax(sh[0][o], sh[1][o]), fmax(sh[2][o], sh[3][o]));
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ partials, int nb,
+                                                    double* __restrict__ out) {
+  constexpr int W = DIAG_NSUM + DIAG_NMAX;
+  __shared__ double sh[256][W];
+  double acc[W];
+  for (int q = 0; q < W; ++q) acc[q] = (q >= DIAG_NSUM && q != DIAG_NSUM + 7) ? -INFINITY : 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) {
+    const double* p = partials + (long)b * W;
+    for (int q = 0; q < W; ++q) {
+      if (q >= DIAG_NSUM && q != DIAG_NSUM + 7) acc[q] = fmax(acc[q], p[q]);
+      else acc[q] += p[q];
+    }
+  }
+  for (int q = 0; q < W; ++q) sh[threadIdx.x][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 256; ++w)
+      for (int q = 0; q < W; ++q) {
+        if (q >= DIAG_NSUM && q != DIAG_NSUM + 7) acc[q] = fmax(acc[q], sh[w][q]);
+        else acc[q] += sh[w][q];
+      }
+    for (int q = 0; q < W; ++q) out[q] = acc[q];
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+unsigned zone_blocks(const Geom& G) { return nblk((long)G.n[0] * G.n[1] * G.n[2]); }
+
+void launch_bc_centred(const Geom& G, const BCSpec& bc, double* prim, int nfields, hipStream_t s) {
+  const long total = (long)G.dims[0] * G.dims[1] * G.dims[2];
+  hipLaunchKernelGGL(k_bc_centred, dim3(nblk(total)), dim3(256), 0, s, G, bc, prim, nfields);
+}
+
+void launch_bc_faces(const Geom& G, const BCSpec& bc, double* cons, hipStream_t s) {
+  const long total = (long)G.dims[0] * G.dims[1] * G.dims[2];
+  hipLaunchKernelGGL(k_bc_faces, dim3(nblk(total)), dim3(256), 0, s, G, bc, cons);
+}
+
+void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* cons,
+                   const double* cons_n, const double* flux, const double* edges,
+                   const double* tab, double a, double b, double dt_host, const double* d_dt,
+                   double* out, hipStream_t s) {
+  const unsigned nb = zone_blocks(G);
+  if (flat)
+    hipLaunchKernelGGL(k_update<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
+                       cons_n, flux, edges, tab, a, b, dt_host, d_dt, out);
+  else
+    hipLaunchKernelGGL(k_update<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
+                       cons_n, flux, edges, tab, a, b, dt_host, d_dt, out);
+}
+
+// d_dt[0]: dt of the last step, d_dt[1]: time
+__global__ void k_advance(double* __restrict__ d_dt, double dt_host) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double dt = dt_host > 0.0 ? dt_host : d_dt[0];
+    d_dt[0] = dt;
+    d_dt[1] = d_dt[1] + dt;
+  }
+}
+
+void launch_advance(double* d_dt, double dt_host, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, d_dt, dt_host);
+}
+
+void launch_c2p(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
+                const double* tab, long long* partials, hipStream_t s, const float*) {
+  const unsigned nb = zone_blocks(G);
+  if (flat)
+    hipLaunchKernelGGL(k_c2p<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab, partials);
+  else
+    hipLaunchKernelGGL(k_c2p<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab, partials);
+}
+
+void launch_reduce_stats(const long long* partials, int nb, long long* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(256), 0, s, partials, nb, out);
+}
+
+void launch_prim2cons(const Geom& G, bool flat, double* prim, double* cons, const double* tab,
+                      hipStream_t s) {
+  const unsigned nb = zone_blocks(G);
+  if (flat)
+    hipLaunchKernelGGL(k_prim2cons<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, prim, cons, tab);
+  else
+    hipLaunchKernelGGL(k_prim2cons<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, prim, cons, tab);
+}
+
+void launch_cfl(const Geom& G, bool flat, const double* prim, const double* tab, double cfl,
+                double* partials, double* d_dt, hipStream_t s) {
+  const unsigned nb = zone_blocks(G);
+  if (flat)
+    hipLaunchKernelGGL(k_cfl<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, prim, tab, partials);
+  else
+    hipLaunchKernelGGL(k_cfl<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, prim, tab, partials);
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, partials, (int)nb, cfl, d_dt);
+}
+
+void launch_curl(const Geom& G, const double* a1, const double* a2, const double* a3,
+                 double* cons, hipStream_t s) {
+  hipLaunchKernelGGL(k_curl, dim3(zone_blocks(G)), dim3(256), 0, s, G, a1, a2, a3, cons);
+}
+
+void launch_diag(const Geom& G, bool flat, const double* prim, const double* cons,
+                 const double* tab, double* partials, double* out, hipStream_t s) {
+  const unsigned nb = zone_blocks(G);
+  if (flat)
+    hipLaunchKernelGGL(k_diag<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, prim, cons, tab, partials);
+  else
+    hipLaunchKernelGGL(k_diag<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, prim, cons, tab, partials);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, partials, (int)nb, out);
+}
+
+}  // namespace grmhd

@@ -1,0 +1,162 @@
+"""Grid: device memory (torch tensors) + the C-ABI calls, argument marshalling only."""
+import ctypes as C
+import numpy as np
+import torch
+
+from . import _lib as L
+
+PRIM = ("rho", "u1", "u2", "u3", "p", "B1", "B2", "B3")
+CONS = ("D", "S1", "S2", "S3", "tau", "Bf1", "Bf2", "Bf3")
+
+
+class Grid:
+    def __init__(self, spec, tables=None, precision=L.FP64, guess=L.GUESS_WARM,
+                 device="cuda:0", stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Grid needs a HIP device")
+        self.lib = L.lib()
+        self.spec = spec
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.desc = L.make_desc(spec, precision, guess)
+        h = C.c_void_p()
+        L.check(self.lib.grmhd_init_grid(C.byref(self.desc), C.c_void_p(self.stream.cuda_stream),
+                                         C.byref(h)))
+        self.h = h
+        lay = L.Layout()
+        L.check(self.lib.grmhd_get_layout(self.h, C.byref(lay)))
+        self.layout = lay
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.prim = torch.zeros(int(lay.prim_doubles), **f64)
+        self.cons = torch.zeros(int(lay.cons_doubles), **f64)
+        self.scratch = torch.zeros(int(lay.scratch_bytes) // 8, **f64)
+        L.check(self.lib.grmhd_bind_fields(self.h, C.c_void_p(self.prim.data_ptr()),
+                                           C.c_void_p(self.cons.data_ptr()),
+                                           C.c_void_p(self.scratch.data_ptr()),
+                                           C.c_size_t(int(lay.scratch_bytes))))
+        if tables is None:
+            L.check(self.lib.grmhd_set_metric(self.h, L.METRIC_MINKOWSKI, None, 0))
+        else:
+            self.set_metric(tables)
+
+    # ------------------------------------------------------------ layout views
+    def field_view(self, flat, f):
+        """[k][j][i] ghosted view of field f of a group tensor (padding dropped)."""
+        lay = self.layout
+        d0, d1, d2 = (int(x) for x in lay.dims)
+        base = f * int(lay.field)
+        return flat.as_strided((d2, d1, d0), (int(lay.plane), int(lay.pitch), 1), base)
+
+    def new_single(self):
+        return torch.zeros(int(self.layout.edge_doubles), dtype=torch.float64, device=self.device)
+
+    def _interior(self, v):
+        g = self.spec.ng
+        return v[g:-g, g:-g, g:-g]
+
+    # ------------------------------------------------------------ API calls
+    def set_metric(self, tables):
+        t = np.ascontiguousarray(tables, dtype=np.float64)
+        L.check(self.lib.grmhd_set_metric(self.h, L.METRIC_TABLE_AXISYM,
+                                          t.ctypes.data_as(C.POINTER(C.c_double)), t.size))
+
+    def set_primitives(self, data):
+        """Interior rho, u, p (numpy [k][j][i]) -> prim; then prim2cons."""
+        for f, name in enumerate(PRIM[:5]):
+            v = self._interior(self.field_view(self.prim, f))
+            v.copy_(torch.from_numpy(np.ascontiguousarray(data[name], dtype=np.float64)))
+        self.prim2cons()
+
+    def set_face_fields(self, data):
+        """Ghosted face fields B1f..B3f (numpy, ghosted shape) -> cons."""
+        for a in range(3):
+            v = self.field_view(self.cons, 5 + a)
+            v.copy_(torch.from_numpy(np.ascontiguousarray(data["B%df" % (a + 1)], dtype=np.float64)))
+
+    def curl_potential(self, data):
+        arrs = []
+        for a in range(3):
+            t = self.new_single()
+            self.field_view(t, 0).copy_(torch.from_numpy(np.ascontiguousarray(data["A%d" % (a + 1)], dtype=np.float64)))
+            arrs.append(t)
+        L.check(self.lib.grmhd_curl_potential(self.h, *[C.c_void_p(t.data_ptr()) for t in arrs]))
+        self.synchronize()
+
+    def prim2cons(self):
+        L.check(self.lib.grmhd_prim2cons(self.h))
+
+    def rhs(self):
+        out = torch.zeros_like(self.cons)
+        L.check(self.lib.grmhd_rhs(self.h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def rk_step(self, dt=0.0, want_dt=False):
+        v = C.c_double(0.0)
+        L.check(self.lib.grmhd_rk_step(self.h, C.c_double(dt), C.byref(v) if want_dt else None))
+        return v.value if want_dt else None
+
+    def cons2prim(self, strict=False):
+        n = C.c_int64(0)
+        L.check(self.lib.grmhd_cons2prim(self.h, C.byref(n), 1 if strict else 0))
+        return n.value
+
+    def compute_dt(self):
+        v = C.c_double(0.0)
+        L.check(self.lib.grmhd_compute_dt(self.h, C.byref(v)))
+        return v.value
+
+    def diagnostics(self):
+        d = L.Diag()
+        L.check(self.lib.grmhd_diagnostics(self.h, C.byref(d)))
+        return d.as_dict()
+
+    def set_profiling(self, on=True):
+        L.check(self.lib.grmhd_set_profiling(self.h, 1 if on else 0))
+
+    def profile(self, reset=True):
+        """{kernel class: (total ms, launches)} since the last reset."""
+        p = L.Profile()
+        L.check(self.lib.grmhd_get_profile(self.h, C.byref(p), 1 if reset else 0))
+        out = {}
+        for c in range(L.PROF_NCLASS):
+            if p.launches[c]:
+                out[self.lib.grmhd_profile_class_name(c).decode()] = (p.ms[c], int(p.launches[c]))
+        return out
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    # ------------------------------------------------------------ readback
+    def read_group(self, flat, names, interior=False):
+        self.synchronize()
+        out = {}
+        for f, name in enumerate(names):
+            v = self.field_view(flat, f)
+            if interior:
+                v = self._interior(v)
+            out[name] = v.cpu().numpy().copy()
+        return out
+
+    def to_numpy(self, which="prim", interior=False):
+        self.synchronize()
+        flat = self.prim if which == "prim" else self.cons
+        names = PRIM if which == "prim" else CONS
+        out = {}
+        for f, name in enumerate(names):
+            v = self.field_view(flat, f)
+            if interior:
+                v = self._interior(v)
+            out[name] = v.cpu().numpy().copy()
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.grmhd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
