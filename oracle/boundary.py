@@ -62,8 +62,8 @@ def _fill_dir(q, name, grid, d, normal):
             out[g:g + n3] = rolled
             return sign * out
         if normal:
-            setv(-1, 0.0 * getv(-1))
-            setv(n - 1, 0.0 * getv(n - 1))
+            setv(-1, np.zeros_like(getv(-1)))
+            setv(n - 1, np.zeros_like(getv(n - 1)))
             for m in range(0, g - 1):
                 setv(-2 - m, shifted(m))
             for m in range(0, g):

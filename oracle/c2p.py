@@ -23,8 +23,11 @@ Stop when |f(y)| is below the round-off bound of its own evaluation,
 or when the step |dy| <= tol y (tol = 1e-14); at most maxit (50) steps.
 Outputs: W = (1 - v^2)^(-1/2), rho = D/W, p = p(y),
 v_i = (S_i + (SB/y) B_i)/(y + B^2), u^i = W gamma^ij v_j.
-Failure (flagged, the previous primitives are kept): D <= 0, U <= 0,
-non-finite input, no convergence, v^2 >= 1 or non-finite output.
+Failure (flagged): D <= 0, U <= 0, non-finite input, no convergence,
+v^2 >= 1 or non-finite output.  Without floors the zone keeps its previous
+primitives; with floors (accretion-torus runs) it is reset to atmosphere
+(floor density and pressure, at rest) and its conserved variables are
+recomputed.
 Guess: warm y0 = rho h W^2 of the previous primitives (cold: Gamma U);
 a guess outside (a, b) is replaced by (a + b)/2.
 """

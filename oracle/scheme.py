@@ -5,7 +5,8 @@ after ECHO.  One right-hand-side evaluation, in order:
   1. ghost fill of the 8 centred primitives;
   2. for each direction d: MP5 states of rho, p, u^1..3 and the two
      transverse centred B at d-faces f in [-3, n_d + 1] over the whole
-     transverse ghosted range; normal B = B_face / sqrt(gamma_face);
+     transverse ghosted range (a non-positive rho or p state is replaced by
+     the value of the cell on its side); normal B = B_face / sqrt(gamma_face);
      pointwise fluxes, conserved variables and speeds of both states; HLL
      flux (0 on faces where sqrt(gamma) = 0); the per-face data for the
      edge field: v^d and v^c (c = d+1 mod 3) of both states and a+-;
@@ -187,6 +188,13 @@ class Solver:
         rec = {}
         for k in ("rho", "p", "u1", "u2", "u3"):
             rec[k] = face_states(P[k], d, lo, hi, g, take)
+        # positivity: a non-positive reconstructed rho or p falls back to the
+        # value of the cell on that side of the face (first order)
+        for k in ("rho", "p"):
+            l, r = rec[k]
+            cj = take(P[k], d, lo, hi, g)
+            cj1 = take(P[k], d, lo + 1, hi + 1, g)
+            rec[k] = (np.where(l <= 0.0, cj, l), np.where(r <= 0.0, cj1, r))
         for t in range(3):
             if t != d:
                 rec["B%d" % (t + 1)] = face_states(P["B%d" % (t + 1)], d, lo, hi, g, take)
@@ -332,6 +340,11 @@ class Solver:
         floored = np.zeros(ok.shape, dtype=bool)
         if gr.rho_fl_a > 0.0 or gr.p_fl_a > 0.0 or gr.w_max > 0.0:
             r = self.r_int if self.r_int is not None else 1.0
+            # a failed zone becomes atmosphere: floor density and pressure, at rest
+            rho = np.where(ok, rho, gr.rho_fl_a * r ** gr.rho_fl_n)
+            p = np.where(ok, p, gr.p_fl_a * r ** gr.p_fl_n)
+            u = [np.where(ok, x, 0.0) for x in u]
+            floored |= ~ok
             if gr.rho_fl_a > 0.0:
                 rfl = gr.rho_fl_a * r ** gr.rho_fl_n
                 low = rho < rfl

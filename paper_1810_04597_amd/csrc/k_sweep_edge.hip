@@ -60,8 +60,13 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
       for (int s = 0; s < 6; ++s) q[s] = T(p[(s - 2) * st]);
       mp5_lr(q, l, rr);
     };
+    // a non-positive rho or p state falls back to the cell on its side
     rec(P_RHO, sl.rho, sr.rho);
+    if (sl.rho <= T(0)) sl.rho = q[2];
+    if (sr.rho <= T(0)) sr.rho = q[3];
     rec(P_P, sl.p, sr.p);
+    if (sl.p <= T(0)) sl.p = q[2];
+    if (sr.p <= T(0)) sr.p = q[3];
     rec(P_U1, sl.u[0], sr.u[0]);
     rec(P_U2, sl.u[1], sr.u[1]);
     rec(P_U3, sl.u[2], sr.u[2]);

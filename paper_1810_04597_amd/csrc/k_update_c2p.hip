@@ -303,6 +303,13 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
     bool floored = false;
     if (cp.rho_fl_a > 0.0 || cp.p_fl_a > 0.0 || cp.w_max > 0.0) {
       const double rr = cp.coord == 1 ? exp(G.x0[0] + (i + 0.5) * G.dx[0]) : 1.0;
+      if (!r.ok) {
+        // failed zone -> atmosphere at rest
+        rho = cp.rho_fl_a * pow(rr, cp.rho_fl_n);
+        p = cp.p_fl_a * pow(rr, cp.p_fl_n);
+        u[0] = u[1] = u[2] = 0.0;
+        floored = true;
+      }
       if (cp.rho_fl_a > 0.0) {
         const double rfl = cp.rho_fl_a * pow(rr, cp.rho_fl_n);
         if (rho < rfl) { rho = rfl; floored = true; st[3] = 1; }
