@@ -30,6 +30,21 @@ def algorithmic_units():
     return {}
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the counter passes, or None when the kernel
+    sources changed since they were taken."""
+    path = os.path.join(ROOT, "paper_1810_04597_amd", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    from paper_1810_04597_amd.traffic import source_hash
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != source_hash():
+        return None
+    k = t["kernels"].get(kernel)
+    return None if k is None else k["bytes"]
+
+
 def launch_units(kernel, n):
     """Number of units (faces, edges or zones) one launch of `kernel` processes."""
     g = 5
@@ -132,16 +147,17 @@ def main():
         avg_s = prof[dom][0] / prof[dom][1] / 1e3
         u = units.get(dom, {})
         nunits = launch_units(dom, n)
+        traffic = measured_traffic(dom) if n == 256 else None
         if "flops" in u:
             peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
             achieved = u["flops"] * nunits / avg_s / 1e12
             roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                        "frac": achieved / peak, "traffic": u.get("traffic"),
+                        "frac": achieved / peak, "traffic": traffic,
                         "kernel": dom, "avg_ms": avg_s * 1e3}
         elif "bytes" in u:
             achieved = u["bytes"] * nunits / avg_s / 1e9
             roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": u.get("traffic"),
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                         "kernel": dom, "avg_ms": avg_s * 1e3}
         else:
             roofline = {"bound": "alu", "achieved": None, "peak": FP64_VECTOR_PEAK_TFLOPS,

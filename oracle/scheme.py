@@ -5,8 +5,8 @@ after ECHO.  One right-hand-side evaluation, in order:
   1. ghost fill of the 8 centred primitives;
   2. for each direction d: MP5 states of rho, p, u^1..3 and the two
      transverse centred B at d-faces f in [-3, n_d + 1] over the whole
-     transverse ghosted range (a non-positive rho or p state is replaced by
-     the value of the cell on its side); normal B = B_face / sqrt(gamma_face);
+     transverse ghosted range (reconstructed rho and p are kept at or above
+     0.1 times the cell value on their side); normal B = B_face / sqrt(gamma_face);
      pointwise fluxes, conserved variables and speeds of both states; HLL
      flux (0 on faces where sqrt(gamma) = 0); the per-face data for the
      edge field: v^d and v^c (c = d+1 mod 3) of both states and a+-;
@@ -50,6 +50,7 @@ DERIV = (["d1_alpha", "d2_alpha", "d1_beta1", "d1_beta2", "d1_beta3",
           "d2_beta1", "d2_beta2", "d2_beta3"]
          + ["d1_" + c for c in ("g11", "g12", "g13", "g22", "g23", "g33")]
          + ["d2_" + c for c in ("g11", "g12", "g13", "g22", "g23", "g33")])
+POS_FRAC = 0.1                   # positivity bound of reconstructed rho, p
 FACE_LOC = ("F1", "F2", "C")     # metric location of d-faces
 EDGE_LOC = ("F2", "F1", "E3")    # metric location of edge family e
 
@@ -188,13 +189,13 @@ class Solver:
         rec = {}
         for k in ("rho", "p", "u1", "u2", "u3"):
             rec[k] = face_states(P[k], d, lo, hi, g, take)
-        # positivity: a non-positive reconstructed rho or p falls back to the
-        # value of the cell on that side of the face (first order)
+        # positivity: a reconstructed rho or p is kept at or above a tenth of
+        # the value of the cell on its side of the face (continuous bound)
         for k in ("rho", "p"):
             l, r = rec[k]
             cj = take(P[k], d, lo, hi, g)
             cj1 = take(P[k], d, lo + 1, hi + 1, g)
-            rec[k] = (np.where(l <= 0.0, cj, l), np.where(r <= 0.0, cj1, r))
+            rec[k] = (np.maximum(l, POS_FRAC * cj), np.maximum(r, POS_FRAC * cj1))
         for t in range(3):
             if t != d:
                 rec["B%d" % (t + 1)] = face_states(P["B%d" % (t + 1)], d, lo, hi, g, take)

@@ -16,7 +16,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Device code that is also instantiated on the host by the operation-count
+// harness (with a counting number type), so it is __host__ __device__.
+#define GR_HD __host__ __device__ __forceinline__
+
 namespace grmhd {
+
+using std::sqrt;
+using std::fmin;
+using std::fmax;
+using std::fabs;
 
 constexpr int NG = 5;
 constexpr int NPRIM = 8;   // rho, u1, u2, u3, p, B1, B2, B3
@@ -55,15 +64,37 @@ struct Geom {
   }
 };
 
+// ------------------------------------------------------------------ XCD-aware block order
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8),
+// each with its own L2.  Remapping b so that every XCD works on one contiguous
+// range of the flattened index space keeps the stencil neighbours of a block
+// (the rows and planes around it) in the same L2.  A bijection on [0, nb).
+constexpr unsigned NXCD = 8;
+#if defined(__HIPCC__)
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+#ifdef GRMHD_NO_XCD_REMAP
+  (void)nb;
+  return b;
+#else
+  const unsigned x = b % NXCD, q = b / NXCD;
+  const unsigned per = nb / NXCD, rem = nb % NXCD;
+  return x * per + (x < rem ? x : rem) + q;
+#endif
+}
+__device__ __forceinline__ long flat_thread() {
+  return (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+}
+#endif
+
 // ------------------------------------------------------------------ MP5
 template <typename T>
-__device__ __forceinline__ T minmod(T a, T b) {
+GR_HD T minmod(T a, T b) {
   // (sgn a + sgn b)/2 * min(|a|, |b|)
   return (a > T(0) && b > T(0)) ? fmin(a, b) : ((a < T(0) && b < T(0)) ? fmax(a, b) : T(0));
 }
 
 template <typename T>
-__device__ __forceinline__ T minmod4(T w, T x, T y, T z) {
+GR_HD T minmod4(T w, T x, T y, T z) {
   if (w > T(0) && x > T(0) && y > T(0) && z > T(0)) return fmin(fmin(w, x), fmin(y, z));
   if (w < T(0) && x < T(0) && y < T(0) && z < T(0)) return fmax(fmax(w, x), fmax(y, z));
   return T(0);
@@ -71,7 +102,7 @@ __device__ __forceinline__ T minmod4(T w, T x, T y, T z) {
 
 // Limited left state at the face between q0 and qp1 from q_{j-2..j+2}.
 template <typename T>
-__device__ __forceinline__ T mp5(T qm2, T qm1, T q0, T qp1, T qp2) {
+GR_HD T mp5(T qm2, T qm1, T q0, T qp1, T qp2) {
   const T ql = (T(3) * qm2 - T(20) * qm1 + T(90) * q0 + T(60) * qp1 - T(5) * qp2) * T(1.0 / 128.0);
   const T qmp = q0 + minmod(qp1 - q0, T(4) * (q0 - qm1));
   if ((ql - q0) * (ql - qmp) <= T(0)) return ql;
@@ -90,7 +121,7 @@ __device__ __forceinline__ T mp5(T qm2, T qm1, T q0, T qp1, T qp2) {
 
 // Left and right states at face f+1/2 from the six cells f-2 .. f+3 (c[0..5]).
 template <typename T>
-__device__ __forceinline__ void mp5_lr(const T c[6], T& l, T& r) {
+GR_HD void mp5_lr(const T c[6], T& l, T& r) {
   l = mp5(c[0], c[1], c[2], c[3], c[4]);
   r = mp5(c[5], c[4], c[3], c[2], c[1]);
 }
@@ -98,11 +129,11 @@ __device__ __forceinline__ void mp5_lr(const T c[6], T& l, T& r) {
 // ------------------------------------------------------------------ FD operators
 // Sixth-order staggered derivative at m from f_{m-5/2..m+5/2} = f[0..5]
 // (stored indices m-3 .. m+2).
-__device__ __forceinline__ double fd_deriv(const double f[6], double inv_dx) {
+GR_HD double fd_deriv(const double f[6], double inv_dx) {
   return (75.0 / 64.0 * (f[3] - f[2]) - 25.0 / 384.0 * (f[4] - f[1]) +
           3.0 / 640.0 * (f[5] - f[0])) * inv_dx;
 }
-__device__ __forceinline__ double fd_interp(const double f[6]) {
+GR_HD double fd_interp(const double f[6]) {
   return (150.0 * (f[3] + f[2]) - 25.0 * (f[4] + f[1]) + 3.0 * (f[5] + f[0])) * (1.0 / 256.0);
 }
 
@@ -110,25 +141,25 @@ __device__ __forceinline__ double fd_interp(const double f[6]) {
 template <typename T>
 struct FlatMet {
   static constexpr bool flat = true;
-  __device__ __forceinline__ void lower(const T a[3], T o[3]) const { o[0] = a[0]; o[1] = a[1]; o[2] = a[2]; }
-  __device__ __forceinline__ void raise(const T a[3], T o[3]) const { o[0] = a[0]; o[1] = a[1]; o[2] = a[2]; }
-  __device__ __forceinline__ T guu(int) const { return T(1); }
-  __device__ __forceinline__ T tvel(T v, int) const { return v; }             // alpha v - beta
-  __device__ __forceinline__ T dens(T x) const { return x; }                 // sqrt(gamma) x
-  __device__ __forceinline__ T undens(T x) const { return x; }
-  __device__ __forceinline__ T fcomb(T x, T y, int) const { return x; }      // sqrt(g)(alpha x - beta^d y)
-  __device__ __forceinline__ T alpha() const { return T(1); }
-  __device__ __forceinline__ T beta(int) const { return T(0); }
-  __device__ __forceinline__ T sqrtg() const { return T(1); }
-  __device__ __forceinline__ T e_up(T x) const { return x; }                 // x / sqrt(gamma)
-  __device__ __forceinline__ T e_lo(T x) const { return x; }                 // x * sqrt(gamma)
+  GR_HD void lower(const T a[3], T o[3]) const { o[0] = a[0]; o[1] = a[1]; o[2] = a[2]; }
+  GR_HD void raise(const T a[3], T o[3]) const { o[0] = a[0]; o[1] = a[1]; o[2] = a[2]; }
+  GR_HD T guu(int) const { return T(1); }
+  GR_HD T tvel(T v, int) const { return v; }             // alpha v - beta
+  GR_HD T dens(T x) const { return x; }                 // sqrt(gamma) x
+  GR_HD T undens(T x) const { return x; }
+  GR_HD T fcomb(T x, T y, int) const { return x; }      // sqrt(g)(alpha x - beta^d y)
+  GR_HD T alpha() const { return T(1); }
+  GR_HD T beta(int) const { return T(0); }
+  GR_HD T sqrtg() const { return T(1); }
+  GR_HD T e_up(T x) const { return x; }                 // x / sqrt(gamma)
+  GR_HD T e_lo(T x) const { return x; }                 // x * sqrt(gamma)
 };
 
 template <typename T>
 struct TabMet {
   static constexpr bool flat = false;
   T al, b[3], g11, g12, g13, g22, g23, g33, u11, u12, u13, u22, u23, u33, sg;
-  __device__ __forceinline__ void load(const double* __restrict__ tab, long tplane, int loc, long t) {
+  GR_HD void load(const double* __restrict__ tab, long tplane, int loc, long t) {
     const double* p = tab + (long)loc * NGEOM * tplane + t;
     al = T(p[M_AL * tplane]);
     b[0] = T(p[M_B1 * tplane]); b[1] = T(p[M_B2 * tplane]); b[2] = T(p[M_B3 * tplane]);
@@ -138,26 +169,26 @@ struct TabMet {
     u22 = T(p[M_U22 * tplane]); u23 = T(p[M_U23 * tplane]); u33 = T(p[M_U33 * tplane]);
     sg = T(p[M_SG * tplane]);
   }
-  __device__ __forceinline__ void lower(const T a[3], T o[3]) const {
+  GR_HD void lower(const T a[3], T o[3]) const {
     o[0] = g11 * a[0] + g12 * a[1] + g13 * a[2];
     o[1] = g12 * a[0] + g22 * a[1] + g23 * a[2];
     o[2] = g13 * a[0] + g23 * a[1] + g33 * a[2];
   }
-  __device__ __forceinline__ void raise(const T a[3], T o[3]) const {
+  GR_HD void raise(const T a[3], T o[3]) const {
     o[0] = u11 * a[0] + u12 * a[1] + u13 * a[2];
     o[1] = u12 * a[0] + u22 * a[1] + u23 * a[2];
     o[2] = u13 * a[0] + u23 * a[1] + u33 * a[2];
   }
-  __device__ __forceinline__ T guu(int d) const { return d == 0 ? u11 : (d == 1 ? u22 : u33); }
-  __device__ __forceinline__ T tvel(T v, int d) const { return al * v - b[d]; }
-  __device__ __forceinline__ T dens(T x) const { return sg * x; }
-  __device__ __forceinline__ T undens(T x) const { return x / sg; }
-  __device__ __forceinline__ T fcomb(T x, T y, int d) const { return sg * (al * x - b[d] * y); }
-  __device__ __forceinline__ T alpha() const { return al; }
-  __device__ __forceinline__ T beta(int d) const { return b[d]; }
-  __device__ __forceinline__ T sqrtg() const { return sg; }
-  __device__ __forceinline__ T e_up(T x) const { return x / sg; }
-  __device__ __forceinline__ T e_lo(T x) const { return sg * x; }
+  GR_HD T guu(int d) const { return d == 0 ? u11 : (d == 1 ? u22 : u33); }
+  GR_HD T tvel(T v, int d) const { return al * v - b[d]; }
+  GR_HD T dens(T x) const { return sg * x; }
+  GR_HD T undens(T x) const { return x / sg; }
+  GR_HD T fcomb(T x, T y, int d) const { return sg * (al * x - b[d] * y); }
+  GR_HD T alpha() const { return al; }
+  GR_HD T beta(int d) const { return b[d]; }
+  GR_HD T sqrtg() const { return sg; }
+  GR_HD T e_up(T x) const { return x / sg; }
+  GR_HD T e_lo(T x) const { return sg * x; }
 };
 
 // ------------------------------------------------------------------ pointwise physics
@@ -169,7 +200,7 @@ struct PState {
 
 // Derived quantities of a primitive state (3+1 GRMHD, ideal gas).
 template <typename T, class M>
-__device__ __forceinline__ void make_state(PState<T>& s, const M& m, T gam) {
+GR_HD void make_state(PState<T>& s, const M& m, T gam) {
   T ul[3];
   m.lower(s.u, ul);
   const T uu = ul[0] * s.u[0] + ul[1] * s.u[1] + ul[2] * s.u[2];
@@ -194,7 +225,7 @@ __device__ __forceinline__ void make_state(PState<T>& s, const M& m, T gam) {
 
 // Densitised conserved hydro variables.
 template <typename T, class M>
-__device__ __forceinline__ void cons_of(const PState<T>& s, const M& m, T c[5]) {
+GR_HD void cons_of(const PState<T>& s, const M& m, T c[5]) {
   c[0] = m.dens(s.D);
   c[1] = m.dens(s.S[0]); c[2] = m.dens(s.S[1]); c[3] = m.dens(s.S[2]);
   c[4] = m.dens(s.tau);
@@ -202,7 +233,7 @@ __device__ __forceinline__ void cons_of(const PState<T>& s, const M& m, T c[5]) 
 
 // Densitised fluxes of (D, S_1..3, tau) in direction d.
 template <typename T, class M>
-__device__ __forceinline__ void flux_of(const PState<T>& s, const M& m, int d, T f[5]) {
+GR_HD void flux_of(const PState<T>& s, const M& m, int d, T f[5]) {
   // electric field E_i = -sqrt(g) [ijk] v^j B^k, E^i = -[ijk] v_j B_k / sqrt(g)
   T el[3], eu_d;
   el[0] = m.e_lo(-(s.v[1] * s.B[2] - s.v[2] * s.B[1]));
@@ -223,7 +254,7 @@ __device__ __forceinline__ void flux_of(const PState<T>& s, const M& m, int d, T
 
 // Fast magnetosonic speed estimate lambda^+-_d.
 template <typename T, class M>
-__device__ __forceinline__ void speeds_of(const PState<T>& s, const M& m, int d, T gam, T& lp, T& lm) {
+GR_HD void speeds_of(const PState<T>& s, const M& m, int d, T gam, T& lp, T& lm) {
   const T rhoh = s.rho * s.h;
   const T cs2 = gam * s.p / rhoh;
   const T bb = s.B2 / (s.W * s.W) + s.vB * s.vB;
@@ -245,13 +276,172 @@ __device__ __forceinline__ void speeds_of(const PState<T>& s, const M& m, int d,
 }
 
 // Threshold below which a+ + a- counts as zero.
-template <typename T> __device__ __forceinline__ T tiny_speed();
-template <> __device__ __forceinline__ double tiny_speed<double>() { return 1e-300; }
-template <> __device__ __forceinline__ float tiny_speed<float>() { return 1e-37f; }
+template <typename T> struct TinySpeed { static GR_HD double v() { return 1e-300; } };
+template <> struct TinySpeed<float> { static GR_HD float v() { return 1e-37f; } };
+template <typename T> GR_HD T tiny_speed() { return T(TinySpeed<T>::v()); }
 
 template <typename T>
-__device__ __forceinline__ T hll(T fl, T fr, T ul, T ur, T ap, T am, T inv_s, bool tiny) {
+GR_HD T hll(T fl, T fr, T ul, T ur, T ap, T am, T inv_s, bool tiny) {
   return tiny ? T(0.5) * (fl + fr) : (ap * fl + am * fr - ap * am * (ur - ul)) * inv_s;
+}
+
+// ------------------------------------------------------------------ per-face body
+constexpr double POS_FRAC = 0.1;
+// q[v][s]: six cells f-2 .. f+3 of the reconstructed variables in the order
+// rho, p, u^1, u^2, u^3, B^{d+1}, B^{d+2}; bn: normal B at the face.
+template <int DIR, typename T, class M>
+GR_HD void face_body(const T q[7][6], T bn, bool axis, const M& m, T gam, T fh[5], T ctd[6]) {
+  constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+  PState<T> sl, sr;
+  // rho and p states are kept at or above POS_FRAC times the cell value on
+  // their side of the face (a continuous positivity bound)
+  mp5_lr(q[0], sl.rho, sr.rho);
+  sl.rho = fmax(sl.rho, T(POS_FRAC) * q[0][2]);
+  sr.rho = fmax(sr.rho, T(POS_FRAC) * q[0][3]);
+  mp5_lr(q[1], sl.p, sr.p);
+  sl.p = fmax(sl.p, T(POS_FRAC) * q[1][2]);
+  sr.p = fmax(sr.p, T(POS_FRAC) * q[1][3]);
+  mp5_lr(q[2], sl.u[0], sr.u[0]);
+  mp5_lr(q[3], sl.u[1], sr.u[1]);
+  mp5_lr(q[4], sl.u[2], sr.u[2]);
+  mp5_lr(q[5], sl.B[T1], sr.B[T1]);
+  mp5_lr(q[6], sl.B[T2], sr.B[T2]);
+  sl.B[DIR] = bn;
+  sr.B[DIR] = bn;
+  make_state(sl, m, gam);
+  make_state(sr, m, gam);
+  T fl[5], fr[5], ul[5], ur[5];
+  flux_of(sl, m, DIR, fl);
+  flux_of(sr, m, DIR, fr);
+  cons_of(sl, m, ul);
+  cons_of(sr, m, ur);
+  T lpl, lml, lpr, lmr;
+  speeds_of(sl, m, DIR, gam, lpl, lml);
+  speeds_of(sr, m, DIR, gam, lpr, lmr);
+  const T ap = fmax(T(0), fmax(lpl, lpr));
+  const T am = fmax(T(0), fmax(-lml, -lmr));
+  const T s = ap + am;
+  const bool tiny = s < tiny_speed<T>();
+  const T inv_s = tiny ? T(0) : T(1) / s;
+  for (int q5 = 0; q5 < 5; ++q5) {
+    T f = hll(fl[q5], fr[q5], ul[q5], ur[q5], ap, am, inv_s, tiny);
+    fh[q5] = axis ? T(0) : f;
+  }
+  ctd[0] = sl.v[DIR];
+  ctd[1] = sr.v[DIR];
+  ctd[2] = sl.v[T1];
+  ctd[3] = sr.v[T1];
+  ctd[4] = ap;
+  ctd[5] = am;
+}
+
+// ------------------------------------------------------------------ per-edge body
+// Edge field of family E (d = E+1, c = E+2 mod 3).  qd[v][s]: six d-faces
+// along c of v^d_L, v^d_R, v^c_L, v^c_R, B^d; qc[s]: six c-faces along d of
+// B^c; a*: speeds of the two adjacent faces of each family.
+template <int E, typename T, class M>
+GR_HD T edge_body(const T qd[5][6], const T qc[6], T apd0, T apd1, T amd0, T amd1,
+                  T apc0, T apc1, T amc0, T amc1, const M& m) {
+  constexpr int D = (E + 1) % 3, C = (E + 2) % 3;
+  T vd[2][2], vc[2][2], bd[2], bc[2];   // [a][b]
+  mp5_lr(qd[0], vd[0][0], vd[0][1]);
+  mp5_lr(qd[1], vd[1][0], vd[1][1]);
+  mp5_lr(qd[2], vc[0][0], vc[0][1]);
+  mp5_lr(qd[3], vc[1][0], vc[1][1]);
+  mp5_lr(qd[4], bd[0], bd[1]);
+  mp5_lr(qc, bc[0], bc[1]);
+  const T apd = fmax(apd0, apd1), amd = fmax(amd0, amd1);
+  const T apc = fmax(apc0, apc1), amc = fmax(amc0, amc1);
+  const T sdd = apd + amd, scc = apc + amc;
+  const bool tiny_d = sdd < tiny_speed<T>(), tiny_c = scc < tiny_speed<T>();
+  const T isd = tiny_d ? T(0) : T(1) / sdd;
+  const T isc = tiny_c ? T(0) : T(1) / scc;
+  const T wd[2] = {tiny_d ? T(0.5) : apd * isd, tiny_d ? T(0.5) : amd * isd};
+  const T wc[2] = {tiny_c ? T(0.5) : apc * isc, tiny_c ? T(0.5) : amc * isc};
+  const T kd = tiny_d ? T(0) : apd * amd * isd;
+  const T kc = tiny_c ? T(0) : apc * amc * isc;
+  T ee = T(0);
+  for (int a = 0; a < 2; ++a) {
+    for (int bb = 0; bb < 2; ++bb) {
+      const T vtd = m.tvel(vd[a][bb], D);
+      const T vtc = m.tvel(vc[a][bb], C);
+      const T eab = vtc * bd[bb] - vtd * bc[a];
+      ee = ee + wd[a] * wc[bb] * eab;
+    }
+  }
+  ee = ee + kd * (bc[1] - bc[0]) - kc * (bd[1] - bd[0]);
+  return ee;
+}
+
+// ------------------------------------------------------------------ inversion
+template <typename T>
+struct NewtonOut {
+  T rho, p, u[3];
+  int iters;
+  bool ok;
+};
+
+// Safeguarded Newton inversion in y = rho h W^2 (undensitised D, S_i, tau, B^i).
+template <typename T, class MET>
+GR_HD NewtonOut<T> newton(T dd, const T S[3], T tau, const T B[3], const MET& m, T gam,
+                          T y0, double tol, int maxit) {
+  using std::isfinite;
+  NewtonOut<T> o;
+  const T utot = tau + dd;
+  T su[3], bl[3];
+  m.raise(S, su);
+  m.lower(B, bl);
+  const T s2 = S[0] * su[0] + S[1] * su[1] + S[2] * su[2];
+  const T b2 = bl[0] * B[0] + bl[1] * B[1] + bl[2] * B[2];
+  const T sb = S[0] * B[0] + S[1] * B[1] + S[2] * B[2];
+  const T sb2 = sb * sb;
+  const T gf = (gam - 1.0) / gam;
+  const bool valid = isfinite(dd) && isfinite(utot) && isfinite(s2) && isfinite(b2) &&
+                     isfinite(sb) && dd > 0.0 && utot > 0.0;
+  T a = 0.0, bb = gam * utot;
+  T y = y0;
+  if (!(y > a && y < bb)) y = 0.5 * (a + bb);
+  bool conv = false;
+  int it = 0;
+  const T EPS4 = T(4.0 * 2.220446049250313e-16);
+  if (valid) {
+    for (; it < maxit;) {
+      ++it;
+      const T yy = y * y;
+      const T v2 = (s2 + sb2 * (2.0 * y + b2) / yy) / ((y + b2) * (y + b2));
+      const bool bad = v2 >= 1.0;
+      const T sq = sqrt(1.0 - v2);
+      const T p = gf * (y * (1.0 - v2) - dd * sq);
+      const T f = y - p + 0.5 * b2 * (1.0 + v2) - 0.5 * sb2 / yy - utot;
+      const T yb = y + b2;
+      const T y3 = yy * y;
+      const T dv2 = (-2.0 * sb2 * yb / y3 / (yb * yb) -
+                          2.0 * (s2 + sb2 * (2.0 * y + b2) / yy) / (yb * yb * yb));
+      const T dp = gf * ((1.0 - v2) - y * dv2 + dd * dv2 / (2.0 * sq));
+      const T fp = 1.0 - dp + 0.5 * b2 * dv2 + sb2 / y3;
+      const T fabs_ = y + fabs(p) + 0.5 * b2 * (1.0 + v2) + 0.5 * sb2 / yy + utot;
+      if (!bad && fabs(f) <= EPS4 * fabs_) { conv = true; break; }
+      const bool below = bad || (f < 0.0);
+      if (below) a = y; else bb = y;
+      T yn = y - f / fp;
+      if (bad || !(yn >= a && yn <= bb)) yn = 0.5 * (a + bb);
+      const T dy = yn - y;
+      y = yn;
+      if (fabs(dy) <= tol * y) { conv = true; break; }
+    }
+  }
+  const T v2 = (s2 + sb2 * (2.0 * y + b2) / (y * y)) / ((y + b2) * (y + b2));
+  const T w = 1.0 / sqrt(1.0 - v2);
+  o.p = gf * (y * (1.0 - v2) - dd * sqrt(1.0 - v2));
+  o.rho = dd / w;
+  T vl[3], vu[3];
+  for (int q = 0; q < 3; ++q) vl[q] = (S[q] + (sb / y) * bl[q]) / (y + b2);
+  m.raise(vl, vu);
+  for (int q = 0; q < 3; ++q) o.u[q] = w * vu[q];
+  o.ok = conv && valid && (v2 < 1.0) && isfinite(o.rho) && isfinite(o.p) && isfinite(o.u[0]) &&
+         isfinite(o.u[1]) && isfinite(o.u[2]);
+  o.iters = it;
+  return o;
 }
 
 }  // namespace grmhd

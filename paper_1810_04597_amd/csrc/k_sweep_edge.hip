@@ -4,7 +4,8 @@
 // whole ghosted transverse range, flattened with x^1 fastest so a wavefront
 // reads 64 consecutive x^1 cells (coalesced).  Per face: MP5 left/right
 // states of rho, p, u^1..3 and the two transverse centred B (paper,
-// Introduction: high-order reconstruction), normal B from the face field,
+// Introduction: high-order reconstruction; rho and p bounded below by 0.1 of
+// the cell value on their side), normal B from the face field,
 // pointwise state, fluxes, conserved variables and fast speeds of both
 // states, HLL flux (0 where sqrt(gamma) = 0, the polar axis).  Writes the
 // five hydro fluxes and the six per-face quantities the edge field needs
@@ -29,14 +30,17 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
   int ext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) ext[a] = (a == DIR) ? G.n[a] + 5 : G.dims[a];
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = flat_thread();
   const long total = (long)ext[0] * ext[1] * ext[2];
   if (t >= total) return;
+  // traversal order: x^1 fastest; for the x^3 sweep x^3 comes next, so the
+  // six planes of a stencil are read by neighbouring workgroups (L2 reuse)
+  constexpr int MID = DIR == 2 ? 2 : 1, SLOW = DIR == 2 ? 1 : 2;
   int ii[3];
   ii[0] = (int)(t % ext[0]);
   const long r = t / ext[0];
-  ii[1] = (int)(r % ext[1]);
-  ii[2] = (int)(r / ext[1]);
+  ii[MID] = (int)(r % ext[MID]);
+  ii[SLOW] = (int)(r / ext[MID]);
 #pragma unroll
   for (int a = 0; a < 3; ++a) ii[a] += (a == DIR) ? -3 : -NG;
   const long c = G.idx(ii[0], ii[1], ii[2]);
@@ -51,27 +55,15 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
     m.load(tab, G.tab_plane, loc, G.tidx(ii[0], ii[1]));
   }
 
-  PState<T> sl, sr;
+  T q[7][6];
   {
-    T q[6];
-    auto rec = [&](int f, T& l, T& rr) {
-      const double* p = prim + (long)f * G.field + c;
+    const int fields[7] = {P_RHO, P_P, P_U1, P_U2, P_U3, P_B1 + T1, P_B1 + T2};
 #pragma unroll
-      for (int s = 0; s < 6; ++s) q[s] = T(p[(s - 2) * st]);
-      mp5_lr(q, l, rr);
-    };
-    // a non-positive rho or p state falls back to the cell on its side
-    rec(P_RHO, sl.rho, sr.rho);
-    if (sl.rho <= T(0)) sl.rho = q[2];
-    if (sr.rho <= T(0)) sr.rho = q[3];
-    rec(P_P, sl.p, sr.p);
-    if (sl.p <= T(0)) sl.p = q[2];
-    if (sr.p <= T(0)) sr.p = q[3];
-    rec(P_U1, sl.u[0], sr.u[0]);
-    rec(P_U2, sl.u[1], sr.u[1]);
-    rec(P_U3, sl.u[2], sr.u[2]);
-    rec(P_B1 + T1, sl.B[T1], sr.B[T1]);
-    rec(P_B1 + T2, sl.B[T2], sr.B[T2]);
+    for (int v = 0; v < 7; ++v) {
+      const double* p = prim + (long)fields[v] * G.field + c;
+#pragma unroll
+      for (int s = 0; s < 6; ++s) q[v][s] = T(p[(s - 2) * st]);
+    }
   }
   const double bface = cons[(long)(C_BF1 + DIR) * G.field + c];
   T bn;
@@ -82,35 +74,12 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
     axis = (m.sg == T(0));
     bn = axis ? T(0) : T(bface) / m.sg;
   }
-  sl.B[DIR] = bn;
-  sr.B[DIR] = bn;
-  make_state(sl, m, gam);
-  make_state(sr, m, gam);
-  T fl[5], fr[5], ul[5], ur[5];
-  flux_of(sl, m, DIR, fl);
-  flux_of(sr, m, DIR, fr);
-  cons_of(sl, m, ul);
-  cons_of(sr, m, ur);
-  T lpl, lml, lpr, lmr;
-  speeds_of(sl, m, DIR, gam, lpl, lml);
-  speeds_of(sr, m, DIR, gam, lpr, lmr);
-  const T ap = fmax(T(0), fmax(lpl, lpr));
-  const T am = fmax(T(0), fmax(-lml, -lmr));
-  const T s = ap + am;
-  const bool tiny = s < tiny_speed<T>();
-  const T inv_s = tiny ? T(0) : T(1) / s;
+  T fh[5], cd[6];
+  face_body<DIR>(q, bn, axis, m, gam, fh, cd);
 #pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    T fh = hll(fl[q], fr[q], ul[q], ur[q], ap, am, inv_s, tiny);
-    if (axis) fh = T(0);
-    flux[(long)q * G.field + c] = double(fh);
-  }
-  ctd[0 * G.field + c] = double(sl.v[DIR]);
-  ctd[1 * G.field + c] = double(sr.v[DIR]);
-  ctd[2 * G.field + c] = double(sl.v[T1]);
-  ctd[3 * G.field + c] = double(sr.v[T1]);
-  ctd[4 * G.field + c] = double(ap);
-  ctd[5 * G.field + c] = double(am);
+  for (int q5 = 0; q5 < 5; ++q5) flux[(long)q5 * G.field + c] = double(fh[q5]);
+#pragma unroll
+  for (int q6 = 0; q6 < 6; ++q6) ctd[(long)q6 * G.field + c] = double(cd[q6]);
 }
 
 // Edge field of family E.  ctd_d / ctd_c: per-face data of the d and c sweeps.
@@ -124,69 +93,43 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
   int ext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) ext[a] = (a == E) ? G.n[a] : G.n[a] + 5;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = flat_thread();
   const long total = (long)ext[0] * ext[1] * ext[2];
   if (t >= total) return;
+  // families 1 and 2 reconstruct along x^3: traverse x^3 before x^2
+  constexpr int MID = E == 2 ? 1 : 2, SLOW = E == 2 ? 2 : 1;
   int ii[3];
   ii[0] = (int)(t % ext[0]);
   const long r = t / ext[0];
-  ii[1] = (int)(r % ext[1]);
-  ii[2] = (int)(r / ext[1]);
+  ii[MID] = (int)(r % ext[MID]);
+  ii[SLOW] = (int)(r / ext[MID]);
 #pragma unroll
   for (int a = 0; a < 3; ++a) ii[a] += (a == E) ? 0 : -3;
   const long b = G.idx(ii[0], ii[1], ii[2]);
   const long sd = G.stride(D), sc = G.stride(C);
 
-  T q[6];
-  // d-face quantities reconstructed along c (side b of the edge)
-  auto along_c = [&](const double* __restrict__ src, T& l, T& rr) {
-#pragma unroll
-    for (int s = 0; s < 6; ++s) q[s] = T(src[b + (s - 2) * sc]);
-    mp5_lr(q, l, rr);
-  };
-  T vd[2][2], vc[2][2], bd[2], bc[2];   // [a][b]
-  along_c(ctd_d + 0 * G.field, vd[0][0], vd[0][1]);
-  along_c(ctd_d + 1 * G.field, vd[1][0], vd[1][1]);
-  along_c(ctd_d + 2 * G.field, vc[0][0], vc[0][1]);
-  along_c(ctd_d + 3 * G.field, vc[1][0], vc[1][1]);
-  along_c(cons + (long)(C_BF1 + D) * G.field, bd[0], bd[1]);
+  T qd[5][6], qc[6];
   {
-    const double* src = cons + (long)(C_BF1 + C) * G.field;
+    const double* src[5] = {ctd_d, ctd_d + G.field, ctd_d + 2 * G.field, ctd_d + 3 * G.field,
+                            cons + (long)(C_BF1 + D) * G.field};
 #pragma unroll
-    for (int s = 0; s < 6; ++s) q[s] = T(src[b + (s - 2) * sd]);
-    mp5_lr(q, bc[0], bc[1]);
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int s = 0; s < 6; ++s) qd[v][s] = T(src[v][b + (s - 2) * sc]);
+    const double* bcs = cons + (long)(C_BF1 + C) * G.field;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) qc[s] = T(bcs[b + (s - 2) * sd]);
   }
-  const T apd = fmax(T(ctd_d[4 * G.field + b]), T(ctd_d[4 * G.field + b + sc]));
-  const T amd = fmax(T(ctd_d[5 * G.field + b]), T(ctd_d[5 * G.field + b + sc]));
-  const T apc = fmax(T(ctd_c[4 * G.field + b]), T(ctd_c[4 * G.field + b + sd]));
-  const T amc = fmax(T(ctd_c[5 * G.field + b]), T(ctd_c[5 * G.field + b + sd]));
-
   MET m;
   if constexpr (!MET::flat) {
     // x^3 edges -> E3 tables, x^1 edges (i, j+1/2, k+1/2) -> F2, x^2 edges -> F1
     constexpr int loc = E == 2 ? LOC_E3 : (E == 0 ? LOC_F2 : LOC_F1);
     m.load(tab, G.tab_plane, loc, G.tidx(ii[0], ii[1]));
   }
-  const T sdd = apd + amd, scc = apc + amc;
-  const bool tiny_d = sdd < tiny_speed<T>(), tiny_c = scc < tiny_speed<T>();
-  const T isd = tiny_d ? T(0) : T(1) / sdd;
-  const T isc = tiny_c ? T(0) : T(1) / scc;
-  const T wd[2] = {tiny_d ? T(0.5) : apd * isd, tiny_d ? T(0.5) : amd * isd};
-  const T wc[2] = {tiny_c ? T(0.5) : apc * isc, tiny_c ? T(0.5) : amc * isc};
-  const T kd = tiny_d ? T(0) : apd * amd * isd;
-  const T kc = tiny_c ? T(0) : apc * amc * isc;
-  T ee = T(0);
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb) {
-      const T vtd = m.tvel(vd[a][bb], D);
-      const T vtc = m.tvel(vc[a][bb], C);
-      const T eab = vtc * bd[bb] - vtd * bc[a];
-      ee = ee + wd[a] * wc[bb] * eab;
-    }
-  }
-  ee = ee + kd * (bc[1] - bc[0]) - kc * (bd[1] - bd[0]);
+  const T ee = edge_body<E>(qd, qc, T(ctd_d[4 * G.field + b]), T(ctd_d[4 * G.field + b + sc]),
+                            T(ctd_d[5 * G.field + b]), T(ctd_d[5 * G.field + b + sc]),
+                            T(ctd_c[4 * G.field + b]), T(ctd_c[4 * G.field + b + sd]),
+                            T(ctd_c[5 * G.field + b]), T(ctd_c[5 * G.field + b + sd]), m);
   edge[b] = double(ee);
 }
 

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
                                                 const double* __restrict__ tab, double a, double b,
                                                 double dt_host, const double* __restrict__ d_dt,
                                                 double* __restrict__ out) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = flat_thread();
   if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
   int i, j, k;
   zone_of(G, t, i, j, k);
@@ -174,6 +174,107 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
   }
 }
 
+// z-marching variant (flat metric): one thread per (i, j) column segment of
+// KZ zones along x^3.  The x^3 stencils (F of the x^3 sweep, E_1, E_2) are
+// kept in register windows, so each of their planes is read once per
+// segment instead of six times; x^1 and x^2 stencils are read per plane.
+constexpr int KZ = 16;
+
+template <class MET>
+__global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restrict__ prim,
+                                                   double* __restrict__ cons,
+                                                   const double* __restrict__ cons_n,
+                                                   const double* __restrict__ flux,
+                                                   const double* __restrict__ edges,
+                                                   const double* __restrict__ tab, double a,
+                                                   double b, double dt_host,
+                                                   const double* __restrict__ d_dt) {
+  const long t = flat_thread();
+  const int nseg = (G.n[2] + KZ - 1) / KZ;
+  if (t >= (long)G.n[0] * G.n[1] * nseg) return;
+  const int i = (int)(t % G.n[0]);
+  const long r = t / G.n[0];
+  const int j = (int)(r % G.n[1]);
+  const int k0 = (int)(r / G.n[1]) * KZ;
+  const int k1 = min(k0 + KZ, G.n[2]);
+  const double dt = dt_host > 0.0 ? dt_host : *d_dt;
+  const long sx = 1, sy = G.pitch, sz = G.plane;
+  const double idx0 = 1.0 / G.dx[0], idx1 = 1.0 / G.dx[1], idx2 = 1.0 / G.dx[2];
+  const double* fz = flux + 2L * 5 * G.field;   // x^3-sweep fluxes
+  const double* e1 = edges;                     // E_1 (offsets in x^2, x^3)
+  const double* e2 = edges + G.field;           // E_2 (offsets in x^3, x^1)
+  const double* e3 = edges + 2 * G.field;       // E_3 (offsets in x^1, x^2)
+  // windows along x^3: w[s] holds stored index k - 3 + s
+  double wf[5][6], w1[6], w2[6];
+  long c = G.idx(i, j, k0);
+#pragma unroll
+  for (int s = 0; s < 5; ++s) {
+    const long cs = c + (s - 3) * sz;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) wf[q][s] = fz[(long)q * G.field + cs];
+    w1[s] = e1[cs];
+    w2[s] = e2[cs];
+  }
+  for (int k = k0; k < k1; ++k, c += sz) {
+    const long cn = c + 2 * sz;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) wf[q][5] = fz[(long)q * G.field + cn];
+    w1[5] = e1[cn];
+    w2[5] = e2[cn];
+    double f[6];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      double L = 0.0;
+      const double* fx = flux + (long)q * G.field + c;
+      const double* fy = flux + (5L + q) * G.field + c;
+#pragma unroll
+      for (int s = 0; s < 6; ++s) f[s] = fx[(s - 3) * sx];
+      L = L - fd_deriv(f, idx0);
+#pragma unroll
+      for (int s = 0; s < 6; ++s) f[s] = fy[(s - 3) * sy];
+      L = L - fd_deriv(f, idx1);
+      L = L - fd_deriv(wf[q], idx2);
+      const long o = (long)q * G.field + c;
+      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
+    }
+    // B^1: -D_2 E_3 + D_3 E_2
+    {
+#pragma unroll
+      for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sy];
+      const double L = -fd_deriv(f, idx1) + fd_deriv(w2, idx2);
+      const long o = (long)C_BF1 * G.field + c;
+      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
+    }
+    // B^2: -D_3 E_1 + D_1 E_3
+    {
+#pragma unroll
+      for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sx];
+      const double L = -fd_deriv(w1, idx2) + fd_deriv(f, idx0);
+      const long o = (long)C_BF2 * G.field + c;
+      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
+    }
+    // B^3: -D_1 E_2 + D_2 E_1
+    {
+      double g2[6];
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        f[s] = e2[c + (s - 3) * sx];
+        g2[s] = e1[c + (s - 3) * sy];
+      }
+      const double L = -fd_deriv(f, idx0) + fd_deriv(g2, idx1);
+      const long o = (long)C_BF3 * G.field + c;
+      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
+    }
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) wf[q][s] = wf[q][s + 1];
+      w1[s] = w1[s + 1];
+      w2[s] = w2[s + 1];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ centred B
 template <class MET>
 __device__ __forceinline__ void centred_b(const Geom& G, const double* __restrict__ cons, long c,
@@ -189,81 +290,12 @@ __device__ __forceinline__ void centred_b(const Geom& G, const double* __restric
   }
 }
 
-// ------------------------------------------------------------------ inversion
-struct NewtonOut {
-  double rho, p, u[3];
-  int iters;
-  bool ok;
-};
-
-template <class MET>
-__device__ __forceinline__ NewtonOut newton(double dd, const double S[3], double tau,
-                                            const double B[3], const MET& m, double gam,
-                                            double y0, double tol, int maxit) {
-  NewtonOut o;
-  const double utot = tau + dd;
-  double su[3], bl[3];
-  m.raise(S, su);
-  m.lower(B, bl);
-  const double s2 = S[0] * su[0] + S[1] * su[1] + S[2] * su[2];
-  const double b2 = bl[0] * B[0] + bl[1] * B[1] + bl[2] * B[2];
-  const double sb = S[0] * B[0] + S[1] * B[1] + S[2] * B[2];
-  const double sb2 = sb * sb;
-  const double gf = (gam - 1.0) / gam;
-  const bool valid = isfinite(dd) && isfinite(utot) && isfinite(s2) && isfinite(b2) &&
-                     isfinite(sb) && dd > 0.0 && utot > 0.0;
-  double a = 0.0, bb = gam * utot;
-  double y = y0;
-  if (!(y > a && y < bb)) y = 0.5 * (a + bb);
-  bool conv = false;
-  int it = 0;
-  constexpr double EPS4 = 4.0 * 2.220446049250313e-16;
-  if (valid) {
-    for (; it < maxit;) {
-      ++it;
-      const double yy = y * y;
-      const double v2 = (s2 + sb2 * (2.0 * y + b2) / yy) / ((y + b2) * (y + b2));
-      const bool bad = v2 >= 1.0;
-      const double sq = sqrt(1.0 - v2);
-      const double p = gf * (y * (1.0 - v2) - dd * sq);
-      const double f = y - p + 0.5 * b2 * (1.0 + v2) - 0.5 * sb2 / yy - utot;
-      const double yb = y + b2;
-      const double y3 = yy * y;
-      const double dv2 = (-2.0 * sb2 * yb / y3 / (yb * yb) -
-                          2.0 * (s2 + sb2 * (2.0 * y + b2) / yy) / (yb * yb * yb));
-      const double dp = gf * ((1.0 - v2) - y * dv2 + dd * dv2 / (2.0 * sq));
-      const double fp = 1.0 - dp + 0.5 * b2 * dv2 + sb2 / y3;
-      const double fabs_ = y + fabs(p) + 0.5 * b2 * (1.0 + v2) + 0.5 * sb2 / yy + utot;
-      if (!bad && fabs(f) <= EPS4 * fabs_) { conv = true; break; }
-      const bool below = bad || (f < 0.0);
-      if (below) a = y; else bb = y;
-      double yn = y - f / fp;
-      if (bad || !(yn >= a && yn <= bb)) yn = 0.5 * (a + bb);
-      const double dy = yn - y;
-      y = yn;
-      if (fabs(dy) <= tol * y) { conv = true; break; }
-    }
-  }
-  const double v2 = (s2 + sb2 * (2.0 * y + b2) / (y * y)) / ((y + b2) * (y + b2));
-  const double w = 1.0 / sqrt(1.0 - v2);
-  o.p = gf * (y * (1.0 - v2) - dd * sqrt(1.0 - v2));
-  o.rho = dd / w;
-  double vl[3], vu[3];
-  for (int q = 0; q < 3; ++q) vl[q] = (S[q] + (sb / y) * bl[q]) / (y + b2);
-  m.raise(vl, vu);
-  for (int q = 0; q < 3; ++q) o.u[q] = w * vu[q];
-  o.ok = conv && valid && (v2 < 1.0) && isfinite(o.rho) && isfinite(o.p) && isfinite(o.u[0]) &&
-         isfinite(o.u[1]) && isfinite(o.u[2]);
-  o.iters = it;
-  return o;
-}
-
 template <class MET>
 __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __restrict__ prim,
                                              double* __restrict__ cons,
                                              const double* __restrict__ tab,
                                              long long* __restrict__ partials) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = flat_thread();
   const bool live = t < (long)G.n[0] * G.n[1] * G.n[2];
   long long st[6] = {0, 0, 0, 0, 0, 0};
   if (live) {
@@ -291,7 +323,7 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
       const double h = 1.0 + G.gam / (G.gam - 1.0) * p / rho;
       y0 = rho * h * (1.0 + uu);
     }
-    const NewtonOut r = newton(dd, S, tau, B, m, G.gam, y0, cp.tol, cp.maxit);
+    const NewtonOut<double> r = newton<double>(dd, S, tau, B, m, G.gam, y0, cp.tol, cp.maxit);
     if (r.ok) {
       rho = r.rho;
       p = r.p;
@@ -397,7 +429,7 @@ template <class MET>
 __global__ __launch_bounds__(256) void k_prim2cons(Geom G, double* __restrict__ prim,
                                                    double* __restrict__ cons,
                                                    const double* __restrict__ tab) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = flat_thread();
   if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
   int i, j, k;
   zone_of(G, t, i, j, k);
@@ -422,7 +454,7 @@ template <class MET>
 __global__ __launch_bounds__(256) void k_cfl(Geom G, const double* __restrict__ prim,
                                              const double* __restrict__ tab,
                                              double* __restrict__ partials) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = flat_thread();
   double v = 0.0;
   if (t < (long)G.n[0] * G.n[1] * G.n[2]) {
     int i, j, k;
@@ -466,7 +498,7 @@ __global__ __launch_bounds__(256) void k_curl(Geom G, const double* __restrict__
                                               const double* __restrict__ a2,
                                               const double* __restrict__ a3,
                                               double* __restrict__ cons) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = flat_thread();
   if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
   int i, j, k;
   zone_of(G, t, i, j, k);
@@ -535,7 +567,7 @@ __device__ __forceinline__ GhostSrc ghost_src(const Geom& G, const BCSpec& bc, i
 
 __global__ __launch_bounds__(256) void k_bc_centred(Geom G, BCSpec bc, double* __restrict__ prim,
                                                     int nfields) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = flat_thread();
   if (t >= (long)G.dims[0] * G.dims[1] * G.dims[2]) return;
   const int i = (int)(t % G.dims[0]) - NG;
   const long r = t / G.dims[0];
@@ -554,7 +586,7 @@ __global__ __launch_bounds__(256) void k_bc_centred(Geom G, BCSpec bc, double* _
 }
 
 __global__ __launch_bounds__(256) void k_bc_faces(Geom G, BCSpec bc, double* __restrict__ cons) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = flat_thread();
   if (t >= (long)G.dims[0] * G.dims[1] * G.dims[2]) return;
   const int i = (int)(t % G.dims[0]) - NG;
   const long r = t / G.dims[0];
@@ -577,7 +609,7 @@ __global__ __launch_bounds__(256) void k_diag(Geom G, const double* __restrict__
                                               const double* __restrict__ cons,
                                               const double* __restrict__ tab,
                                               double* __restrict__ partials) {
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long t = flat_thread();
   double sv[DIAG_NSUM], mv[DIAG_NMAX];
   for (int q = 0; q < DIAG_NSUM; ++q) sv[q] = 0.0;
   for (int q = 0; q < DIAG_NMAX; ++q) mv[q] = -INFINITY;
@@ -677,7 +709,12 @@ void launch_update(const Geom& G, bool flat, int mode, const double* prim, doubl
                    const double* tab, double a, double b, double dt_host, const double* d_dt,
                    double* out, hipStream_t s) {
   const unsigned nb = zone_blocks(G);
-  if (flat)
+  if (flat && mode == 0) {
+    const long nseg = (G.n[2] + KZ - 1) / KZ;
+    const long total = (long)G.n[0] * G.n[1] * nseg;
+    hipLaunchKernelGGL(k_update_zm<FlatMet<double>>, dim3(nblk(total)), dim3(256), 0, s, G, prim,
+                       cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt);
+  } else if (flat)
     hipLaunchKernelGGL(k_update<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
                        cons_n, flux, edges, tab, a, b, dt_host, d_dt, out);
   else
