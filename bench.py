@@ -82,6 +82,61 @@ def cpu_baseline(seconds_target=12.0):
                       "%d SSP-RK3 steps, %.1f s wall" % (steps, wall)}
 
 
+def precision_report(args):
+    """Both forms on the same seeded grid with the same fixed dt (the FP64
+    CFL step of the initial state), timed separately; per-field maximum error
+    of the FP32-flux form relative to the FP64 form after the steps."""
+    import numpy as np
+    import torch
+    from workloads import box
+    from paper_1810_04597_amd.grid import Grid, PRIM
+    from paper_1810_04597_amd import _lib as L
+    n = args.n
+    g, d = box.turbulent_box(n)
+    grids = {}
+    for name, prec in (("fp64", L.FP64), ("fp32", L.FP32_FLUX)):
+        G = Grid(g, precision=prec)
+        G.curl_potential(d)
+        G.set_primitives(d)
+        grids[name] = G
+    del d
+    dt = grids["fp64"].compute_dt()
+    res = {}
+    for name, G in grids.items():
+        G.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(G.stream)
+        for _ in range(args.steps):
+            G.rk_step(dt)
+        e1.record(G.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[name] = {"ms_per_step": ms / args.steps, "zone_updates_per_s": n ** 3 * args.steps / (ms / 1e3)}
+        print("bench: %s form done" % name, file=sys.stderr, flush=True)
+    errs = {}
+    A, B = grids["fp32"], grids["fp64"]
+    gg = g.ng
+    for f, k in enumerate(PRIM):
+        a = A.field_view(A.prim, f)[gg:-gg, gg:-gg, gg:-gg]
+        b = B.field_view(B.prim, f)[gg:-gg, gg:-gg, gg:-gg]
+        if k in ("rho", "p"):
+            errs[k] = float(((a - b).abs() / b.abs()).max())
+        else:
+            errs[k] = float((a - b).abs().max() / b.abs().max())
+    out = {"metric": "zone-updates/s per RK3 step, FP32-flux form vs FP64 (%d^3)" % n,
+           "value": res["fp32"]["zone_updates_per_s"], "unit": "zone-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": 0,
+           "ms_per_step": res["fp32"]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32-flux/f64", "data": "synthetic",
+           "config": {"workload": "turbulent SRMHD box %d^3, fixed dt %.3e, seed 1810" % (n, dt)},
+           "fp64": res["fp64"], "rel_error_vs_fp64": errs,
+           "speedup_vs_fp64": res["fp32"]["zone_updates_per_s"] / res["fp64"]["zone_updates_per_s"]}
+    for G in grids.values():
+        G.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,12 +146,17 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true", default=True)
+    ap.add_argument("--mode", default="step", choices=["step", "precision"],
+                    help="step: the FP64 RK3 step (default); precision: FP32-flux form "
+                         "against FP64 on the same grid, fixed dt, per-field error")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (a single grid block per device); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))
+    if args.mode == "precision":
+        return precision_report(args)
 
     import torch
     from workloads import box

@@ -103,8 +103,14 @@ def _nan(shape):
 
 
 class Solver:
-    def __init__(self, grid, tables=None):
+    """precision: "fp64", or "fp32" for the precision form in which the
+    reconstruction, face physics, HLL flux and edge field are evaluated in
+    float32 from float32-rounded inputs and widened to float64 afterwards
+    (derivatives, sources, RK combine and inversion stay float64)."""
+
+    def __init__(self, grid, tables=None, precision="fp64"):
         self.grid = grid
+        self.ftype = np.float32 if precision == "fp32" else np.float64
         self.g = grid.ng
         self.gam = grid.gamma_ad
         self.met = Metric(minkowski_tables(grid) if tables is None else tables)
@@ -185,7 +191,9 @@ class Solver:
         n = gr.n[d]
         lo, hi = -3, n + 2
         c = (d + 1) % 3
-        P = self.P
+        ft = self.ftype
+        P = {k: v.astype(ft) for k, v in self.P.items()}
+        gam = ft(gam)
         rec = {}
         for k in ("rho", "p", "u1", "u2", "u3"):
             rec[k] = face_states(P[k], d, lo, hi, g, take)
@@ -195,15 +203,15 @@ class Solver:
             l, r = rec[k]
             cj = take(P[k], d, lo, hi, g)
             cj1 = take(P[k], d, lo + 1, hi + 1, g)
-            rec[k] = (np.maximum(l, POS_FRAC * cj), np.maximum(r, POS_FRAC * cj1))
+            rec[k] = (np.maximum(l, ft(POS_FRAC) * cj), np.maximum(r, ft(POS_FRAC) * cj1))
         for t in range(3):
             if t != d:
                 rec["B%d" % (t + 1)] = face_states(P["B%d" % (t + 1)], d, lo, hi, g, take)
-        mf = Metric.sel(self.met.loc[FACE_LOC[d]], d, lo, hi, g)
+        mf = {k: v.astype(ft) for k, v in Metric.sel(self.met.loc[FACE_LOC[d]], d, lo, hi, g).items()}
         sg = mf["sqrtg"]
-        bn_face = take(self.U["Bf%d" % (d + 1)], d, lo, hi, g)
+        bn_face = take(self.U["Bf%d" % (d + 1)], d, lo, hi, g).astype(ft)
         with np.errstate(divide="ignore", invalid="ignore"):
-            bn = np.where(sg != 0.0, bn_face / np.where(sg != 0.0, sg, 1.0), 0.0)
+            bn = np.where(sg != 0.0, bn_face / np.where(sg != 0.0, sg, ft(1.0)), ft(0.0))
         sts = []
         for side in (0, 1):
             u = tuple(rec["u%d" % (t + 1)][side] for t in range(3))
@@ -227,7 +235,7 @@ class Solver:
         full = {}
         for k, v in out.items():
             a = _nan(gr.shape)
-            fd.put(a, d, lo, hi, g, np.broadcast_to(v, take(a, d, lo, hi, g).shape))
+            fd.put(a, d, lo, hi, g, np.broadcast_to(v, take(a, d, lo, hi, g).shape).astype(np.float64))
             full[k] = a
         return full
 
@@ -236,7 +244,10 @@ class Solver:
         g, gr = self.g, self.grid
         d, c = (e + 1) % 3, (e + 2) % 3
         nd, nc = gr.n[d], gr.n[c]
-        D, C = fdat[d], fdat[c]
+        ft = self.ftype
+        D = {k: v.astype(ft) for k, v in fdat[d].items()}
+        C = {k: v.astype(ft) for k, v in fdat[c].items()}
+        UB = {k: self.U[k].astype(ft) for k in FACE}
         # reconstruct d-face data along c to the edge (side b)
         def along_c(q):
             l, r = face_states(q, c, -3, nc + 2, g, take)
@@ -245,9 +256,9 @@ class Solver:
         vd.update({("R", b): x for b, x in zip("LR", along_c(D["vdR"]))})
         vc = {("L", b): x for b, x in zip("LR", along_c(D["vcL"]))}
         vc.update({("R", b): x for b, x in zip("LR", along_c(D["vcR"]))})
-        bd = dict(zip("LR", along_c(self.U["Bf%d" % (d + 1)])))
+        bd = dict(zip("LR", along_c(UB["Bf%d" % (d + 1)])))
         # reconstruct B^c (c-faces) along d (side a)
-        l, r = face_states(self.U["Bf%d" % (c + 1)], d, -3, nd + 2, g, take)
+        l, r = face_states(UB["Bf%d" % (c + 1)], d, -3, nd + 2, g, take)
         bc = {"L": take(l, c, -3, nc + 2, g), "R": take(r, c, -3, nc + 2, g)}
         # speeds: max over the two faces adjacent to the edge
         def adj(q, along, other, n_along, n_other):
@@ -261,17 +272,20 @@ class Solver:
         amc = adj(C["am"], d, c, nd, nc)
         me = Metric.sel(Metric.sel(self.met.loc[EDGE_LOC[e]], d, -3, nd + 2, g),
                         c, -3, nc + 2, g)
+        me = {k: v.astype(ft) for k, v in me.items()}
         al = me["alpha"]
         betd, betc = me["beta%d" % (d + 1)], me["beta%d" % (c + 1)]
         with np.errstate(divide="ignore", invalid="ignore"):
             sd = apd + amd
             sc = apc + amc
-            tiny_d, tiny_c = sd < 1e-300, sc < 1e-300
-            wd = {"L": np.where(tiny_d, 0.5, apd / sd), "R": np.where(tiny_d, 0.5, amd / sd)}
-            wc = {"L": np.where(tiny_c, 0.5, apc / sc), "R": np.where(tiny_c, 0.5, amc / sc)}
-            kd = np.where(tiny_d, 0.0, apd * amd / sd)
-            kc = np.where(tiny_c, 0.0, apc * amc / sc)
-        ee = 0.0
+            tiny = ft(1e-300) if ft == np.float64 else ft(1e-37)
+            tiny_d, tiny_c = sd < tiny, sc < tiny
+            half, zero = ft(0.5), ft(0.0)
+            wd = {"L": np.where(tiny_d, half, apd / sd), "R": np.where(tiny_d, half, amd / sd)}
+            wc = {"L": np.where(tiny_c, half, apc / sc), "R": np.where(tiny_c, half, amc / sc)}
+            kd = np.where(tiny_d, zero, apd * amd / sd)
+            kc = np.where(tiny_c, zero, apc * amc / sc)
+        ee = ft(0.0)
         for a_ in "LR":
             for b_ in "LR":
                 vtd = al * vd[(a_, b_)] - betd
@@ -283,7 +297,7 @@ class Solver:
         sl = [slice(None)] * 3
         sl[fd.AXIS[d]] = slice(-3 + g, nd + 2 + g)
         sl[fd.AXIS[c]] = slice(-3 + g, nc + 2 + g)
-        out[tuple(sl)] = ee
+        out[tuple(sl)] = np.asarray(ee, dtype=np.float64)
         return out
 
     def rhs_parts(self):
