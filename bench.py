@@ -137,6 +137,144 @@ def precision_report(args):
     print(json.dumps(out))
 
 
+def torus_report(args):
+    """Plain FP64 GRMHD torus (Kerr-Schild a = 0.9, tabulated metric, floors,
+    device CFL step): zone-updates/s and per-kernel times."""
+    import torch
+    from workloads.torus import torus
+    from paper_1810_04597_amd.grid import Grid
+    n1, n2, n3 = (int(x) for x in args.torus.split(","))
+    g, d, tab = torus(n1, n2, n3)
+    G = Grid(g, tables=tab)
+    G.curl_potential(d)
+    G.set_primitives(d)
+    for _ in range(args.warmup):
+        G.rk_step()
+    G.set_profiling(True)
+    G.profile(reset=True)
+    G.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(G.stream)
+    for _ in range(args.steps):
+        G.rk_step()
+    e1.record(G.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = G.profile(reset=True)
+    dg = G.diagnostics()
+    out = {"metric": "zone-updates/s per RK3 step, KS torus %dx%dx%d (FP64)" % (n1, n2, n3),
+           "value": g.zones * args.steps / (ms / 1e3), "unit": "zone-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "Kerr-Schild a=0.9 torus %dx%dx%d, r 1.2-50, 2%% noise, beta 100, floors, device CFL" % (n1, n2, n3)},
+           "kernels": {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in prof.items()},
+           "diag": {k: dg[k] for k in ("t", "max_divb", "rho_min", "rho_max", "w_max", "n_floor_rho",
+                                       "n_floor_p", "n_wcap", "n_c2p_fail", "newton_iters_sum",
+                                       "newton_iters_max", "n_nonfinite")}}
+    G.close()
+    print(json.dumps(out))
+
+
+def learned_report(args):
+    """Train the learned Newton guess on the GPU (seeded samples, own kernels),
+    then run the Kerr-Schild torus with three forms on the same GPU: plain
+    FP64 (warm guess), FP32 flux + learned guess, FP32 flux + warm guess;
+    fixed dt; density error of the FP32 forms against FP64."""
+    import numpy as np
+    import torch
+    from workloads.mlp_data import sample_prims, init_weights
+    from workloads.torus import torus
+    from paper_1810_04597_amd.grid import Grid
+    from paper_1810_04597_amd import _lib as L
+    n1, n2, n3 = (int(x) for x in args.torus.split(","))
+    g, d, tab = torus(n1, n2, n3)
+    # --- training on 2^k seeded samples
+    T = Grid(g, tables=tab)
+    prims = sample_prims(args.train_samples)
+    T.mlp_set_weights(L.mlp_pack(init_weights()), np.ones(32, np.float32))
+    feat, targ = T.mlp_datagen(prims, set_norm=True)
+    del prims
+    batch = 4096
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for epoch in range(args.epochs):
+        lr = 1e-3 if epoch < (2 * args.epochs) // 3 else 3e-4
+        for s0 in range(0, feat.shape[0], batch):
+            l = T.mlp_train_step(feat[s0:s0 + batch], targ[s0:s0 + batch], lr, want_loss=(s0 == 0))
+            if s0 == 0:
+                losses.append(l)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    flat, norm = T.mlp_get_weights()
+    print("bench: trained %d epochs in %.1f s, loss %s" % (args.epochs, train_s, losses[-1]),
+          file=sys.stderr, flush=True)
+    # unseen samples: Newton iterations from the cold start and from the network
+    test = sample_prims(1 << 18, seed=99)
+    ft, tt, cons = T.mlp_datagen(test, want_cons=True)
+    out = T.mlp_forward(ft)
+    y0 = ((cons[:, 4] + cons[:, 0]) * torch.pow(10.0, out[:, 0].double() * float(norm[24]) + float(norm[16]))).contiguous()
+    _, ic = T.cons2prim_points(cons)
+    _, im = T.cons2prim_points(cons, y0)
+    ic, im = ic.cpu().numpy(), im.cpu().numpy()
+    ok = (ic > 0) & (im > 0)
+    T.close()
+    del feat, targ
+    forms = {"fp64_warm": (L.FP64, L.GUESS_WARM), "fp32_learned": (L.FP32_FLUX, L.GUESS_MLP),
+             "fp32_warm": (L.FP32_FLUX, L.GUESS_WARM)}
+    res, grids = {}, {}
+    dt = None
+    for name, (prec, guess) in forms.items():
+        G = Grid(g, tables=tab, precision=prec, guess=guess)
+        if guess == L.GUESS_MLP:
+            G.mlp_set_weights(flat, norm)
+        G.curl_potential(d)
+        G.set_primitives(d)
+        if dt is None:
+            dt = G.compute_dt()
+        G.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(G.stream)
+        for _ in range(args.steps):
+            G.rk_step(dt)
+        e1.record(G.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        dg = G.diagnostics()
+        res[name] = {"ms_per_step": ms / args.steps, "zone_updates_per_s": g.zones * args.steps / (ms / 1e3),
+                     "newton_iters_per_zone_last": dg["newton_iters_sum"] / g.zones,
+                     "learned_fallbacks_last": dg["n_mlp_fallback"], "c2p_fail_last": dg["n_c2p_fail"]}
+        grids[name] = G
+        print("bench: %s done" % name, file=sys.stderr, flush=True)
+    ref = grids["fp64_warm"]
+    gg = g.ng
+    b = ref.field_view(ref.prim, 0)[gg:-gg, gg:-gg, gg:-gg]
+    for name in ("fp32_learned", "fp32_warm"):
+        a = grids[name].field_view(grids[name].prim, 0)[gg:-gg, gg:-gg, gg:-gg]
+        rel = ((a - b).abs() / b.abs())
+        res[name]["rho_rel_err_max"] = float(rel.max())
+        res[name]["rho_rel_err_median"] = float(rel.median())
+        body = b > 0.05
+        res[name]["rho_rel_err_max_body"] = float(rel[body].max())
+    for G in grids.values():
+        G.close()
+    out = {"metric": "zone-updates/s, FP32 flux + learned Newton guess vs FP64, KS torus %dx%dx%d" % (n1, n2, n3),
+           "value": res["fp32_learned"]["zone_updates_per_s"], "unit": "zone-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 0, "ms_per_step": res["fp32_learned"]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32-flux/f64 + bf16 mlp", "data": "synthetic",
+           "config": {"workload": "Kerr-Schild a=0.9 torus %dx%dx%d, fixed dt %.3e, 2%% noise, beta 100" % (n1, n2, n3, dt),
+                      "train_samples": args.train_samples, "epochs": args.epochs},
+           "training": {"seconds": train_s, "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1]},
+           "unseen_samples_newton_iters": {"cold": float(ic[ok].mean()), "learned": float(im[ok].mean()),
+                                           "n": int(ok.sum())},
+           "forms": res}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,9 +284,14 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernels", action="store_true", default=True)
-    ap.add_argument("--mode", default="step", choices=["step", "precision"],
+    ap.add_argument("--mode", default="step", choices=["step", "precision", "learned", "torus"],
                     help="step: the FP64 RK3 step (default); precision: FP32-flux form "
-                         "against FP64 on the same grid, fixed dt, per-field error")
+                         "against FP64 on the same grid, fixed dt, per-field error; learned: "
+                         "train the Newton-guess network on the GPU, then the Kerr-Schild "
+                         "torus in plain FP64 vs FP32 flux + learned guess")
+    ap.add_argument("--train-samples", type=int, default=1 << 22)
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--torus", default="384,192,192")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (a single grid block per device); "
@@ -157,6 +300,10 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     if args.mode == "precision":
         return precision_report(args)
+    if args.mode == "learned":
+        return learned_report(args)
+    if args.mode == "torus":
+        return torus_report(args)
 
     import torch
     from workloads import box

@@ -173,6 +173,49 @@ int grmhd_compute_dt(grmhd_grid* h, double* dt);
  * order (deterministic). */
 int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out);
 
+/* Learned Newton initial guess (a training-system pattern layered on the
+ * method; the paper has no counterpart).  An MLP 8 -> 64 -> 64 -> 64 -> 5
+ * (tanh hidden layers, linear output) runs on BF16 matrix cores with FP32
+ * accumulation; FP32 master weights and Adam moments live in the library.
+ * Inputs: [log10 D, log10(tau/D), S_hat/(tau+D), B_hat/sqrt(tau+D)] in the
+ * Eulerian orthonormal frame; outputs [log10(y/U), log10(p/D), u_hat] with
+ * y = rho h W^2 and U = tau + D; both standardised with the normalisation
+ * block.  With c2p_guess = GRMHD_GUESS_MLP the inversion starts Newton from
+ * the network's y0 = U 10^{output 0} and falls back to the warm guess when it
+ * does not converge (counted in grmhd_diag.n_mlp_fallback).
+ * Parameter block (float32, GRMHD_MLP_NPARAM): W1[64][16] (inputs padded to
+ * 16 with zeros), b1[64], W2[64][64], b2[64], W3[64][64], b3[64],
+ * W4[16][64] (outputs padded to 16 with zeros), b4[16].  Normalisation block
+ * (GRMHD_MLP_NNORM): feature mean[8], std[8], target mean[8], std[8].
+ * Sample arrays are device float32: features n x 8, targets n x 8 (5 used),
+ * outputs n x 8 (5 used, standardised). */
+#define GRMHD_MLP_NPARAM 10448
+#define GRMHD_MLP_NNORM 32
+int grmhd_mlp_set_weights(grmhd_grid* h, const float* host_params, size_t n_params,
+                          const float* host_norm, size_t n_norm);
+int grmhd_mlp_get_weights(grmhd_grid* h, float* host_params, float* host_norm);
+/* Training pairs from device primitives prims (n x 8 float64: rho, u^1..3, p,
+ * B^1..3, flat local frame) through the method's prim -> cons map; cons_out
+ * (nullable, n x 8 float64) receives D, S_1..3, tau, B^1..3; set_norm != 0
+ * also sets the normalisation block from these samples. */
+int grmhd_mlp_datagen(grmhd_grid* h, const double* prims, int64_t n, float* feat, float* targ,
+                      double* cons_out, int set_norm);
+/* Batched point-wise inversion in a flat local frame (the safeguarded Newton
+ * of the grid inversion): cons rows D, S_1..3, tau, B^1..3 (device, n x 8
+ * float64); y0 (device, nullable): Newton guesses, Gamma U when NULL;
+ * prim_out rows rho, u^1..3, p, B^1..3; iters_out (nullable, int32): Newton
+ * iterations, negative when the zone failed. */
+int grmhd_cons2prim_points(grmhd_grid* h, const double* cons, int64_t n, const double* y0,
+                           double* prim_out, int32_t* iters_out);
+/* Mean-squared-error gradient over n samples (synchronises; no update). */
+int grmhd_mlp_gradient(grmhd_grid* h, const float* feat, const float* targ, int64_t n,
+                       float* grad_host, double* loss_host);
+/* One Adam step (lr; beta 0.9, 0.999; eps 1e-8) on a batch of samples;
+ * loss (nullable) receives the batch loss before the step (synchronises). */
+int grmhd_mlp_train_step(grmhd_grid* h, const float* feat, const float* targ, int64_t batch,
+                         float lr, double* loss);
+int grmhd_mlp_forward(grmhd_grid* h, const float* feat, int64_t n, float* out);
+
 /* Kernel timing (observability).  When enabled, every launch the library
  * makes is bracketed by HIP events on the grid's stream (no host sync);
  * grmhd_get_profile synchronises the stream, accumulates the elapsed times

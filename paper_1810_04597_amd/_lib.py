@@ -17,7 +17,11 @@ EXPORTS = ("grmhd_init_grid", "grmhd_get_layout", "grmhd_bind_fields", "grmhd_se
            "grmhd_curl_potential", "grmhd_prim2cons", "grmhd_rhs", "grmhd_rk_step",
            "grmhd_cons2prim", "grmhd_compute_dt", "grmhd_diagnostics", "grmhd_destroy",
            "grmhd_last_error", "grmhd_set_profiling", "grmhd_get_profile",
-           "grmhd_profile_class_name")
+           "grmhd_profile_class_name", "grmhd_mlp_set_weights", "grmhd_mlp_get_weights",
+           "grmhd_mlp_datagen", "grmhd_mlp_gradient", "grmhd_mlp_train_step", "grmhd_mlp_forward",
+           "grmhd_cons2prim_points")
+MLP_NPARAM = 10448
+MLP_NNORM = 32
 PROF_NCLASS = 16
 
 
@@ -98,6 +102,14 @@ def lib():
     L.grmhd_get_profile.argtypes = [P, C.POINTER(Profile), C.c_int]
     L.grmhd_profile_class_name.argtypes = [C.c_int]
     L.grmhd_profile_class_name.restype = C.c_char_p
+    F = C.POINTER(C.c_float)
+    L.grmhd_mlp_set_weights.argtypes = [P, F, C.c_size_t, F, C.c_size_t]
+    L.grmhd_mlp_get_weights.argtypes = [P, F, F]
+    L.grmhd_mlp_datagen.argtypes = [P, P, C.c_int64, P, P, P, C.c_int]
+    L.grmhd_cons2prim_points.argtypes = [P, P, C.c_int64, P, P, P]
+    L.grmhd_mlp_gradient.argtypes = [P, P, P, C.c_int64, F, D]
+    L.grmhd_mlp_train_step.argtypes = [P, P, P, C.c_int64, C.c_float, D]
+    L.grmhd_mlp_forward.argtypes = [P, P, C.c_int64, P]
     for name in EXPORTS:
         if name not in ("grmhd_destroy", "grmhd_last_error", "grmhd_profile_class_name"):
             getattr(L, name).restype = C.c_int
@@ -134,3 +146,45 @@ def make_desc(grid, precision=FP64, guess=GUESS_WARM):
     d.w_max = grid.w_max
     d.newton_tol = grid.newton_tol
     return d
+
+
+# ----------------------------------------------------------------- learned guess layout
+MLP_SHAPES = (((64, 16), 0), ((64,), 1024), ((64, 64), 1088), ((64,), 5184),
+              ((64, 64), 5248), ((64,), 9344), ((16, 64), 9408), ((16,), 10432))
+
+
+def mlp_pack(params):
+    """[(W (out, in), b (out))] x 4 (widths 8-64-64-64-5) -> padded flat float32."""
+    import numpy as np
+    flat = np.zeros(MLP_NPARAM, dtype=np.float32)
+    for li, (w, b) in enumerate(params):
+        (ws, wo), (bs, bo) = MLP_SHAPES[2 * li], MLP_SHAPES[2 * li + 1]
+        m = np.zeros(ws, dtype=np.float32)
+        m[:w.shape[0], :w.shape[1]] = w
+        flat[wo:wo + m.size] = m.ravel()
+        v = np.zeros(bs, dtype=np.float32)
+        v[:b.shape[0]] = b
+        flat[bo:bo + v.size] = v
+    return flat
+
+
+def mlp_unpack(flat):
+    import numpy as np
+    widths = (8, 64, 64, 64, 5)
+    out = []
+    for li in range(4):
+        (ws, wo), (bs, bo) = MLP_SHAPES[2 * li], MLP_SHAPES[2 * li + 1]
+        m = np.asarray(flat[wo:wo + ws[0] * ws[1]], dtype=np.float64).reshape(ws)
+        v = np.asarray(flat[bo:bo + bs[0]], dtype=np.float64)
+        out.append((m[:widths[li + 1], :widths[li]].copy(), v[:widths[li + 1]].copy()))
+    return out
+
+
+def mlp_norm_pack(fmean, fstd, tmean, tstd):
+    import numpy as np
+    n = np.zeros(MLP_NNORM, dtype=np.float32)
+    n[0:8], n[8:16] = fmean, fstd
+    n[16:16 + len(tmean)], n[24:24 + len(tstd)] = tmean, tstd
+    n[16 + len(tmean):24] = 0.0
+    n[24 + len(tstd):32] = 1.0
+    return n

@@ -10,6 +10,7 @@
 
 #include "grmhd.h"
 #include "grmhd_kernels.hpp"
+#include "grmhd_mlp.hpp"
 
 using namespace grmhd;
 
@@ -34,12 +35,14 @@ constexpr int SCR_CONS_N = 0;    // 8 fields
 constexpr int SCR_FLUX = 8;      // 3 x 5 fields
 constexpr int SCR_CTD = 23;      // 3 x 6 fields
 constexpr int SCR_EDGE = 41;     // 3 fields
-constexpr int SCR_NFIELDS = 44;
+constexpr int SCR_GUESS = 44;    // 1 field: learned Newton guess per zone
+constexpr int SCR_NFIELDS = 45;
+constexpr int MLP_MAX_WAVES = 256;
 
 const char* const PROF_NAMES[GRMHD_PROF_NCLASS] = {
     "bc_centred", "sweep_x1", "sweep_x2", "sweep_x3", "edge_x1", "edge_x2", "edge_x3",
     "update", "bc_faces", "cons2prim", "cfl", "copy_stage", "advance", "rhs_out",
-    "diagnostics", "other"};
+    "learned_guess", "learned_train"};
 }  // namespace
 
 struct grmhd_grid {
@@ -88,6 +91,9 @@ struct grmhd_grid {
   double* flux() const { return scratch + (long)SCR_FLUX * G.field; }
   double* ctd() const { return scratch + (long)SCR_CTD * G.field; }
   double* edges() const { return scratch + (long)SCR_EDGE * G.field; }
+  double* guess() const { return scratch + (long)SCR_GUESS * G.field; }
+  MlpState mlp;
+  bool mlp_alloc = false;
 };
 
 namespace {
@@ -120,8 +126,6 @@ int validate(const grmhd_grid_desc* d) {
   if (d->precision != GRMHD_FP64 && d->precision != GRMHD_FP32_FLUX)
     return fail(GRMHD_EINVAL, "bad precision");
   if (d->c2p_guess < 0 || d->c2p_guess > 2) return fail(GRMHD_EINVAL, "bad c2p_guess");
-  if (d->c2p_guess == GRMHD_GUESS_MLP)
-    return fail(GRMHD_EUNSUPPORTED, "learned guess not available in this build");
   if (d->newton_maxit < 1 || d->newton_maxit > 1000) return fail(GRMHD_EINVAL, "bad newton_maxit");
   if (!(d->newton_tol > 0.0)) return fail(GRMHD_EINVAL, "newton_tol must be > 0");
   if (d->rho_fl_a < 0.0 || d->p_fl_a < 0.0) return fail(GRMHD_EINVAL, "negative floor");
@@ -286,6 +290,21 @@ static void rhs_pieces(grmhd_grid* h) {
     h->timed(4 + e, [&] { launch_edge(e, h->G, h->flat, fp32, h->cons, h->tab, h->ctd(), h->edges(), h->stream); });
 }
 
+static void c2p_with_guess(grmhd_grid* h, const C2PParams& cp) {
+  const double* y0 = nullptr;
+  if (cp.guess == GRMHD_GUESS_MLP) {
+    h->timed(14, [&] { mlp_launch_guess(h->G, h->flat, h->cons, h->tab, h->mlp, h->guess(), h->stream); });
+    y0 = h->guess();
+  }
+  h->timed(9, [&] { launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, h->stream, y0); });
+}
+
+static int mlp_ready(grmhd_grid* h) {
+  if (h->desc.c2p_guess == GRMHD_GUESS_MLP && !h->mlp.weights_set)
+    return fail(GRMHD_ESTATE, "learned guess selected but no weights set");
+  return GRMHD_OK;
+}
+
 int grmhd_rhs(grmhd_grid* h, double* rhs_out) {
   int rc = ready(h);
   if (rc) return rc;
@@ -300,6 +319,8 @@ int grmhd_rhs(grmhd_grid* h, double* rhs_out) {
 
 int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used) {
   int rc = ready(h);
+  if (rc) return rc;
+  rc = mlp_ready(h);
   if (rc) return rc;
   if (!std::isfinite(dt)) return fail(GRMHD_EINVAL, "dt not finite");
   if (dt <= 0.0)
@@ -317,7 +338,7 @@ int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used) {
                     A[s], B[s], dt, h->d_dt, nullptr, h->stream);
     });
     h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
-    h->timed(9, [&] { launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, h->stream, nullptr); });
+    c2p_with_guess(h, cp);
   }
   h->timed(12, [&] { launch_advance(h->d_dt, dt, h->stream); });
   h->step += 1;
@@ -334,10 +355,12 @@ int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used) {
 int grmhd_cons2prim(grmhd_grid* h, int64_t* n_fail, int strict) {
   int rc = ready(h);
   if (rc) return rc;
+  rc = mlp_ready(h);
+  if (rc) return rc;
   if (strict && !n_fail) return fail(GRMHD_EINVAL, "strict mode needs n_fail");
   const C2PParams cp = c2p_params(h->desc);
   h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
-  h->timed(9, [&] { launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, h->stream, nullptr); });
+  c2p_with_guess(h, cp);
   rc = hip_check("cons2prim");
   if (rc) return rc;
   if (n_fail) {
@@ -405,6 +428,127 @@ int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out) {
   return GRMHD_OK;
 }
 
+static int mlp_alloc(grmhd_grid* h) {
+  if (h->mlp_alloc) return GRMHD_OK;
+  MlpState& M = h->mlp;
+  hipError_t e = hipMalloc(&M.wb, NPARAM * sizeof(unsigned short));
+  if (e == hipSuccess) e = hipMalloc(&M.wf, NPARAM * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&M.norm, mlp::NNORM * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&M.m1, NPARAM * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&M.m2, NPARAM * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&M.part, (size_t)MLP_MAX_WAVES * NPARAM * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&M.part_loss, MLP_MAX_WAVES * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&M.loss, sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&M.dpart, 256 * 32 * sizeof(double));
+  if (e == hipSuccess) e = hipMemsetAsync(M.m1, 0, NPARAM * sizeof(float), h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(M.m2, 0, NPARAM * sizeof(float), h->stream);
+  if (e != hipSuccess) return fail(GRMHD_ENOMEM, std::string("learned-guess buffers: ") + hipGetErrorString(e));
+  h->mlp_alloc = true;
+  return GRMHD_OK;
+}
+
+int grmhd_mlp_set_weights(grmhd_grid* h, const float* host_params, size_t n_params,
+                          const float* host_norm, size_t n_norm) {
+  if (!h || !host_params || !host_norm) return fail(GRMHD_EINVAL, "NULL argument");
+  if (n_params != (size_t)NPARAM || n_norm != (size_t)mlp::NNORM)
+    return fail(GRMHD_EINVAL, "parameter or normalisation size mismatch");
+  for (size_t q = 0; q < n_params; ++q)
+    if (!std::isfinite(host_params[q])) return fail(GRMHD_EINVAL, "non-finite weight");
+  for (size_t q = 0; q < n_norm; ++q)
+    if (!std::isfinite(host_norm[q])) return fail(GRMHD_EINVAL, "non-finite normalisation");
+  int rc = mlp_alloc(h);
+  if (rc) return rc;
+  hipError_t e = hipMemcpy(h->mlp.wf, host_params, NPARAM * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->mlp.norm, host_norm, mlp::NNORM * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemsetAsync(h->mlp.m1, 0, NPARAM * sizeof(float), h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->mlp.m2, 0, NPARAM * sizeof(float), h->stream);
+  if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  mlp_launch_to_bf16(h->mlp, h->stream);
+  h->mlp.step = 0;
+  h->mlp.weights_set = true;
+  return hip_check("mlp_set_weights");
+}
+
+int grmhd_mlp_get_weights(grmhd_grid* h, float* host_params, float* host_norm) {
+  if (!h || !host_params || !host_norm) return fail(GRMHD_EINVAL, "NULL argument");
+  if (!h->mlp_alloc) return fail(GRMHD_ESTATE, "no learned-guess state");
+  hipError_t e = hipMemcpyAsync(host_params, h->mlp.wf, NPARAM * sizeof(float), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(host_norm, h->mlp.norm, mlp::NNORM * sizeof(float), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  return GRMHD_OK;
+}
+
+int grmhd_mlp_datagen(grmhd_grid* h, const double* prims, int64_t n, float* feat, float* targ,
+                      double* cons_out, int set_norm) {
+  if (!h || !prims || !feat || !targ || n <= 0) return fail(GRMHD_EINVAL, "bad argument");
+  int rc = mlp_alloc(h);
+  if (rc) return rc;
+  h->timed(15, [&] {
+    mlp_launch_datagen(prims, (long)n, h->desc.gamma_ad, feat, targ, cons_out, h->mlp.dpart,
+                       set_norm ? h->mlp.norm : nullptr, h->stream);
+  });
+  return hip_check("mlp_datagen");
+}
+
+int grmhd_cons2prim_points(grmhd_grid* h, const double* cons, int64_t n, const double* y0,
+                           double* prim_out, int32_t* iters_out) {
+  if (!h || !cons || !prim_out || n <= 0) return fail(GRMHD_EINVAL, "bad argument");
+  launch_points_c2p(cons, (long)n, h->desc.gamma_ad, y0, h->desc.newton_tol, h->desc.newton_maxit,
+                    prim_out, (int*)iters_out, h->stream);
+  return hip_check("cons2prim_points");
+}
+
+static int nwaves_for(int64_t n) {
+  const int64_t tiles = (n + 15) / 16;
+  return (int)(tiles < MLP_MAX_WAVES ? tiles : MLP_MAX_WAVES);
+}
+
+int grmhd_mlp_gradient(grmhd_grid* h, const float* feat, const float* targ, int64_t n,
+                       float* grad_host, double* loss_host) {
+  if (!h || !feat || !targ || !grad_host || n <= 0) return fail(GRMHD_EINVAL, "bad argument");
+  if (!h->mlp.weights_set) return fail(GRMHD_ESTATE, "weights not set");
+  const int nw = nwaves_for(n);
+  float* g = nullptr;
+  hipError_t e = hipMalloc(&g, NPARAM * sizeof(float));
+  if (e != hipSuccess) return fail(GRMHD_ENOMEM, hipGetErrorString(e));
+  mlp_launch_grad(h->mlp, feat, targ, (long)n, nw, h->stream);
+  mlp_launch_reduce(h->mlp, nw, 0, g, 0.f, 1, h->stream);
+  e = hipMemcpyAsync(grad_host, g, NPARAM * sizeof(float), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess && loss_host) e = hipMemcpyAsync(loss_host, h->mlp.loss, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(g);
+  if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  return hip_check("mlp_gradient");
+}
+
+int grmhd_mlp_train_step(grmhd_grid* h, const float* feat, const float* targ, int64_t batch,
+                         float lr, double* loss) {
+  if (!h || !feat || !targ || batch <= 0 || !(lr > 0.f)) return fail(GRMHD_EINVAL, "bad argument");
+  if (!h->mlp.weights_set) return fail(GRMHD_ESTATE, "weights not set");
+  const int nw = nwaves_for(batch);
+  h->mlp.step += 1;
+  h->timed(15, [&] {
+    mlp_launch_grad(h->mlp, feat, targ, (long)batch, nw, h->stream);
+    mlp_launch_reduce(h->mlp, nw, 1, nullptr, lr, h->mlp.step, h->stream);
+  });
+  int rc = hip_check("mlp_train_step");
+  if (rc) return rc;
+  if (loss) {
+    hipError_t e = hipMemcpyAsync(loss, h->mlp.loss, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_mlp_forward(grmhd_grid* h, const float* feat, int64_t n, float* out) {
+  if (!h || !feat || !out || n <= 0) return fail(GRMHD_EINVAL, "bad argument");
+  if (!h->mlp.weights_set) return fail(GRMHD_ESTATE, "weights not set");
+  mlp_launch_forward(h->mlp, feat, (long)n, out, h->stream);
+  return hip_check("mlp_forward");
+}
+
 int grmhd_set_profiling(grmhd_grid* h, int on) {
   if (!h) return fail(GRMHD_EINVAL, "grid handle is NULL");
   h->prof_on = on != 0;
@@ -443,6 +587,11 @@ void grmhd_destroy(grmhd_grid* h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
   for (auto& r : h->pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   for (auto ev : h->pool) (void)hipEventDestroy(ev);
+  if (h->mlp_alloc) {
+    (void)hipFree(h->mlp.wb); (void)hipFree(h->mlp.wf); (void)hipFree(h->mlp.norm);
+    (void)hipFree(h->mlp.m1); (void)hipFree(h->mlp.m2); (void)hipFree(h->mlp.part);
+    (void)hipFree(h->mlp.part_loss); (void)hipFree(h->mlp.loss); (void)hipFree(h->mlp.dpart);
+  }
   (void)hipFree(h->tab);
   (void)hipFree(h->d_dt);
   (void)hipFree(h->d_part);

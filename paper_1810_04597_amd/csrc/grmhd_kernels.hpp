@@ -15,7 +15,7 @@ struct C2PParams {
 };
 
 // Per-block partial results of the inversion (reduced on the device).
-constexpr int C2P_NSTAT = 8;   // fail, iters_sum, iters_max, floor_rho, floor_p, wcap, mlp_fallback, spare
+constexpr int C2P_NSTAT = 8;   // fail, iters_sum, iters_max, floor_rho, floor_p, wcap, learned fallback, spare
 constexpr int DIAG_NSUM = 8;   // plain sums of the 8 conserved fields
 constexpr int DIAG_NMAX = 8;   // max|divB|, -rho_min, rho_max, -p_min, p_max, w_max, max|B|, nonfinite
 
@@ -37,7 +37,7 @@ void launch_update(const Geom& G, bool flat, int mode, const double* prim, doubl
                    double* out, hipStream_t s);
 void launch_advance(double* d_dt, double dt_host, hipStream_t s);
 void launch_c2p(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
-                const double* tab, long long* stat_partials, hipStream_t s, const float* mlp);
+                const double* tab, long long* stat_partials, hipStream_t s, const double* y0_learned);
 void launch_prim2cons(const Geom& G, bool flat, double* prim, double* cons, const double* tab,
                       hipStream_t s);
 void launch_cfl(const Geom& G, bool flat, const double* prim, const double* tab, double cfl,

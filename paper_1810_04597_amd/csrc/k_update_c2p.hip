@@ -294,10 +294,11 @@ template <class MET>
 __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __restrict__ prim,
                                              double* __restrict__ cons,
                                              const double* __restrict__ tab,
-                                             long long* __restrict__ partials) {
+                                             long long* __restrict__ partials,
+                                             const double* __restrict__ y0_learned) {
   const long t = flat_thread();
   const bool live = t < (long)G.n[0] * G.n[1] * G.n[2];
-  long long st[6] = {0, 0, 0, 0, 0, 0};
+  long long st[7] = {0, 0, 0, 0, 0, 0, 0};
   if (live) {
     int i, j, k;
     zone_of(G, t, i, j, k);
@@ -313,17 +314,23 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
     double rho = prim[P_RHO * G.field + c];
     double p = prim[P_P * G.field + c];
     double u[3] = {prim[P_U1 * G.field + c], prim[P_U2 * G.field + c], prim[P_U3 * G.field + c]};
-    double y0;
-    if (cp.guess == 1) {
-      y0 = G.gam * (tau + dd);
-    } else {
+    double ywarm;
+    {
       double ul[3];
       m.lower(u, ul);
       const double uu = ul[0] * u[0] + ul[1] * u[1] + ul[2] * u[2];
       const double h = 1.0 + G.gam / (G.gam - 1.0) * p / rho;
-      y0 = rho * h * (1.0 + uu);
+      ywarm = rho * h * (1.0 + uu);
     }
-    const NewtonOut<double> r = newton<double>(dd, S, tau, B, m, G.gam, y0, cp.tol, cp.maxit);
+    const double y0 = cp.guess == 1 ? G.gam * (tau + dd) : (cp.guess == 2 ? y0_learned[c] : ywarm);
+    NewtonOut<double> r = newton<double>(dd, S, tau, B, m, G.gam, y0, cp.tol, cp.maxit);
+    if (cp.guess == 2 && !r.ok) {
+      // the learned guess did not lead to convergence: plain Newton from the warm guess
+      const int it0 = r.iters;
+      r = newton<double>(dd, S, tau, B, m, G.gam, ywarm, cp.tol, cp.maxit);
+      r.iters += it0;
+      st[6] = 1;
+    }
     if (r.ok) {
       rho = r.rho;
       p = r.p;
@@ -381,22 +388,20 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
       for (int q = 0; q < 5; ++q) cons[(long)q * G.field + c] = cc[q];
     }
   }
-  // per-block partials: fail, iters_sum, iters_max, floor_rho, floor_p, wcap
-  __shared__ long long sh[4][6];
+  // per-block partials: fail, iters_sum, iters_max, floor_rho, floor_p, wcap, learned fallback
+  __shared__ long long sh[4][7];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  long long r0 = wave_sum_ll(st[0]), r1 = wave_sum_ll(st[1]), r2 = wave_max_ll(st[2]);
-  long long r3 = wave_sum_ll(st[3]), r4 = wave_sum_ll(st[4]), r5 = wave_sum_ll(st[5]);
-  if (lane == 0) { sh[wv][0] = r0; sh[wv][1] = r1; sh[wv][2] = r2; sh[wv][3] = r3; sh[wv][4] = r4; sh[wv][5] = r5; }
+  long long rr[7];
+  for (int q = 0; q < 7; ++q) rr[q] = q == 2 ? wave_max_ll(st[q]) : wave_sum_ll(st[q]);
+  if (lane == 0)
+    for (int q = 0; q < 7; ++q) sh[wv][q] = rr[q];
   __syncthreads();
   if (threadIdx.x == 0) {
-    long long o[6] = {0, 0, 0, 0, 0, 0};
-    for (int w = 0; w < 4; ++w) {
-      o[0] += sh[w][0]; o[1] += sh[w][1]; o[2] = sh[w][2] > o[2] ? sh[w][2] : o[2];
-      o[3] += sh[w][3]; o[4] += sh[w][4]; o[5] += sh[w][5];
-    }
+    long long o[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int w = 0; w < 4; ++w)
+      for (int q = 0; q < 7; ++q) o[q] = q == 2 ? (sh[w][q] > o[q] ? sh[w][q] : o[q]) : o[q] + sh[w][q];
     long long* dst = partials + (long)blockIdx.x * C2P_NSTAT;
-    for (int q = 0; q < 6; ++q) dst[q] = o[q];
-    dst[6] = 0;
+    for (int q = 0; q < 7; ++q) dst[q] = o[q];
     dst[7] = 0;
   }
 }
@@ -736,12 +741,14 @@ void launch_advance(double* d_dt, double dt_host, hipStream_t s) {
 }
 
 void launch_c2p(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
-                const double* tab, long long* partials, hipStream_t s, const float*) {
+                const double* tab, long long* partials, hipStream_t s, const double* y0_learned) {
   const unsigned nb = zone_blocks(G);
   if (flat)
-    hipLaunchKernelGGL(k_c2p<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab, partials);
+    hipLaunchKernelGGL(k_c2p<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab,
+                       partials, y0_learned);
   else
-    hipLaunchKernelGGL(k_c2p<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab, partials);
+    hipLaunchKernelGGL(k_c2p<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab,
+                       partials, y0_learned);
 }
 
 void launch_reduce_stats(const long long* partials, int nb, long long* out, hipStream_t s) {

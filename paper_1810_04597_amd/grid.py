@@ -111,6 +111,71 @@ class Grid:
         L.check(self.lib.grmhd_diagnostics(self.h, C.byref(d)))
         return d.as_dict()
 
+    # ------------------------------------------------------------ learned guess
+    def mlp_set_weights(self, flat, norm):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        norm = np.ascontiguousarray(norm, dtype=np.float32)
+        Fp = C.POINTER(C.c_float)
+        L.check(self.lib.grmhd_mlp_set_weights(self.h, flat.ctypes.data_as(Fp), flat.size,
+                                               norm.ctypes.data_as(Fp), norm.size))
+
+    def mlp_get_weights(self):
+        flat = np.zeros(L.MLP_NPARAM, dtype=np.float32)
+        norm = np.zeros(L.MLP_NNORM, dtype=np.float32)
+        Fp = C.POINTER(C.c_float)
+        L.check(self.lib.grmhd_mlp_get_weights(self.h, flat.ctypes.data_as(Fp), norm.ctypes.data_as(Fp)))
+        return flat, norm
+
+    def mlp_datagen(self, prims, set_norm=False, want_cons=False):
+        """prims: (n, 8) float64 array (host or device) -> (features, targets)
+        device float32 tensors (n, 8) [, cons (n, 8) float64]."""
+        pr = torch.as_tensor(np.ascontiguousarray(prims, dtype=np.float64) if isinstance(prims, np.ndarray) else prims,
+                             dtype=torch.float64).to(self.device).contiguous()
+        n = pr.shape[0]
+        feat = torch.empty((n, 8), dtype=torch.float32, device=self.device)
+        targ = torch.empty((n, 8), dtype=torch.float32, device=self.device)
+        cons = torch.empty((n, 8), dtype=torch.float64, device=self.device) if want_cons else None
+        L.check(self.lib.grmhd_mlp_datagen(self.h, C.c_void_p(pr.data_ptr()), n,
+                                           C.c_void_p(feat.data_ptr()), C.c_void_p(targ.data_ptr()),
+                                           C.c_void_p(cons.data_ptr()) if want_cons else None,
+                                           1 if set_norm else 0))
+        self.synchronize()
+        return (feat, targ, cons) if want_cons else (feat, targ)
+
+    def cons2prim_points(self, cons, y0=None):
+        """Batched point-wise inversion (flat frame): cons (n, 8) device float64;
+        y0 (n,) device float64 or None (cold start).  -> (prims (n, 8), iterations)."""
+        n = cons.shape[0]
+        prim = torch.empty((n, 8), dtype=torch.float64, device=self.device)
+        it = torch.empty((n,), dtype=torch.int32, device=self.device)
+        L.check(self.lib.grmhd_cons2prim_points(self.h, C.c_void_p(cons.data_ptr()), n,
+                                                C.c_void_p(y0.data_ptr()) if y0 is not None else None,
+                                                C.c_void_p(prim.data_ptr()), C.c_void_p(it.data_ptr())))
+        self.synchronize()
+        return prim, it
+
+    def mlp_gradient(self, feat, targ):
+        g = np.zeros(L.MLP_NPARAM, dtype=np.float32)
+        loss = C.c_double(0.0)
+        L.check(self.lib.grmhd_mlp_gradient(self.h, C.c_void_p(feat.data_ptr()), C.c_void_p(targ.data_ptr()),
+                                            feat.shape[0], g.ctypes.data_as(C.POINTER(C.c_float)),
+                                            C.byref(loss)))
+        return g, loss.value
+
+    def mlp_train_step(self, feat, targ, lr, want_loss=False):
+        loss = C.c_double(0.0)
+        L.check(self.lib.grmhd_mlp_train_step(self.h, C.c_void_p(feat.data_ptr()), C.c_void_p(targ.data_ptr()),
+                                              feat.shape[0], C.c_float(lr),
+                                              C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def mlp_forward(self, feat):
+        out = torch.empty((feat.shape[0], 8), dtype=torch.float32, device=self.device)
+        L.check(self.lib.grmhd_mlp_forward(self.h, C.c_void_p(feat.data_ptr()), feat.shape[0],
+                                           C.c_void_p(out.data_ptr())))
+        self.synchronize()
+        return out
+
     def set_profiling(self, on=True):
         L.check(self.lib.grmhd_set_profiling(self.h, 1 if on else 0))
 
