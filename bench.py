@@ -275,6 +275,9 @@ def learned_report(args):
     print(json.dumps(out))
 
 
+CALIB_COPY_BYTES = 1 << 30
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +286,9 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, one plain device copy of CALIB_COPY_BYTES "
+                         "(reference for scaling the HBM traffic counters)")
     ap.add_argument("--profile-kernels", action="store_true", default=True)
     ap.add_argument("--mode", default="step", choices=["step", "precision", "learned", "torus"],
                     help="step: the FP64 RK3 step (default); precision: FP32-flux form "
@@ -341,6 +347,13 @@ def main():
     ms = ev0.elapsed_time(ev1)
     prof = G.profile(reset=True) if args.profile_kernels else {}
     diag = G.diagnostics()
+    if args.calib_copy:
+        src = torch.ones(CALIB_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     zones = n ** 3
     value = zones * args.steps / (ms / 1e3)
     # dominant kernel class

@@ -154,9 +154,15 @@ int grmhd_prim2cons(grmhd_grid* h);
 int grmhd_rhs(grmhd_grid* h, double* rhs_out);
 
 /* One SSP-RK3 step of the bound state.  dt > 0: that step; dt <= 0: the CFL
- * step dt = cfl / max sum_d max|lambda_d|/dx_d computed on the device from
- * the primitives at the start of the step (no host sync).  dt_used (nullable)
- * receives the step taken (synchronises). */
+ * step dt = cfl / max sum_d max|lambda_d|/dx_d of the primitives at the
+ * start of the step, on the device (no host sync).  A step taken with
+ * dt <= 0 also reduces that value for the state it leaves (inside its last
+ * inversion), and the next dt <= 0 step reuses it; grmhd_compute_dt does the
+ * same.  bind_fields, set_metric, curl_potential, prim2cons and cons2prim
+ * drop the stored value; a caller that writes the bound prim/cons directly
+ * calls one of the latter two before stepping, as the state must be made
+ * consistent anyway.  dt_used (nullable) receives the step taken
+ * (synchronises). */
 int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used);
 
 /* Inversion of the bound cons into the bound prim at interior cells (warm,
@@ -166,7 +172,8 @@ int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used);
  * failed (requires n_fail). */
 int grmhd_cons2prim(grmhd_grid* h, int64_t* n_fail, int strict);
 
-/* CFL time step of the bound primitives (synchronises). */
+/* CFL time step of the bound primitives (synchronises); a following
+ * rk_step with dt <= 0 takes this step. */
 int grmhd_compute_dt(grmhd_grid* h, double* dt);
 
 /* Diagnostics of the bound state (synchronises).  Sums are taken in a fixed

@@ -1,7 +1,7 @@
 """Finite-difference operators on a staggered grid (oracle, FP64).
 
-Paper, Introduction: the equations are solved "using 3D finite-differences".
-The ECHO family writes the flux derivative as a plain difference of
+Paper, Introduction: the equations are discretised with finite differences
+in three dimensions.  The ECHO family writes the flux derivative as a plain difference of
 high-order corrected face fluxes, f_hat = f - Delta^2 f / 24 + 3 Delta^4 f / 640;
 expanded, that is the sixth-order staggered derivative below.  Its companion
 I_d interpolates face values to the cell centre to sixth order.

@@ -1,7 +1,7 @@
 """MP5 reconstruction (oracle, FP64).
 
-Paper, Introduction: "high-order reconstruction algorithms".  The scheme
-family's fifth-order choice is the monotonicity-preserving MP5 limiter of
+Paper, Introduction: the scheme reconstructs interface values to high
+order.  The scheme family's fifth-order choice is the monotonicity-preserving MP5 limiter of
 Suresh & Huynh (1997).  Two readings apply (both listed with the other
 readings of the paper):
   * the unlimited value is the degree-4 Lagrange interpolant of the point

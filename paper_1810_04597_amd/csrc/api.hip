@@ -58,7 +58,8 @@ struct grmhd_grid {
   bool flat = true;
   bool metric_set = false;
   // library-owned device buffers
-  double* d_dt = nullptr;        // [0] dt of the current step, [1] time
+  double* d_dt = nullptr;        // [0] dt of the current step, [1] time, [2] CFL dt of the state
+  bool next_dt_valid = false;    // d_dt[2] holds the CFL dt of the current primitives
   double* d_part = nullptr;      // per-block partials (cfl, diagnostics)
   long long* d_spart = nullptr;  // per-block inversion statistics
   long long* d_stats = nullptr;  // reduced inversion statistics (8)
@@ -200,12 +201,12 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** 
   h->nblk = zone_blocks(h->G);
   const size_t part = (size_t)h->nblk * (DIAG_NSUM + DIAG_NMAX) * sizeof(double);
   hipError_t e = hipSuccess;
-  e = hipMalloc(&h->d_dt, 2 * sizeof(double));
+  e = hipMalloc(&h->d_dt, 3 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&h->d_part, part);
   if (e == hipSuccess) e = hipMalloc(&h->d_spart, (size_t)h->nblk * C2P_NSTAT * sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&h->d_stats, C2P_NSTAT * sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&h->d_diag, (DIAG_NSUM + DIAG_NMAX) * sizeof(double));
-  if (e == hipSuccess) e = hipMemsetAsync(h->d_dt, 0, 2 * sizeof(double), h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->d_dt, 0, 3 * sizeof(double), h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->d_stats, 0, C2P_NSTAT * sizeof(long long), h->stream);
   if (e != hipSuccess) {
     std::string m = std::string("device buffers: ") + hipGetErrorString(e);
@@ -232,11 +233,13 @@ int grmhd_bind_fields(grmhd_grid* h, double* prim, double* cons, void* scratch,
   h->prim = prim;
   h->cons = cons;
   h->scratch = (double*)scratch;
+  h->next_dt_valid = false;
   return GRMHD_OK;
 }
 
 int grmhd_set_metric(grmhd_grid* h, int kind, const double* host_tables, size_t n_doubles) {
   if (!h) return fail(GRMHD_EINVAL, "grid handle is NULL");
+  h->next_dt_valid = false;
   if (kind == GRMHD_METRIC_MINKOWSKI) {
     if (h->desc.coord != GRMHD_CART) return fail(GRMHD_EINVAL, "Minkowski kind needs Cartesian coordinates");
     if (h->tab) { (void)hipFree(h->tab); h->tab = nullptr; }
@@ -265,6 +268,7 @@ int grmhd_curl_potential(grmhd_grid* h, const double* A1, const double* A2, cons
   int rc = ready(h);
   if (rc) return rc;
   if (!A1 || !A2 || !A3) return fail(GRMHD_EINVAL, "NULL potential");
+  h->next_dt_valid = false;
   h->timed(15, [&] { launch_curl(h->G, A1, A2, A3, h->cons, h->stream); });
   h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
   return hip_check("curl_potential");
@@ -273,6 +277,7 @@ int grmhd_curl_potential(grmhd_grid* h, const double* A1, const double* A2, cons
 int grmhd_prim2cons(grmhd_grid* h) {
   int rc = ready(h);
   if (rc) return rc;
+  h->next_dt_valid = false;
   h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
   h->timed(15, [&] { launch_prim2cons(h->G, h->flat, h->prim, h->cons, h->tab, h->stream); });
   h->timed(0, [&] { launch_bc_centred(h->G, h->bc, h->prim, NPRIM, h->stream); });
@@ -290,13 +295,17 @@ static void rhs_pieces(grmhd_grid* h) {
     h->timed(4 + e, [&] { launch_edge(e, h->G, h->flat, fp32, h->cons, h->tab, h->ctd(), h->edges(), h->stream); });
 }
 
-static void c2p_with_guess(grmhd_grid* h, const C2PParams& cp) {
+// with_cfl: also reduce the CFL time step of the inverted state into d_dt[2]
+static void c2p_with_guess(grmhd_grid* h, const C2PParams& cp, bool with_cfl = false) {
   const double* y0 = nullptr;
   if (cp.guess == GRMHD_GUESS_MLP) {
     h->timed(14, [&] { mlp_launch_guess(h->G, h->flat, h->cons, h->tab, h->mlp, h->guess(), h->stream); });
     y0 = h->guess();
   }
-  h->timed(9, [&] { launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, h->stream, y0); });
+  h->timed(9, [&] {
+    launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, h->stream, y0,
+               with_cfl ? h->d_part : nullptr, h->desc.cfl, h->d_dt + 2);
+  });
 }
 
 static int mlp_ready(grmhd_grid* h) {
@@ -312,7 +321,7 @@ int grmhd_rhs(grmhd_grid* h, double* rhs_out) {
   rhs_pieces(h);
   h->timed(13, [&] {
     launch_update(h->G, h->flat, 1, h->prim, h->cons, h->cons_n(), h->flux(), h->edges(), h->tab,
-                  0.0, 0.0, 0.0, h->d_dt, rhs_out, h->stream);
+                  0.0, 0.0, 0.0, h->d_dt, rhs_out, 0, h->stream);
   });
   return hip_check("rhs");
 }
@@ -323,29 +332,34 @@ int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used) {
   rc = mlp_ready(h);
   if (rc) return rc;
   if (!std::isfinite(dt)) return fail(GRMHD_EINVAL, "dt not finite");
-  if (dt <= 0.0)
-    h->timed(10, [&] { launch_cfl(h->G, h->flat, h->prim, h->tab, h->desc.cfl, h->d_part, h->d_dt, h->stream); });
-  const long field_bytes = (long)h->G.field * (long)sizeof(double);
-  hipError_t e = hipSuccess;
-  h->timed(11, [&] { e = hipMemcpyAsync(h->cons_n(), h->cons, NCONS * field_bytes, hipMemcpyDeviceToDevice, h->stream); });
-  if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  // Device time step: the CFL dt of the current primitives.  When the last
+  // state change was a step taken in this mode, its final inversion already
+  // reduced that value into d_dt[2]; otherwise it is reduced here.
+  const bool device_dt = dt <= 0.0;
+  const double* dt_src = h->d_dt + 2;
+  if (device_dt && !h->next_dt_valid)
+    h->timed(10, [&] { launch_cfl(h->G, h->flat, h->prim, h->tab, h->desc.cfl, h->d_part, h->d_dt + 2, h->stream); });
+  h->next_dt_valid = false;
+  // U^n is saved by the first stage's update (a = 0, so U^(1) needs only U^n).
   const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
   const C2PParams cp = c2p_params(h->desc);
   for (int s = 0; s < 3; ++s) {
     rhs_pieces(h);
     h->timed(7, [&] {
       launch_update(h->G, h->flat, 0, h->prim, h->cons, h->cons_n(), h->flux(), h->edges(), h->tab,
-                    A[s], B[s], dt, h->d_dt, nullptr, h->stream);
+                    A[s], B[s], dt, dt_src, nullptr, s == 0 ? 1 : 0, h->stream);
     });
+    // dt and time are recorded once the last update has consumed d_dt[2]
+    if (s == 2) h->timed(12, [&] { launch_advance(h->d_dt, dt_src, dt, h->stream); });
     h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
-    c2p_with_guess(h, cp);
+    c2p_with_guess(h, cp, s == 2 && device_dt);
   }
-  h->timed(12, [&] { launch_advance(h->d_dt, dt, h->stream); });
   h->step += 1;
   rc = hip_check("rk_step");
   if (rc) return rc;
+  h->next_dt_valid = device_dt;
   if (dt_used) {
-    e = hipMemcpyAsync(dt_used, h->d_dt, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    hipError_t e = hipMemcpyAsync(dt_used, h->d_dt, sizeof(double), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
   }
@@ -358,6 +372,7 @@ int grmhd_cons2prim(grmhd_grid* h, int64_t* n_fail, int strict) {
   rc = mlp_ready(h);
   if (rc) return rc;
   if (strict && !n_fail) return fail(GRMHD_EINVAL, "strict mode needs n_fail");
+  h->next_dt_valid = false;
   const C2PParams cp = c2p_params(h->desc);
   h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
   c2p_with_guess(h, cp);
@@ -379,8 +394,9 @@ int grmhd_compute_dt(grmhd_grid* h, double* dt) {
   int rc = ready(h);
   if (rc) return rc;
   if (!dt) return fail(GRMHD_EINVAL, "dt is NULL");
-  launch_cfl(h->G, h->flat, h->prim, h->tab, h->desc.cfl, h->d_part, h->d_dt, h->stream);
-  hipError_t e = hipMemcpyAsync(dt, h->d_dt, sizeof(double), hipMemcpyDeviceToHost, h->stream);
+  h->timed(10, [&] { launch_cfl(h->G, h->flat, h->prim, h->tab, h->desc.cfl, h->d_part, h->d_dt + 2, h->stream); });
+  h->next_dt_valid = true;
+  hipError_t e = hipMemcpyAsync(dt, h->d_dt + 2, sizeof(double), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
   return hip_check("compute_dt");

@@ -32,12 +32,13 @@ void launch_edge(int e, const Geom& G, bool flat, bool fp32, const double* cons,
 // mode 0: RK combine into cons (needs cons_n, a, b, dt on device);
 // mode 1: write L into out (cons layout).
 void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* cons,
-                   const double* cons_n, const double* flux, const double* edges,
+                   double* cons_n, const double* flux, const double* edges,
                    const double* tab, double a, double b, double dt_host, const double* d_dt,
-                   double* out, hipStream_t s);
-void launch_advance(double* d_dt, double dt_host, hipStream_t s);
+                   double* out, int save_n, hipStream_t s);
+void launch_advance(double* d_dt, const double* src, double dt_host, hipStream_t s);
 void launch_c2p(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
-                const double* tab, long long* stat_partials, hipStream_t s, const double* y0_learned);
+                const double* tab, long long* stat_partials, hipStream_t s, const double* y0_learned,
+                double* cfl_partials = nullptr, double cfl = 0.0, double* d_next_dt = nullptr);
 void launch_prim2cons(const Geom& G, bool flat, double* prim, double* cons, const double* tab,
                       hipStream_t s);
 void launch_cfl(const Geom& G, bool flat, const double* prim, const double* tab, double cfl,

@@ -107,12 +107,12 @@ __device__ __forceinline__ void sources_of(const PState<double>& s, const MET& m
 template <class MET>
 __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* __restrict__ prim,
                                                 double* __restrict__ cons,
-                                                const double* __restrict__ cons_n,
+                                                double* __restrict__ cons_n,
                                                 const double* __restrict__ flux,
                                                 const double* __restrict__ edges,
                                                 const double* __restrict__ tab, double a, double b,
                                                 double dt_host, const double* __restrict__ d_dt,
-                                                double* __restrict__ out) {
+                                                double* __restrict__ out, int save_n) {
   const long t = flat_thread();
   if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
   int i, j, k;
@@ -148,9 +148,12 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
     }
     L = L + src[q];
     const long o = (long)q * G.field + c;
-    if (mode == 0)
-      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
-    else
+    if (mode == 0) {
+      const double old = cons[o];
+      const double un = save_n ? old : cons_n[o];
+      if (save_n) cons_n[o] = old;
+      cons[o] = a * un + b * (old + dt * L);
+    } else
       out[o] = L;
   }
 #pragma unroll
@@ -167,11 +170,23 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
     const double t2 = fd_deriv(f, 1.0 / G.dx[d2]);
     const double L = -t1 + t2;
     const long o = (long)(C_BF1 + nd) * G.field + c;
-    if (mode == 0)
-      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
-    else
+    if (mode == 0) {
+      const double old = cons[o];
+      const double un = save_n ? old : cons_n[o];
+      if (save_n) cons_n[o] = old;
+      cons[o] = a * un + b * (old + dt * L);
+    } else
       out[o] = L;
   }
+}
+
+// RK stage store; save_n (first stage, a = 0): U^n is this value, saved
+__device__ __forceinline__ void rk_store(double* __restrict__ cons, double* __restrict__ cons_n, long o,
+                                         double a, double b, double dt, double L, int save_n) {
+  const double old = cons[o];
+  const double un = save_n ? old : cons_n[o];
+  if (save_n) cons_n[o] = old;
+  cons[o] = a * un + b * (old + dt * L);
 }
 
 // z-marching variant (flat metric): one thread per (i, j) column segment of
@@ -183,12 +198,12 @@ constexpr int KZ = 16;
 template <class MET>
 __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restrict__ prim,
                                                    double* __restrict__ cons,
-                                                   const double* __restrict__ cons_n,
+                                                   double* __restrict__ cons_n,
                                                    const double* __restrict__ flux,
                                                    const double* __restrict__ edges,
                                                    const double* __restrict__ tab, double a,
                                                    double b, double dt_host,
-                                                   const double* __restrict__ d_dt) {
+                                                   const double* __restrict__ d_dt, int save_n) {
   const long t = flat_thread();
   const int nseg = (G.n[2] + KZ - 1) / KZ;
   if (t >= (long)G.n[0] * G.n[1] * nseg) return;
@@ -234,24 +249,21 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
       for (int s = 0; s < 6; ++s) f[s] = fy[(s - 3) * sy];
       L = L - fd_deriv(f, idx1);
       L = L - fd_deriv(wf[q], idx2);
-      const long o = (long)q * G.field + c;
-      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
+      rk_store(cons, cons_n, (long)q * G.field + c, a, b, dt, L, save_n);
     }
     // B^1: -D_2 E_3 + D_3 E_2
     {
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sy];
       const double L = -fd_deriv(f, idx1) + fd_deriv(w2, idx2);
-      const long o = (long)C_BF1 * G.field + c;
-      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
+      rk_store(cons, cons_n, (long)C_BF1 * G.field + c, a, b, dt, L, save_n);
     }
     // B^2: -D_3 E_1 + D_1 E_3
     {
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sx];
       const double L = -fd_deriv(w1, idx2) + fd_deriv(f, idx0);
-      const long o = (long)C_BF2 * G.field + c;
-      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
+      rk_store(cons, cons_n, (long)C_BF2 * G.field + c, a, b, dt, L, save_n);
     }
     // B^3: -D_1 E_2 + D_2 E_1
     {
@@ -262,8 +274,7 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
         g2[s] = e1[c + (s - 3) * sy];
       }
       const double L = -fd_deriv(f, idx0) + fd_deriv(g2, idx1);
-      const long o = (long)C_BF3 * G.field + c;
-      cons[o] = a * cons_n[o] + b * (cons[o] + dt * L);
+      rk_store(cons, cons_n, (long)C_BF3 * G.field + c, a, b, dt, L, save_n);
     }
 #pragma unroll
     for (int s = 0; s < 5; ++s) {
@@ -295,10 +306,12 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
                                              double* __restrict__ cons,
                                              const double* __restrict__ tab,
                                              long long* __restrict__ partials,
-                                             const double* __restrict__ y0_learned) {
+                                             const double* __restrict__ y0_learned,
+                                             double* __restrict__ cfl_partials) {
   const long t = flat_thread();
   const bool live = t < (long)G.n[0] * G.n[1] * G.n[2];
   long long st[7] = {0, 0, 0, 0, 0, 0, 0};
+  double cfl_v = 0.0;
   if (live) {
     int i, j, k;
     zone_of(G, t, i, j, k);
@@ -378,15 +391,33 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
     prim[P_B1 * G.field + c] = B[0];
     prim[P_B2 * G.field + c] = B[1];
     prim[P_B3 * G.field + c] = B[2];
-    if (floored) {
+    if (floored || cfl_partials) {
       PState<double> s;
       s.rho = rho; s.p = p;
       for (int q = 0; q < 3; ++q) { s.u[q] = u[q]; s.B[q] = B[q]; }
       make_state(s, m, G.gam);
-      double cc[5];
-      cons_of(s, m, cc);
-      for (int q = 0; q < 5; ++q) cons[(long)q * G.field + c] = cc[q];
+      if (floored) {
+        double cc[5];
+        cons_of(s, m, cc);
+        for (int q = 0; q < 5; ++q) cons[(long)q * G.field + c] = cc[q];
+      }
+      if (cfl_partials) {
+        double tot = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          double lp, lm;
+          speeds_of(s, m, d, G.gam, lp, lm);
+          tot = tot + fmax(fabs(lp), fabs(lm)) / G.dx[d];
+        }
+        cfl_v = tot;
+      }
     }
+  }
+  if (cfl_partials) {
+    __shared__ double shc[4];
+    const double w = wave_max(cfl_v);
+    if ((threadIdx.x & 63) == 0) shc[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) cfl_partials[blockIdx.x] = fmax(fmax(shc[0], shc[1]), fmax(shc[2], shc[3]));
   }
   // per-block partials: fail, iters_sum, iters_max, floor_rho, floor_p, wcap, learned fallback
   __shared__ long long sh[4][7];
@@ -570,16 +601,64 @@ __device__ __forceinline__ GhostSrc ghost_src(const Geom& G, const BCSpec& bc, i
   return s;
 }
 
+// Enumerates exactly the ghost elements: slabs of ghost x^3 planes, then
+// ghost x^2 rows of interior planes, then ghost x^1 cells of interior rows;
+// with an axis boundary, the axis faces j = n2-1 of interior cells follow
+// (face fields only).
+__device__ __forceinline__ bool ghost_index(const Geom& G, long t, bool axis_row, int& i, int& j,
+                                            int& k) {
+  const long d0 = G.dims[0], d1 = G.dims[1];
+  const long NA = 2L * NG * d1 * d0;
+  const long NB = (long)G.n[2] * 2 * NG * d0;
+  const long NC = (long)G.n[2] * G.n[1] * 2 * NG;
+  const long ND = axis_row ? (long)G.n[2] * G.n[0] : 0;
+  if (t < NA) {
+    const int kl = (int)(t / (d1 * d0));
+    const long r = t % (d1 * d0);
+    k = kl < NG ? kl - NG : G.n[2] + kl - NG;
+    j = (int)(r / d0) - NG;
+    i = (int)(r % d0) - NG;
+    return true;
+  }
+  t -= NA;
+  if (t < NB) {
+    k = (int)(t / (2 * NG * d0));
+    const long r = t % (2 * NG * d0);
+    const int jl = (int)(r / d0);
+    j = jl < NG ? jl - NG : G.n[1] + jl - NG;
+    i = (int)(r % d0) - NG;
+    return true;
+  }
+  t -= NB;
+  if (t < NC) {
+    k = (int)(t / ((long)G.n[1] * 2 * NG));
+    const long r = t % ((long)G.n[1] * 2 * NG);
+    j = (int)(r / (2 * NG));
+    const int il = (int)(r % (2 * NG));
+    i = il < NG ? il - NG : G.n[0] + il - NG;
+    return true;
+  }
+  t -= NC;
+  if (t < ND) {
+    k = (int)(t / G.n[0]);
+    i = (int)(t % G.n[0]);
+    j = G.n[1] - 1;
+    return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ long ghost_total(const Geom& G, bool axis_row) {
+  const long d0 = G.dims[0], d1 = G.dims[1];
+  return 2L * NG * d1 * d0 + (long)G.n[2] * 2 * NG * d0 + (long)G.n[2] * G.n[1] * 2 * NG +
+         (axis_row ? (long)G.n[2] * G.n[0] : 0);
+}
+
 __global__ __launch_bounds__(256) void k_bc_centred(Geom G, BCSpec bc, double* __restrict__ prim,
                                                     int nfields) {
   const long t = flat_thread();
-  if (t >= (long)G.dims[0] * G.dims[1] * G.dims[2]) return;
-  const int i = (int)(t % G.dims[0]) - NG;
-  const long r = t / G.dims[0];
-  const int j = (int)(r % G.dims[1]) - NG;
-  const int k = (int)(r / G.dims[1]) - NG;
-  const bool inside = i >= 0 && i < G.n[0] && j >= 0 && j < G.n[1] && k >= 0 && k < G.n[2];
-  if (inside) return;
+  int i, j, k;
+  if (t >= ghost_total(G, false) || !ghost_index(G, t, false, i, j, k)) return;
   const long dst = G.idx(i, j, k);
   for (int f = 0; f < nfields; ++f) {
     const bool flip = (f == P_U2 || f == P_U3 || f == P_B2 || f == P_B3);
@@ -592,13 +671,11 @@ __global__ __launch_bounds__(256) void k_bc_centred(Geom G, BCSpec bc, double* _
 
 __global__ __launch_bounds__(256) void k_bc_faces(Geom G, BCSpec bc, double* __restrict__ cons) {
   const long t = flat_thread();
-  if (t >= (long)G.dims[0] * G.dims[1] * G.dims[2]) return;
-  const int i = (int)(t % G.dims[0]) - NG;
-  const long r = t / G.dims[0];
-  const int j = (int)(r % G.dims[1]) - NG;
-  const int k = (int)(r / G.dims[1]) - NG;
+  const bool axis = bc.bc[2] == 2;
+  int i, j, k;
+  if (t >= ghost_total(G, axis) || !ghost_index(G, t, axis, i, j, k)) return;
   const bool inside = i >= 0 && i < G.n[0] && j >= 0 && j < G.n[1] && k >= 0 && k < G.n[2];
-  const bool axis_face = bc.bc[2] == 2 && (j == -1 || j == G.n[1] - 1);
+  const bool axis_face = axis && (j == -1 || j == G.n[1] - 1);
   const long dst = G.idx(i, j, k);
   for (int nd = 0; nd < 3; ++nd) {
     if (inside && !(nd == 1 && axis_face)) continue;
@@ -699,56 +776,63 @@ __global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ p
 // ------------------------------------------------------------------ launchers
 unsigned zone_blocks(const Geom& G) { return nblk((long)G.n[0] * G.n[1] * G.n[2]); }
 
+static long ghost_count(const Geom& G, bool axis_row) {
+  const long d0 = G.dims[0], d1 = G.dims[1];
+  return 2L * NG * d1 * d0 + (long)G.n[2] * 2 * NG * d0 + (long)G.n[2] * G.n[1] * 2 * NG +
+         (axis_row ? (long)G.n[2] * G.n[0] : 0);
+}
+
 void launch_bc_centred(const Geom& G, const BCSpec& bc, double* prim, int nfields, hipStream_t s) {
-  const long total = (long)G.dims[0] * G.dims[1] * G.dims[2];
-  hipLaunchKernelGGL(k_bc_centred, dim3(nblk(total)), dim3(256), 0, s, G, bc, prim, nfields);
+  hipLaunchKernelGGL(k_bc_centred, dim3(nblk(ghost_count(G, false))), dim3(256), 0, s, G, bc, prim, nfields);
 }
 
 void launch_bc_faces(const Geom& G, const BCSpec& bc, double* cons, hipStream_t s) {
-  const long total = (long)G.dims[0] * G.dims[1] * G.dims[2];
-  hipLaunchKernelGGL(k_bc_faces, dim3(nblk(total)), dim3(256), 0, s, G, bc, cons);
+  hipLaunchKernelGGL(k_bc_faces, dim3(nblk(ghost_count(G, bc.bc[2] == 2))), dim3(256), 0, s, G, bc, cons);
 }
 
 void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* cons,
-                   const double* cons_n, const double* flux, const double* edges,
+                   double* cons_n, const double* flux, const double* edges,
                    const double* tab, double a, double b, double dt_host, const double* d_dt,
-                   double* out, hipStream_t s) {
+                   double* out, int save_n, hipStream_t s) {
   const unsigned nb = zone_blocks(G);
   if (flat && mode == 0) {
     const long nseg = (G.n[2] + KZ - 1) / KZ;
     const long total = (long)G.n[0] * G.n[1] * nseg;
     hipLaunchKernelGGL(k_update_zm<FlatMet<double>>, dim3(nblk(total)), dim3(256), 0, s, G, prim,
-                       cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt);
+                       cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, save_n);
   } else if (flat)
     hipLaunchKernelGGL(k_update<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
-                       cons_n, flux, edges, tab, a, b, dt_host, d_dt, out);
+                       cons_n, flux, edges, tab, a, b, dt_host, d_dt, out, save_n);
   else
     hipLaunchKernelGGL(k_update<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
-                       cons_n, flux, edges, tab, a, b, dt_host, d_dt, out);
+                       cons_n, flux, edges, tab, a, b, dt_host, d_dt, out, save_n);
 }
 
-// d_dt[0]: dt of the last step, d_dt[1]: time
-__global__ void k_advance(double* __restrict__ d_dt, double dt_host) {
+// d_dt[0]: dt of the last step, d_dt[1]: time; src: where the device dt was read
+__global__ void k_advance(double* d_dt, const double* src, double dt_host) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const double dt = dt_host > 0.0 ? dt_host : d_dt[0];
+    const double dt = dt_host > 0.0 ? dt_host : src[0];
     d_dt[0] = dt;
     d_dt[1] = d_dt[1] + dt;
   }
 }
 
-void launch_advance(double* d_dt, double dt_host, hipStream_t s) {
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, d_dt, dt_host);
+void launch_advance(double* d_dt, const double* src, double dt_host, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, d_dt, src, dt_host);
 }
 
 void launch_c2p(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
-                const double* tab, long long* partials, hipStream_t s, const double* y0_learned) {
+                const double* tab, long long* partials, hipStream_t s, const double* y0_learned,
+                double* cfl_partials, double cfl, double* d_next_dt) {
   const unsigned nb = zone_blocks(G);
   if (flat)
     hipLaunchKernelGGL(k_c2p<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab,
-                       partials, y0_learned);
+                       partials, y0_learned, cfl_partials);
   else
     hipLaunchKernelGGL(k_c2p<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab,
-                       partials, y0_learned);
+                       partials, y0_learned, cfl_partials);
+  if (cfl_partials)
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, cfl_partials, (int)nb, cfl, d_next_dt);
 }
 
 void launch_reduce_stats(const long long* partials, int nb, long long* out, hipStream_t s) {

@@ -1,11 +1,11 @@
 """Measured HBM traffic per kernel launch from two rocprofv3 counter passes.
 
-    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_f> -o run -- python bench.py ...
-    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_w> -o run -- python bench.py ...
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir_f> -o run -- python bench.py --calib-copy ...
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir_w> -o run -- python bench.py --calib-copy ...
     python -m paper_1810_04597_amd.traffic <dir_f> <dir_w>
 
-The counters (KiB per dispatch) are scaled by what they read for the stage
-copy of the RK3 step, a plain copy of known size (8 fields of the layout):
+The counters (KiB per dispatch) are scaled by what they read for the plain
+device copy of 1 GiB that bench.py --calib-copy runs after its steps:
 factor = known bytes / counter bytes, separately for FETCH and WRITE.
 Writes traffic.json with the hash of the kernel sources, so the benchmark
 reports the traffic only while the kernels are unchanged.
@@ -33,7 +33,7 @@ def source_hash():
 CLASS_OF = {"k_sweep<0": "sweep_x1", "k_sweep<1": "sweep_x2", "k_sweep<2": "sweep_x3",
             "k_edge<0": "edge_x1", "k_edge<1": "edge_x2", "k_edge<2": "edge_x3",
             "k_update": "update", "k_c2p": "cons2prim", "k_bc_centred": "bc_centred",
-            "k_bc_faces": "bc_faces", "k_cfl": "cfl", "__amd_rocclr_copyBuffer": "copy_stage"}
+            "k_bc_faces": "bc_faces", "k_cfl": "cfl", "__amd_rocclr_copyBuffer": "copy_calib"}
 
 
 def _read(d, counter):
@@ -53,15 +53,17 @@ def _read(d, counter):
     return out
 
 
-def main(dir_f, dir_w, field_doubles, nfields_copy=8):
+def main(dir_f, dir_w, copy_bytes=1 << 30):
     fetch = _read(dir_f, "FETCH_SIZE")
     write = _read(dir_w, "WRITE_SIZE")
-    known_kib = nfields_copy * field_doubles * 8 / 1024.0
+    known_kib = copy_bytes / 1024.0
     big = lambda lst: [v for g, v in lst if g == max(x for x, _ in lst)]
-    cf = known_kib / (sum(big(fetch["copy_stage"])) / len(big(fetch["copy_stage"])))
-    cw = known_kib / (sum(big(write["copy_stage"])) / len(big(write["copy_stage"])))
+    cf = known_kib / (sum(big(fetch["copy_calib"])) / len(big(fetch["copy_calib"])))
+    cw = known_kib / (sum(big(write["copy_calib"])) / len(big(write["copy_calib"])))
     res = {"source_hash": source_hash(), "fetch_scale": cf, "write_scale": cw, "kernels": {}}
     for cls in fetch:
+        if cls == "copy_calib":
+            continue
         fv = big(fetch[cls])
         wv = big(write.get(cls, [(0, 0.0)]))
         fb = sum(fv) / len(fv) * cf * 1024
@@ -73,4 +75,4 @@ def main(dir_f, dir_w, field_doubles, nfields_copy=8):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 19245632)
+    main(sys.argv[1], sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 1 << 30)

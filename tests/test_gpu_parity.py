@@ -151,3 +151,27 @@ def test_determinism_bitwise():
         outs.append(G.to_numpy("cons"))
     for k in CONS:
         assert np.array_equal(outs[0][k], outs[1][k], equal_nan=True), k
+
+
+@gpu
+def test_device_dt_follows_state_changes():
+    """A device-dt step stores the CFL step of the state it leaves; a new
+    state (curl_potential / set_primitives) drops it, and the next
+    device-dt step takes the CFL step of the new state."""
+    _torch()
+    from workloads import box
+    from oracle.scheme import Solver
+    g, d, s, G = _pair_box(16)
+    G.rk_step(0.0)
+    g2, d2 = box.turbulent_box(16, seed=7)
+    s2 = Solver(g2)
+    s2.curl_potential(d2)
+    s2.set_primitives(d2)
+    G.curl_potential(d2)
+    G.set_primitives(d2)
+    dt_g = G.rk_step(0.0, want_dt=True)
+    assert abs(dt_g / s2.cfl_dt() - 1) < 1e-13
+    # the stored value of the state just left is the CFL step of that state
+    dt_next = G.rk_step(0.0, want_dt=True)
+    s2.rk_step(s2.cfl_dt())
+    assert abs(dt_next / s2.cfl_dt() - 1) < 1e-11
