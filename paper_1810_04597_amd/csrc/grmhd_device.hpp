@@ -87,17 +87,24 @@ __device__ __forceinline__ long flat_thread() {
 #endif
 
 // ------------------------------------------------------------------ MP5
+// Word holding the sign bit (bit 31) of a float or double.
+GR_HD int sign_word(double a) { return (int)(__builtin_bit_cast(unsigned long long, a) >> 32); }
+GR_HD int sign_word(float a) { return __builtin_bit_cast(int, a); }
+
+// minmod(a, b) = (sgn a + sgn b)/2 min(|a|, |b|): zero unless the sign bits
+// agree, else the argument nearer zero.
 template <typename T>
 GR_HD T minmod(T a, T b) {
-  // (sgn a + sgn b)/2 * min(|a|, |b|)
-  return (a > T(0) && b > T(0)) ? fmin(a, b) : ((a < T(0) && b < T(0)) ? fmax(a, b) : T(0));
+  const T m = fabs(a) < fabs(b) ? a : b;
+  return (sign_word(a) ^ sign_word(b)) >= 0 ? m : T(0);
 }
 
+// Four-argument minmod: min |.| with the common sign, zero without one.
 template <typename T>
 GR_HD T minmod4(T w, T x, T y, T z) {
-  if (w > T(0) && x > T(0) && y > T(0) && z > T(0)) return fmin(fmin(w, x), fmin(y, z));
-  if (w < T(0) && x < T(0) && y < T(0) && z < T(0)) return fmax(fmax(w, x), fmax(y, z));
-  return T(0);
+  const int sw = sign_word(w), sx = sign_word(x), sy = sign_word(y), sz = sign_word(z);
+  const T m = fmin(fmin(fabs(w), fabs(x)), fmin(fabs(y), fabs(z)));
+  return (sw | sx | sy | sz) >= 0 ? m : ((sw & sx & sy & sz) < 0 ? -m : T(0));
 }
 
 // Limited left state at the face between q0 and qp1 from q_{j-2..j+2}.
@@ -116,7 +123,10 @@ GR_HD T mp5(T qm2, T qm1, T q0, T qp1, T qp2) {
   const T qlc = q0 + T(0.5) * (q0 - qm1) + T(4.0 / 3.0) * dm4m;
   const T qmin = fmax(fmin(fmin(q0, qp1), qmd), fmin(fmin(q0, qul), qlc));
   const T qmax = fmin(fmax(fmax(q0, qp1), qmd), fmax(fmax(q0, qul), qlc));
-  return ql + minmod(qmin - ql, qmax - ql);
+  // median(ql, qmin, qmax), written in the scheme as ql + minmod(qmin - ql,
+  // qmax - ql); both bounding intervals contain q0, so qmin <= qmax and the
+  // median is the clamp (equal up to the rounding of ql + (qmin - ql)).
+  return fmin(fmax(ql, qmin), qmax);
 }
 
 // Left and right states at face f+1/2 from the six cells f-2 .. f+3 (c[0..5]).
@@ -207,12 +217,12 @@ GR_HD void make_state(PState<T>& s, const M& m, T gam) {
   s.W = sqrt(T(1) + uu);
   const T iw = T(1) / s.W;
   for (int i = 0; i < 3; ++i) { s.v[i] = s.u[i] * iw; s.vl[i] = ul[i] * iw; }
-  s.v2 = uu / (T(1) + uu);
+  s.v2 = uu * (iw * iw);   // u^2 / W^2
   m.lower(s.B, s.Bl);
   s.B2 = s.Bl[0] * s.B[0] + s.Bl[1] * s.B[1] + s.Bl[2] * s.B[2];
   s.vB = s.vl[0] * s.B[0] + s.vl[1] * s.B[1] + s.vl[2] * s.B[2];
   s.E2 = s.B2 * s.v2 - s.vB * s.vB;
-  s.h = T(1) + gam / (gam - T(1)) * s.p / s.rho;
+  s.h = T(1) + (gam * s.p) / ((gam - T(1)) * s.rho);
   s.y = s.rho * s.h * s.W * s.W;
   s.D = s.rho * s.W;
   const T yb = s.y + s.B2;
@@ -257,7 +267,7 @@ template <typename T, class M>
 GR_HD void speeds_of(const PState<T>& s, const M& m, int d, T gam, T& lp, T& lm) {
   const T rhoh = s.rho * s.h;
   const T cs2 = gam * s.p / rhoh;
-  const T bb = s.B2 / (s.W * s.W) + s.vB * s.vB;
+  const T bb = s.B2 * (T(1) - s.v2) + s.vB * s.vB;   // b^2 = B^2/W^2 + (v.B)^2
   const T va2 = bb / (rhoh + bb);
   const T a2 = cs2 + va2 - cs2 * va2;
   const T vd = s.v[d];

@@ -82,6 +82,101 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
   for (int q6 = 0; q6 < 6; ++q6) ctd[(long)q6 * G.field + c] = double(cd[q6]);
 }
 
+// LDS-staged sweep for DIR = 1, 2 (stencils across rows or planes, which a
+// wavefront would otherwise fetch as six separate row loads per variable).
+// A workgroup owns SX consecutive transverse positions (flattened, x^1
+// fastest) times SF consecutive faces along DIR; it stages the SF + 5 cells
+// of each reconstructed variable its faces need in LDS, so each cell row is
+// read once per workgroup, then each wavefront runs the per-face body on one
+// face row.  Workgroups of one column follow each other along DIR.
+// One wavefront per face row (SX = 64); SF face rows per workgroup.
+constexpr int SX = 64;
+
+template <int DIR, int SF, class MET, typename T>
+__global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __restrict__ prim,
+                                                   const double* __restrict__ cons,
+                                                   const double* __restrict__ tab,
+                                                   double* __restrict__ flux,
+                                                   double* __restrict__ ctd) {
+  static_assert(DIR == 1 || DIR == 2, "x^2 and x^3 sweeps only");
+  constexpr int TB = DIR == 1 ? 2 : 1;          // the transverse axis other than x^1
+  constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+  constexpr int SR = SF + 5, NRR = (SR + SF - 1) / SF;
+  __shared__ T sh[7][SR][SX];
+  const int nA = G.dims[0];
+  const long M = (long)nA * G.dims[TB];
+  const int nface = G.n[DIR] + 5;               // faces -3 .. n + 1
+  const int ntf = (nface + SF - 1) / SF;
+  const long bid = xcd_block(blockIdx.x, gridDim.x);
+  const int ft = (int)(bid % ntf);
+  const long mt = bid / ntf;
+  const int tx = threadIdx.x % SX, ty = threadIdx.x / SX;
+  const long mm = mt * SX + tx;
+  const bool m_ok = mm < M;
+  const long mc = m_ok ? mm : M - 1;            // clamped: every staging load is in bounds
+  int ii[3];
+  ii[0] = (int)(mc % nA) - NG;
+  ii[TB] = (int)(mc / nA) - NG;
+  ii[DIR] = 0;
+  const long base = G.idx(ii[0], ii[1], ii[2]);
+  const long st = G.stride(DIR);
+  const int f0 = -3 + ft * SF;
+  // stage cells f0 - 2 .. f0 + SF + 2; wavefront ty loads rows ty + SF rr
+  // (a wave-uniform condition).  Rows past the last ghost cell are clamped to
+  // it: no face of the tile that exists reads them.  All loads are issued
+  // before the first LDS write.
+  {
+    constexpr int fields[7] = {P_RHO, P_P, P_U1, P_U2, P_U3, P_B1 + T1, P_B1 + T2};
+    const int cmax = G.n[DIR] + NG - 1;
+    T stage[7][NRR];
+#pragma unroll
+    for (int v = 0; v < 7; ++v)
+#pragma unroll
+      for (int rr = 0; rr < NRR; ++rr) {
+        if (ty + SF * rr < SR) {
+          const int cd = min(f0 - 2 + ty + SF * rr, cmax);
+          stage[v][rr] = T(prim[(long)fields[v] * G.field + base + cd * st]);
+        }
+      }
+#pragma unroll
+    for (int v = 0; v < 7; ++v)
+#pragma unroll
+      for (int rr = 0; rr < NRR; ++rr)
+        if (ty + SF * rr < SR) sh[v][ty + SF * rr][tx] = stage[v][rr];
+  }
+  __syncthreads();
+  const int f = f0 + ty;
+  if (!m_ok || f > G.n[DIR] + 1) return;
+  ii[DIR] = f;
+  const long c = base + f * st;
+  const T gam = T(G.gam);
+  MET m;
+  if constexpr (!MET::flat) {
+    constexpr int loc = DIR == 1 ? LOC_F2 : LOC_C;
+    m.load(tab, G.tab_plane, loc, G.tidx(ii[0], ii[1]));
+  }
+  T q[7][6];
+#pragma unroll
+  for (int v = 0; v < 7; ++v)
+#pragma unroll
+    for (int s = 0; s < 6; ++s) q[v][s] = sh[v][ty + s][tx];
+  const double bface = cons[(long)(C_BF1 + DIR) * G.field + c];
+  T bn;
+  bool axis = false;
+  if constexpr (MET::flat) {
+    bn = T(bface);
+  } else {
+    axis = (m.sg == T(0));
+    bn = axis ? T(0) : T(bface) / m.sg;
+  }
+  T fh[5], cd[6];
+  face_body<DIR>(q, bn, axis, m, gam, fh, cd);
+#pragma unroll
+  for (int q5 = 0; q5 < 5; ++q5) flux[(long)q5 * G.field + c] = double(fh[q5]);
+#pragma unroll
+  for (int q6 = 0; q6 < 6; ++q6) ctd[(long)q6 * G.field + c] = double(cd[q6]);
+}
+
 // Edge field of family E.  ctd_d / ctd_c: per-face data of the d and c sweeps.
 template <int E, class MET, typename T>
 __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__ cons,
@@ -133,7 +228,90 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
   edge[b] = double(ee);
 }
 
+// LDS-staged edge field for families E = 0, 2, whose five d-face inputs are
+// reconstructed across rows (along x^3 for E = 0, x^2 for E = 2).  Tiles of
+// SX consecutive positions (flattened, x^1 fastest) times SF edges along c;
+// the SF + 5 rows of the five inputs are staged once per workgroup.  The
+// c-face B (along d) and the four speeds are read directly.
+template <int E, int SF, class MET, typename T>
+__global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __restrict__ cons,
+                                                      const double* __restrict__ tab,
+                                                      const double* __restrict__ ctd_d,
+                                                      const double* __restrict__ ctd_c,
+                                                      double* __restrict__ edge) {
+  static_assert(E == 0 || E == 2, "families whose d-face inputs vary across rows");
+  constexpr int D = (E + 1) % 3, C = (E + 2) % 3, B = 3 - C;   // B: the non-x^1 axis that is not C
+  constexpr int SR = SF + 5, NRR = (SR + SF - 1) / SF;
+  __shared__ T sh[5][SR][SX];
+  const int extA = (E == 0) ? G.n[0] : G.n[0] + 5, offA = (E == 0) ? 0 : -3;
+  const int extB = (B == E) ? G.n[B] : G.n[B] + 5, offB = (B == E) ? 0 : -3;
+  const long M = (long)extA * extB;
+  const int nc = G.n[C] + 5;                    // edges -3 .. n + 1 along c
+  const int ntc = (nc + SF - 1) / SF;
+  const long bid = xcd_block(blockIdx.x, gridDim.x);
+  const int ct = (int)(bid % ntc);
+  const long mt = bid / ntc;
+  const int tx = threadIdx.x % SX, ty = threadIdx.x / SX;
+  const long mm = mt * SX + tx;
+  const bool m_ok = mm < M;
+  const long mc = m_ok ? mm : M - 1;            // clamped: every staging load is in bounds
+  int ii[3];
+  ii[0] = (int)(mc % extA) + offA;
+  ii[B] = (int)(mc / extA) + offB;
+  ii[C] = 0;
+  const long base = G.idx(ii[0], ii[1], ii[2]);
+  const long sd = G.stride(D), sc = G.stride(C);
+  const int c0 = -3 + ct * SF;
+  {
+    const double* src[5] = {ctd_d, ctd_d + G.field, ctd_d + 2 * G.field, ctd_d + 3 * G.field,
+                            cons + (long)(C_BF1 + D) * G.field};
+    const int cmax = G.n[C] + NG - 1;
+    T stage[5][NRR];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int rr = 0; rr < NRR; ++rr) {
+        if (ty + SF * rr < SR) {
+          const int cd = min(c0 - 2 + ty + SF * rr, cmax);
+          stage[v][rr] = T(src[v][base + cd * sc]);
+        }
+      }
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+      for (int rr = 0; rr < NRR; ++rr)
+        if (ty + SF * rr < SR) sh[v][ty + SF * rr][tx] = stage[v][rr];
+  }
+  __syncthreads();
+  const int cc = c0 + ty;
+  if (!m_ok || cc > G.n[C] + 1) return;
+  ii[C] = cc;
+  const long b = base + cc * sc;
+  T qd[5][6], qc[6];
+#pragma unroll
+  for (int v = 0; v < 5; ++v)
+#pragma unroll
+    for (int s2 = 0; s2 < 6; ++s2) qd[v][s2] = sh[v][ty + s2][tx];
+  {
+    const double* bcs = cons + (long)(C_BF1 + C) * G.field;
+#pragma unroll
+    for (int s2 = 0; s2 < 6; ++s2) qc[s2] = T(bcs[b + (s2 - 2) * sd]);
+  }
+  MET m;
+  if constexpr (!MET::flat) {
+    constexpr int loc = E == 2 ? LOC_E3 : LOC_F2;
+    m.load(tab, G.tab_plane, loc, G.tidx(ii[0], ii[1]));
+  }
+  const T ee = edge_body<E>(qd, qc, T(ctd_d[4 * G.field + b]), T(ctd_d[4 * G.field + b + sc]),
+                            T(ctd_d[5 * G.field + b]), T(ctd_d[5 * G.field + b + sc]),
+                            T(ctd_c[4 * G.field + b]), T(ctd_c[4 * G.field + b + sd]),
+                            T(ctd_c[5 * G.field + b]), T(ctd_c[5 * G.field + b + sd]), m);
+  edge[b] = double(ee);
+}
+
 // ------------------------------------------------------------------ launchers
+constexpr int SWEEP_SF = 4;   // face rows per workgroup of the staged sweeps
+constexpr int EDGE_SF = 4;    // edge rows per workgroup of the staged edge fields
 static inline unsigned nblocks(long total) { return (unsigned)((total + 255) / 256); }
 
 template <class MET, typename T>
@@ -143,9 +321,16 @@ static void launch_sweep_t(int d, const Geom& G, const double* prim, const doubl
   for (int a = 0; a < 3; ++a) total *= (a == d) ? G.n[a] + 5 : G.dims[a];
   double* fl = flux + (long)d * 5 * G.field;
   double* cd = ctd + (long)d * 6 * G.field;
-  if (d == 0) hipLaunchKernelGGL((k_sweep<0, MET, T>), dim3(nblocks(total)), dim3(256), 0, s, G, prim, cons, tab, fl, cd);
-  if (d == 1) hipLaunchKernelGGL((k_sweep<1, MET, T>), dim3(nblocks(total)), dim3(256), 0, s, G, prim, cons, tab, fl, cd);
-  if (d == 2) hipLaunchKernelGGL((k_sweep<2, MET, T>), dim3(nblocks(total)), dim3(256), 0, s, G, prim, cons, tab, fl, cd);
+  if (d == 0) {
+    hipLaunchKernelGGL((k_sweep<0, MET, T>), dim3(nblocks(total)), dim3(256), 0, s, G, prim, cons, tab, fl, cd);
+    return;
+  }
+  // tiles: SX transverse positions x SF faces
+  constexpr int SF = SWEEP_SF;
+  const long M = (long)G.dims[0] * G.dims[d == 1 ? 2 : 1];
+  const long tiles = ((M + SX - 1) / SX) * ((G.n[d] + 5 + SF - 1) / SF);
+  if (d == 1) hipLaunchKernelGGL((k_sweep_lds<1, SF, MET, T>), dim3(tiles), dim3(SX * SF), 0, s, G, prim, cons, tab, fl, cd);
+  if (d == 2) hipLaunchKernelGGL((k_sweep_lds<2, SF, MET, T>), dim3(tiles), dim3(SX * SF), 0, s, G, prim, cons, tab, fl, cd);
 }
 
 template <class MET, typename T>
@@ -157,9 +342,17 @@ static void launch_edge_t(int e, const Geom& G, const double* cons, const double
   const double* cd = ctd + (long)d * 6 * G.field;
   const double* cc = ctd + (long)c * 6 * G.field;
   double* ed = edges + (long)e * G.field;
-  if (e == 0) hipLaunchKernelGGL((k_edge<0, MET, T>), dim3(nblocks(total)), dim3(256), 0, s, G, cons, tab, cd, cc, ed);
-  if (e == 1) hipLaunchKernelGGL((k_edge<1, MET, T>), dim3(nblocks(total)), dim3(256), 0, s, G, cons, tab, cd, cc, ed);
-  if (e == 2) hipLaunchKernelGGL((k_edge<2, MET, T>), dim3(nblocks(total)), dim3(256), 0, s, G, cons, tab, cd, cc, ed);
+  if (e == 1) {
+    hipLaunchKernelGGL((k_edge<1, MET, T>), dim3(nblocks(total)), dim3(256), 0, s, G, cons, tab, cd, cc, ed);
+    return;
+  }
+  // staged families: tiles of SX positions (x^1 and the remaining axis) x SF edges along c
+  constexpr int SF = EDGE_SF;
+  const int B = 3 - c;
+  const long M = (long)((e == 0) ? G.n[0] : G.n[0] + 5) * ((B == e) ? G.n[B] : G.n[B] + 5);
+  const long tiles = ((M + SX - 1) / SX) * ((G.n[c] + 5 + SF - 1) / SF);
+  if (e == 0) hipLaunchKernelGGL((k_edge_lds<0, SF, MET, T>), dim3(tiles), dim3(SX * SF), 0, s, G, cons, tab, cd, cc, ed);
+  if (e == 2) hipLaunchKernelGGL((k_edge_lds<2, SF, MET, T>), dim3(tiles), dim3(SX * SF), 0, s, G, cons, tab, cd, cc, ed);
 }
 
 void launch_sweep(int d, const Geom& G, bool flat, bool fp32, const double* prim, const double* cons,
