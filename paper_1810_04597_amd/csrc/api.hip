@@ -41,7 +41,7 @@ constexpr int MLP_MAX_WAVES = 256;
 
 const char* const PROF_NAMES[GRMHD_PROF_NCLASS] = {
     "bc_centred", "sweep_x1", "sweep_x2", "sweep_x3", "edge_x1", "edge_x2", "edge_x3",
-    "update", "bc_faces", "cons2prim", "cfl", "copy_stage", "advance", "rhs_out",
+    "update", "bc_faces", "cons2prim", "cfl", "reserved", "advance", "rhs_out",
     "learned_guess", "learned_train"};
 }  // namespace
 

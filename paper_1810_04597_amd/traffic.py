@@ -15,6 +15,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,10 +31,11 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-CLASS_OF = {"k_sweep<0": "sweep_x1", "k_sweep<1": "sweep_x2", "k_sweep<2": "sweep_x3",
-            "k_edge<0": "edge_x1", "k_edge<1": "edge_x2", "k_edge<2": "edge_x3",
-            "k_update": "update", "k_c2p": "cons2prim", "k_bc_centred": "bc_centred",
-            "k_bc_faces": "bc_faces", "k_cfl": "cfl", "__amd_rocclr_copyBuffer": "copy_calib"}
+CLASS_OF = [(r"k_sweep(_lds)?<0", "sweep_x1"), (r"k_sweep(_lds)?<1", "sweep_x2"),
+            (r"k_sweep(_lds)?<2", "sweep_x3"), (r"k_edge(_lds)?<0", "edge_x1"),
+            (r"k_edge(_lds)?<1", "edge_x2"), (r"k_edge(_lds)?<2", "edge_x3"),
+            (r"k_update", "update"), (r"k_c2p", "cons2prim"), (r"k_bc_centred", "bc_centred"),
+            (r"k_bc_faces", "bc_faces"), (r"k_cfl", "cfl"), (r"__amd_rocclr_copyBuffer", "copy_calib")]
 
 
 def _read(d, counter):
@@ -44,8 +46,8 @@ def _read(d, counter):
             continue
         name = r["Kernel_Name"]
         cls = None
-        for key, c in CLASS_OF.items():
-            if key in name:
+        for pat, c in CLASS_OF:
+            if re.search(pat, name):
                 cls = c
         if cls is None:
             continue
