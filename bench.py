@@ -235,6 +235,8 @@ def learned_report(args):
         if dt is None:
             dt = G.compute_dt()
         G.synchronize()
+        G.set_profiling(True)
+        G.profile(reset=True)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(G.stream)
@@ -243,10 +245,14 @@ def learned_report(args):
         e1.record(G.stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
+        prof = G.profile(reset=True)
+        G.set_profiling(False)
         dg = G.diagnostics()
         res[name] = {"ms_per_step": ms / args.steps, "zone_updates_per_s": g.zones * args.steps / (ms / 1e3),
                      "newton_iters_per_zone_last": dg["newton_iters_sum"] / g.zones,
-                     "learned_fallbacks_last": dg["n_mlp_fallback"], "c2p_fail_last": dg["n_c2p_fail"]}
+                     "learned_fallbacks_last": dg["n_mlp_fallback"],
+                     "learned_chosen_last": dg["n_mlp_chosen"], "c2p_fail_last": dg["n_c2p_fail"],
+                     "kernels_avg_ms": {k: v[0] / v[1] for k, v in prof.items()}}
         grids[name] = G
         print("bench: %s done" % name, file=sys.stderr, flush=True)
     ref = grids["fp64_warm"]

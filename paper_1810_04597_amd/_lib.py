@@ -50,7 +50,7 @@ class Diag(C.Structure):
                 ("n_floor_rho", C.c_int64), ("n_floor_p", C.c_int64), ("n_wcap", C.c_int64),
                 ("n_c2p_fail", C.c_int64), ("n_mlp_fallback", C.c_int64),
                 ("newton_iters_sum", C.c_int64), ("newton_iters_max", C.c_int64),
-                ("n_nonfinite", C.c_int64)]
+                ("n_nonfinite", C.c_int64), ("n_mlp_chosen", C.c_int64)]
 
     def as_dict(self):
         out = {}

@@ -441,6 +441,7 @@ int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out) {
   out->n_floor_p = st[4];
   out->n_wcap = st[5];
   out->n_mlp_fallback = st[6];
+  out->n_mlp_chosen = st[7];
   return GRMHD_OK;
 }
 

@@ -389,12 +389,15 @@ struct NewtonOut {
   T rho, p, u[3];
   int iters;
   bool ok;
+  bool alt;     // the iteration started from y_alt
 };
 
 // Safeguarded Newton inversion in y = rho h W^2 (undensitised D, S_i, tau, B^i).
+// y_alt > 0: a second candidate start; the iteration starts from whichever of
+// y0 and y_alt has the smaller |residual| (one extra residual evaluation).
 template <typename T, class MET>
 GR_HD NewtonOut<T> newton(T dd, const T S[3], T tau, const T B[3], const MET& m, T gam,
-                          T y0, double tol, int maxit) {
+                          T y0, double tol, int maxit, T y_alt = T(-1)) {
   using std::isfinite;
   NewtonOut<T> o;
   const T utot = tau + dd;
@@ -411,6 +414,21 @@ GR_HD NewtonOut<T> newton(T dd, const T S[3], T tau, const T B[3], const MET& m,
   T a = 0.0, bb = gam * utot;
   T y = y0;
   if (!(y > a && y < bb)) y = 0.5 * (a + bb);
+  o.alt = false;
+  if (valid && y_alt > a && y_alt < bb) {
+    // residual of the energy equation at a candidate start; +inf where v^2 >= 1
+    auto resid = [&](T yc) {
+      const T yy = yc * yc;
+      const T v2 = (s2 + sb2 * (2.0 * yc + b2) / yy) / ((yc + b2) * (yc + b2));
+      if (!(v2 < 1.0)) return T(INFINITY);
+      const T p = gf * (yc * (1.0 - v2) - dd * sqrt(1.0 - v2));
+      return fabs(yc - p + 0.5 * b2 * (1.0 + v2) - 0.5 * sb2 / yy - utot);
+    };
+    if (resid(y_alt) < resid(y)) {
+      y = y_alt;
+      o.alt = true;
+    }
+  }
   bool conv = false;
   int it = 0;
   const T EPS4 = T(4.0 * 2.220446049250313e-16);

@@ -32,10 +32,17 @@ __device__ __forceinline__ unsigned short f2bf(float x) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
+// Four floats to bfloat16, round to nearest even (v_cvt_pk_bf16_f32; the
+// same rounding as f2bf for every finite value).
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ bf4 pack(f4 v) {
+  const b2v lo = __builtin_convertvector((f2v){v[0], v[1]}, b2v);
+  const b2v hi = __builtin_convertvector((f2v){v[2], v[3]}, b2v);
+  const unsigned a = __builtin_bit_cast(unsigned, lo), b = __builtin_bit_cast(unsigned, hi);
   bf4 o;
-  o[0] = (short)f2bf(v[0]); o[1] = (short)f2bf(v[1]);
-  o[2] = (short)f2bf(v[2]); o[3] = (short)f2bf(v[3]);
+  o[0] = (short)(a & 0xffff); o[1] = (short)(a >> 16);
+  o[2] = (short)(b & 0xffff); o[3] = (short)(b >> 16);
   return o;
 }
 
@@ -67,8 +74,16 @@ struct Acts {
 };
 
 // Forward pass of one tile of 16 samples; xb: B operand of the inputs.
+// tanh(x) = 1 - 2 / (exp(2x) + 1) with the hardware exp2 and reciprocal
+// (absolute error ~1e-7, far below the bfloat16 rounding of the activations)
+__device__ __forceinline__ float tanh_fast(float x) {
+  return 1.f - __fdividef(2.f, __expf(2.f * x) + 1.f);
+}
+
+// Training and the forward entry point use the library tanhf.
 __device__ __forceinline__ void forward_tile(const unsigned short* __restrict__ wb,
                                              const float* __restrict__ wf, bf4 xb, Acts& a) {
+  auto act = [](float x) { return tanhf(x); };
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   bf4 hb[4];
 #pragma unroll
@@ -76,7 +91,7 @@ __device__ __forceinline__ void forward_tile(const unsigned short* __restrict__ 
     f4 acc = {0.f, 0.f, 0.f, 0.f};
     acc = mfma(load_a(wb + OW1, 16, 16 * mt + lr, 4 * lg), xb, acc);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = tanhf(acc[r] + wf[OB1 + 16 * mt + 4 * lg + r]);
+    for (int r = 0; r < 4; ++r) acc[r] = act(acc[r] + wf[OB1 + 16 * mt + 4 * lg + r]);
     a.h1[mt] = acc;
     hb[mt] = pack(acc);
   }
@@ -88,7 +103,7 @@ __device__ __forceinline__ void forward_tile(const unsigned short* __restrict__ 
     for (int kt = 0; kt < 4; ++kt)
       acc = mfma(load_a(wb + OW2, 64, 16 * mt + lr, 16 * kt + 4 * lg), hb[kt], acc);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = tanhf(acc[r] + wf[OB2 + 16 * mt + 4 * lg + r]);
+    for (int r = 0; r < 4; ++r) acc[r] = act(acc[r] + wf[OB2 + 16 * mt + 4 * lg + r]);
     a.h2[mt] = acc;
     hb2[mt] = pack(acc);
   }
@@ -99,7 +114,7 @@ __device__ __forceinline__ void forward_tile(const unsigned short* __restrict__ 
     for (int kt = 0; kt < 4; ++kt)
       acc = mfma(load_a(wb + OW3, 64, 16 * mt + lr, 16 * kt + 4 * lg), hb2[kt], acc);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = tanhf(acc[r] + wf[OB3 + 16 * mt + 4 * lg + r]);
+    for (int r = 0; r < 4; ++r) acc[r] = act(acc[r] + wf[OB3 + 16 * mt + 4 * lg + r]);
     a.h3[mt] = acc;
     hb[mt] = pack(acc);
   }
@@ -110,6 +125,73 @@ __device__ __forceinline__ void forward_tile(const unsigned short* __restrict__ 
 #pragma unroll
   for (int r = 0; r < 4; ++r) acc[r] += wf[OB4 + 4 * lg + r];
   a.out = acc;
+}
+
+// Inference over four 16-sample tiles at once (the guess kernel): each
+// weight fragment and bias is loaded once per wavefront and feeds the four
+// tiles' independent MFMA chains; tanh_fast activations.
+__device__ __forceinline__ void forward4(const unsigned short* __restrict__ wb,
+                                         const float* __restrict__ wf, const bf4 xb[4], f4 out[4]) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  bf4 h[4][4];   // [tile][k tile] activations, B layout
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const bf4 w = load_a(wb + OW1, 16, 16 * mt + lr, 4 * lg);
+    f4 bias;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias[r] = wf[OB1 + 16 * mt + 4 * lg + r];
+#pragma unroll
+    for (int tl = 0; tl < 4; ++tl) {
+      f4 acc = mfma(w, xb[tl], (f4){0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = tanh_fast(acc[r] + bias[r]);
+      h[tl][mt] = pack(acc);
+    }
+  }
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    const int ow = layer == 0 ? OW2 : OW3, ob = layer == 0 ? OB2 : OB3;
+    bf4 hn[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f4 acc[4];
+#pragma unroll
+      for (int tl = 0; tl < 4; ++tl) acc[tl] = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) {
+        const bf4 w = load_a(wb + ow, 64, 16 * mt + lr, 16 * kt + 4 * lg);
+#pragma unroll
+        for (int tl = 0; tl < 4; ++tl) acc[tl] = mfma(w, h[tl][kt], acc[tl]);
+      }
+      f4 bias;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bias[r] = wf[ob + 16 * mt + 4 * lg + r];
+#pragma unroll
+      for (int tl = 0; tl < 4; ++tl) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[tl][r] = tanh_fast(acc[tl][r] + bias[r]);
+        hn[tl][mt] = pack(acc[tl]);
+      }
+    }
+#pragma unroll
+    for (int tl = 0; tl < 4; ++tl)
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) h[tl][mt] = hn[tl][mt];
+  }
+#pragma unroll
+  for (int tl = 0; tl < 4; ++tl) out[tl] = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kt = 0; kt < 4; ++kt) {
+    const bf4 w = load_a(wb + OW4, 64, lr, 16 * kt + 4 * lg);
+#pragma unroll
+    for (int tl = 0; tl < 4; ++tl) out[tl] = mfma(w, h[tl][kt], out[tl]);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float bias = wf[OB4 + 4 * lg + r];
+#pragma unroll
+    for (int tl = 0; tl < 4; ++tl) out[tl][r] += bias;
+  }
 }
 
 // B operand of a tile of standardised inputs x[sample][8] (features >= 8 are 0).
@@ -507,29 +589,39 @@ __global__ __launch_bounds__(256) void k_guess(Geom G, const double* __restrict_
                          m.undens(cons[C_S3 * G.field + c])};
     const double tau = m.undens(cons[C_TAU * G.field + c]);
     utot = tau + dd;
-    double fr[8], Sh[3], Bh[3];
+    double Sh[3], Bh[3];
     frame_components(m, S, B, Sh, Bh);
-    mlp_features(dd, Sh, tau, Bh, fr);
+    // the features of mlp_features in single precision with the hardware
+    // log2 / reciprocal square root (they are rounded to bfloat16 next)
+    const float fdd = (float)dd, fe = (float)utot;
+    const float ie = __fdividef(1.f, fe), ise = __frsqrt_rn(fe);
+    float fr[8];
+    fr[0] = __log10f(fdd);
+    fr[1] = __log10f(__fdividef((float)tau, fdd));
+    for (int q = 0; q < 3; ++q) {
+      fr[2 + q] = (float)Sh[q] * ie;
+      fr[5 + q] = (float)Bh[q] * ise;
+    }
     for (int q = 0; q < 8; ++q) {
-      const float v = (float)fr[q];
-      f[q] = isfinite(v) ? (v - norm[NM_FMEAN + q]) / norm[NM_FSTD + q] : 0.f;
+      const float v = fr[q];
+      f[q] = isfinite(v) ? (v - norm[NM_FMEAN + q]) * __fdividef(1.f, norm[NM_FSTD + q]) : 0.f;
     }
   }
   f4 outs[4];
+  bf4 xb[4];
 #pragma unroll
   for (int tile = 0; tile < 4; ++tile) {
     const int src = 16 * tile + lr;
-    bf4 xb = {0, 0, 0, 0};
+    f4 xv;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const float lo = __shfl(f[r], src, 64);
       const float hi = __shfl(f[4 + r], src, 64);
-      xb[r] = lg == 0 ? (short)f2bf(lo) : (lg == 1 ? (short)f2bf(hi) : (short)0);
+      xv[r] = lg == 0 ? lo : (lg == 1 ? hi : 0.f);
     }
-    Acts a;
-    forward_tile(wb, wf, xb, a);
-    outs[tile] = a.out;
+    xb[tile] = pack(xv);
   }
+  forward4(wb, wf, xb, outs);
   // outputs of this lane's zone: tile = lane/16, sample = lane%16:
   // outputs 0..3 from lane (lane%16), r = 0..3; output 4 from lane 16 + lane%16, r = 0
   float o5[5];
@@ -544,8 +636,8 @@ __global__ __launch_bounds__(256) void k_guess(Geom G, const double* __restrict_
   }
   if (!live) return;
   // guess from the first output: y0 = U 10^{t0}
-  const double t0 = (double)o5[0] * norm[NM_TSTD + 0] + norm[NM_TMEAN + 0];
-  const double y0 = utot * pow(10.0, t0);
+  const float t0 = o5[0] * norm[NM_TSTD + 0] + norm[NM_TMEAN + 0];
+  const double y0 = utot * (double)__exp10f(t0);
   y0out[c] = isfinite(y0) ? y0 : -1.0;
 }
 

@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
                                              double* __restrict__ cfl_partials) {
   const long t = flat_thread();
   const bool live = t < (long)G.n[0] * G.n[1] * G.n[2];
-  long long st[7] = {0, 0, 0, 0, 0, 0, 0};
+  long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double cfl_v = 0.0;
   if (live) {
     int i, j, k;
@@ -350,10 +350,13 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
       const double h = 1.0 + G.gam / (G.gam - 1.0) * p / rho;
       ywarm = rho * h * (1.0 + uu);
     }
-    const double y0 = cp.guess == 1 ? G.gam * (tau + dd) : (cp.guess == 2 ? y0_learned[c] : ywarm);
-    NewtonOut<double> r = newton<double>(dd, S, tau, B, m, G.gam, y0, cp.tol, cp.maxit);
-    if (cp.guess == 2 && !r.ok) {
-      // the learned guess did not lead to convergence: plain Newton from the warm guess
+    // learned guess: a second candidate start next to the warm one (the
+    // smaller residual wins); the warm start is rerun if a learned start fails
+    const double y0 = cp.guess == 1 ? G.gam * (tau + dd) : ywarm;
+    const double yalt = cp.guess == 2 ? y0_learned[c] : -1.0;
+    NewtonOut<double> r = newton<double>(dd, S, tau, B, m, G.gam, y0, cp.tol, cp.maxit, yalt);
+    st[7] = r.alt ? 1 : 0;
+    if (r.alt && !r.ok) {
       const int it0 = r.iters;
       r = newton<double>(dd, S, tau, B, m, G.gam, ywarm, cp.tol, cp.maxit);
       r.iters += it0;
@@ -434,21 +437,21 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
     __syncthreads();
     if (threadIdx.x == 0) cfl_partials[blockIdx.x] = fmax(fmax(shc[0], shc[1]), fmax(shc[2], shc[3]));
   }
-  // per-block partials: fail, iters_sum, iters_max, floor_rho, floor_p, wcap, learned fallback
-  __shared__ long long sh[4][7];
+  // per-block partials: fail, iters_sum, iters_max, floor_rho, floor_p, wcap,
+  // learned fallback, learned start chosen
+  __shared__ long long sh[4][8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  long long rr[7];
-  for (int q = 0; q < 7; ++q) rr[q] = q == 2 ? wave_max_ll(st[q]) : wave_sum_ll(st[q]);
+  long long rr[8];
+  for (int q = 0; q < 8; ++q) rr[q] = q == 2 ? wave_max_ll(st[q]) : wave_sum_ll(st[q]);
   if (lane == 0)
-    for (int q = 0; q < 7; ++q) sh[wv][q] = rr[q];
+    for (int q = 0; q < 8; ++q) sh[wv][q] = rr[q];
   __syncthreads();
   if (threadIdx.x == 0) {
-    long long o[7] = {0, 0, 0, 0, 0, 0, 0};
+    long long o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int w = 0; w < 4; ++w)
-      for (int q = 0; q < 7; ++q) o[q] = q == 2 ? (sh[w][q] > o[q] ? sh[w][q] : o[q]) : o[q] + sh[w][q];
+      for (int q = 0; q < 8; ++q) o[q] = q == 2 ? (sh[w][q] > o[q] ? sh[w][q] : o[q]) : o[q] + sh[w][q];
     long long* dst = partials + (long)blockIdx.x * C2P_NSTAT;
-    for (int q = 0; q < 7; ++q) dst[q] = o[q];
-    dst[7] = 0;
+    for (int q = 0; q < 8; ++q) dst[q] = o[q];
   }
 }
 

@@ -190,3 +190,51 @@ def test_grid_inversion_with_learned_guess_matches_oracle():
     print("learned-guess torus: max rel err", e, "fallbacks", dg["n_mlp_fallback"], "iters",
           dg["newton_iters_sum"] / g.zones)
     assert max(e.values()) < 1e-9, e
+
+
+@gpu
+def test_learned_start_wins_when_warm_start_is_poor():
+    """Torus grid whose stored primitives (the warm start) are replaced by a
+    uniform state after the conserved variables were set: with the learned
+    guess as the second candidate, most zones start from it, the inversion
+    needs fewer Newton iterations than from the poor warm start, and both
+    reach the oracle's inversion of the same conserved state (same root,
+    same floors)."""
+    torch = _torch()
+    from workloads.torus import torus
+    from oracle.scheme import Solver
+    from paper_1810_04597_amd.grid import Grid
+    from paper_1810_04597_amd import _lib as L
+    from helpers import max_rel, interior
+    g0, d0, G0 = _grid()
+    _train(G0, 1 << 18, 4)
+    flat, norm = G0.mlp_get_weights()
+    g, d, tab = torus(32, 16, 16)
+    s = Solver(g, tab)
+    s.curl_potential(d)
+    s.set_primitives(d)
+    s.cons2prim()
+    P = {k: interior(v) for k, v in s.P.items()}
+    res = {}
+    for guess in (L.GUESS_WARM, L.GUESS_MLP):
+        G = Grid(g, tables=tab, guess=guess)
+        if guess == L.GUESS_MLP:
+            G.mlp_set_weights(flat, norm)
+        G.curl_potential(d)
+        G.set_primitives(d)
+        for f, val in ((0, 1.0), (1, 0.0), (2, 0.0), (3, 0.0), (4, 1.0)):
+            G._interior(G.field_view(G.prim, f)).fill_(val)
+        assert G.cons2prim() == 0
+        dg = G.diagnostics()
+        gp = G.to_numpy("prim", interior=True)
+        # u^2 of the initial torus is zero up to round-off: absolute bound
+        e = max_rel(gp, P, ("rho", "u1", "u3", "p"))
+        e["u2"] = float(np.max(np.abs(gp["u2"] - P["u2"])))
+        assert max(e.values()) < 1e-9, (guess, e)
+        res[guess] = dg
+    warm, learned = res[L.GUESS_WARM], res[L.GUESS_MLP]
+    print("poor warm start: iterations warm %d learned %d, learned chosen %d of %d, fallbacks %d" % (
+        warm["newton_iters_sum"], learned["newton_iters_sum"], learned["n_mlp_chosen"], g.zones,
+        learned["n_mlp_fallback"]))
+    assert learned["n_mlp_chosen"] > g.zones // 2
+    assert learned["newton_iters_sum"] < warm["newton_iters_sum"]
