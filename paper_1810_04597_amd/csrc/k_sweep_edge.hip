@@ -110,7 +110,8 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   const long bid = xcd_block(blockIdx.x, gridDim.x);
   const int ft = (int)(bid % ntf);
   const long mt = bid / ntf;
-  const int tx = threadIdx.x % SX, ty = threadIdx.x / SX;
+  // ty (the face row) is the wavefront index: uniform, so row offsets go to the scalar unit
+  const int tx = threadIdx.x % SX, ty = __builtin_amdgcn_readfirstlane(threadIdx.x / SX);
   const long mm = mt * SX + tx;
   const bool m_ok = mm < M;
   const long mc = m_ok ? mm : M - 1;            // clamped: every staging load is in bounds
@@ -128,16 +129,16 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   {
     constexpr int fields[7] = {P_RHO, P_P, P_U1, P_U2, P_U3, P_B1 + T1, P_B1 + T2};
     const int cmax = G.n[DIR] + NG - 1;
+    const double* pb = prim + base;             // per lane; the offsets below are uniform
     T stage[7][NRR];
 #pragma unroll
-    for (int v = 0; v < 7; ++v)
+    for (int rr = 0; rr < NRR; ++rr) {
+      if (ty + SF * rr < SR) {
+        const long ro = (long)min(f0 - 2 + ty + SF * rr, cmax) * st;
 #pragma unroll
-      for (int rr = 0; rr < NRR; ++rr) {
-        if (ty + SF * rr < SR) {
-          const int cd = min(f0 - 2 + ty + SF * rr, cmax);
-          stage[v][rr] = T(prim[(long)fields[v] * G.field + base + cd * st]);
-        }
+        for (int v = 0; v < 7; ++v) stage[v][rr] = T(pb[(long)fields[v] * G.field + ro]);
       }
+    }
 #pragma unroll
     for (int v = 0; v < 7; ++v)
 #pragma unroll
@@ -251,7 +252,8 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   const long bid = xcd_block(blockIdx.x, gridDim.x);
   const int ct = (int)(bid % ntc);
   const long mt = bid / ntc;
-  const int tx = threadIdx.x % SX, ty = threadIdx.x / SX;
+  // ty (the face row) is the wavefront index: uniform, so row offsets go to the scalar unit
+  const int tx = threadIdx.x % SX, ty = __builtin_amdgcn_readfirstlane(threadIdx.x / SX);
   const long mm = mt * SX + tx;
   const bool m_ok = mm < M;
   const long mc = m_ok ? mm : M - 1;            // clamped: every staging load is in bounds
@@ -268,14 +270,13 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
     const int cmax = G.n[C] + NG - 1;
     T stage[5][NRR];
 #pragma unroll
-    for (int v = 0; v < 5; ++v)
+    for (int rr = 0; rr < NRR; ++rr) {
+      if (ty + SF * rr < SR) {
+        const long ro = base + (long)min(c0 - 2 + ty + SF * rr, cmax) * sc;
 #pragma unroll
-      for (int rr = 0; rr < NRR; ++rr) {
-        if (ty + SF * rr < SR) {
-          const int cd = min(c0 - 2 + ty + SF * rr, cmax);
-          stage[v][rr] = T(src[v][base + cd * sc]);
-        }
+        for (int v = 0; v < 5; ++v) stage[v][rr] = T(src[v][ro]);
       }
+    }
 #pragma unroll
     for (int v = 0; v < 5; ++v)
 #pragma unroll
