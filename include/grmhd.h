@@ -188,11 +188,13 @@ int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out);
  * Inputs: [log10 D, log10(tau/D), S_hat/(tau+D), B_hat/sqrt(tau+D)] in the
  * Eulerian orthonormal frame; outputs [log10(y/U), log10(p/D), u_hat] with
  * y = rho h W^2 and U = tau + D; both standardised with the normalisation
- * block.  With c2p_guess = GRMHD_GUESS_MLP the network's y0 = U 10^{output 0}
- * is a second candidate start next to the warm guess (the previous
- * primitives): Newton starts from the candidate with the smaller residual
- * (counted in grmhd_diag.n_mlp_chosen) and is rerun from the warm guess when a
- * learned start does not converge (counted in grmhd_diag.n_mlp_fallback).
+ * block.  With c2p_guess = GRMHD_GUESS_MLP the inversion starts every zone
+ * from the warm guess (the previous primitives) and defers the zones whose
+ * first residual, relative to the magnitude of its terms, exceeds 1e-2 to a
+ * second pass: there the network's y0 = U 10^{output 0} is a second candidate
+ * start, Newton starts from the candidate with the smaller residual (counted
+ * in grmhd_diag.n_mlp_chosen) and is rerun from the warm guess when a learned
+ * start does not converge (counted in grmhd_diag.n_mlp_fallback).
  * Parameter block (float32, GRMHD_MLP_NPARAM): W1[64][16] (inputs padded to
  * 16 with zeros), b1[64], W2[64][64], b2[64], W3[64][64], b3[64],
  * W4[16][64] (outputs padded to 16 with zeros), b4[16].  Normalisation block

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -35,7 +36,7 @@ constexpr int SCR_CONS_N = 0;    // 8 fields
 constexpr int SCR_FLUX = 8;      // 3 x 5 fields
 constexpr int SCR_CTD = 23;      // 3 x 6 fields
 constexpr int SCR_EDGE = 41;     // 3 fields
-constexpr int SCR_GUESS = 44;    // 1 field: learned Newton guess per zone
+constexpr int SCR_GUESS = 44;    // 1 field: list of zones deferred to the learned-guess pass (int)
 constexpr int SCR_NFIELDS = 45;
 constexpr int MLP_MAX_WAVES = 256;
 
@@ -60,6 +61,7 @@ struct grmhd_grid {
   // library-owned device buffers
   double* d_dt = nullptr;        // [0] dt of the current step, [1] time, [2] CFL dt of the state
   bool next_dt_valid = false;    // d_dt[2] holds the CFL dt of the current primitives
+  int* d_list_n = nullptr;       // number of zones deferred to the learned-guess pass
   double* d_part = nullptr;      // per-block partials (cfl, diagnostics)
   long long* d_spart = nullptr;  // per-block inversion statistics
   long long* d_stats = nullptr;  // reduced inversion statistics (8)
@@ -92,7 +94,7 @@ struct grmhd_grid {
   double* flux() const { return scratch + (long)SCR_FLUX * G.field; }
   double* ctd() const { return scratch + (long)SCR_CTD * G.field; }
   double* edges() const { return scratch + (long)SCR_EDGE * G.field; }
-  double* guess() const { return scratch + (long)SCR_GUESS * G.field; }
+  int* list() const { return reinterpret_cast<int*>(scratch + (long)SCR_GUESS * G.field); }
   MlpState mlp;
   bool mlp_alloc = false;
 };
@@ -171,6 +173,10 @@ C2PParams c2p_params(const grmhd_grid_desc& d) {
   cp.p_fl_a = d.p_fl_a;
   cp.p_fl_n = d.p_fl_n;
   cp.w_max = d.w_max;
+  // learned guess: zones whose warm start (the previous primitives) leaves a
+  // relative residual above 1e-2 go to the network pass; elsewhere the warm
+  // start is better than the network's accuracy
+  cp.defer_tol = d.c2p_guess == GRMHD_GUESS_MLP ? 1e-2 : 0.0;
   return cp;
 }
 
@@ -199,11 +205,16 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** 
   for (int s = 0; s < 6; ++s) h->bc.bc[s] = desc->bc[s];
   h->stream = (hipStream_t)hip_stream;
   h->nblk = zone_blocks(h->G);
-  const size_t part = (size_t)h->nblk * (DIAG_NSUM + DIAG_NMAX) * sizeof(double);
+  // reduction partials: diagnostics (nblk x 16) and CFL (nblk + learned-pass blocks)
+  const size_t part = std::max((size_t)h->nblk * (DIAG_NSUM + DIAG_NMAX),
+                               (size_t)h->nblk + C2P_LIST_BLOCKS) * sizeof(double);
+  const size_t spart = ((size_t)h->nblk + C2P_LIST_BLOCKS) * C2P_NSTAT * sizeof(long long);
   hipError_t e = hipSuccess;
   e = hipMalloc(&h->d_dt, 3 * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&h->d_part, part);
-  if (e == hipSuccess) e = hipMalloc(&h->d_spart, (size_t)h->nblk * C2P_NSTAT * sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc(&h->d_spart, spart);
+  if (e == hipSuccess) e = hipMalloc(&h->d_list_n, sizeof(int));
+  if (e == hipSuccess) e = hipMemsetAsync(h->d_spart, 0, spart, h->stream);
   if (e == hipSuccess) e = hipMalloc(&h->d_stats, C2P_NSTAT * sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&h->d_diag, (DIAG_NSUM + DIAG_NMAX) * sizeof(double));
   if (e == hipSuccess) e = hipMemsetAsync(h->d_dt, 0, 3 * sizeof(double), h->stream);
@@ -295,17 +306,30 @@ static void rhs_pieces(grmhd_grid* h) {
     h->timed(4 + e, [&] { launch_edge(e, h->G, h->flat, fp32, h->cons, h->tab, h->ctd(), h->edges(), h->stream); });
 }
 
-// with_cfl: also reduce the CFL time step of the inverted state into d_dt[2]
+// with_cfl: also reduce the CFL time step of the inverted state into d_dt[2].
+// Learned guess: the inversion defers zones with a poor warm start to a list,
+// the network pass inverts those; counters and CFL partials of both passes
+// are reduced together.
 static void c2p_with_guess(grmhd_grid* h, const C2PParams& cp, bool with_cfl = false) {
-  const double* y0 = nullptr;
+  double* cflp = with_cfl ? h->d_part : nullptr;
+  const int nb = (int)h->nblk;
   if (cp.guess == GRMHD_GUESS_MLP) {
-    h->timed(14, [&] { mlp_launch_guess(h->G, h->flat, h->cons, h->tab, h->mlp, h->guess(), h->stream); });
-    y0 = h->guess();
+    h->timed(9, [&] {
+      launch_zero_int(h->d_list_n, h->stream);
+      launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, cflp, h->list(), h->d_list_n,
+                 h->stream);
+    });
+    h->timed(14, [&] {
+      mlp_launch_c2p_list(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->mlp, h->list(), h->d_list_n,
+                          h->d_spart + (long)nb * C2P_NSTAT, cflp ? cflp + nb : nullptr, h->stream);
+    });
+    if (with_cfl) launch_dt_final(cflp, nb + C2P_LIST_BLOCKS, h->desc.cfl, h->d_dt + 2, h->stream);
+  } else {
+    h->timed(9, [&] {
+      launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, cflp, nullptr, nullptr, h->stream);
+    });
+    if (with_cfl) launch_dt_final(cflp, nb, h->desc.cfl, h->d_dt + 2, h->stream);
   }
-  h->timed(9, [&] {
-    launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, h->stream, y0,
-               with_cfl ? h->d_part : nullptr, h->desc.cfl, h->d_dt + 2);
-  });
 }
 
 static int mlp_ready(grmhd_grid* h) {
@@ -380,7 +404,7 @@ int grmhd_cons2prim(grmhd_grid* h, int64_t* n_fail, int strict) {
   if (rc) return rc;
   if (n_fail) {
     long long st[C2P_NSTAT];
-    launch_reduce_stats(h->d_spart, (int)h->nblk, h->d_stats, h->stream);
+    launch_reduce_stats(h->d_spart, (int)h->nblk + C2P_LIST_BLOCKS, h->d_stats, h->stream);
     hipError_t e = hipMemcpyAsync(st, h->d_stats, sizeof(st), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
@@ -410,7 +434,7 @@ int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out) {
   long long st[C2P_NSTAT];
   double dtt[2] = {0.0, 0.0};
   launch_diag(h->G, h->flat, h->prim, h->cons, h->tab, h->d_part, h->d_diag, h->stream);
-  launch_reduce_stats(h->d_spart, (int)h->nblk, h->d_stats, h->stream);
+  launch_reduce_stats(h->d_spart, (int)h->nblk + C2P_LIST_BLOCKS, h->d_stats, h->stream);
   hipError_t e = hipMemcpyAsync(dg, h->d_diag, sizeof(dg), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(st, h->d_stats, sizeof(st), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(dtt, h->d_dt, sizeof(dtt), hipMemcpyDeviceToHost, h->stream);
@@ -611,6 +635,7 @@ void grmhd_destroy(grmhd_grid* h) {
   }
   (void)hipFree(h->tab);
   (void)hipFree(h->d_dt);
+  (void)hipFree(h->d_list_n);
   (void)hipFree(h->d_part);
   (void)hipFree(h->d_spart);
   (void)hipFree(h->d_stats);

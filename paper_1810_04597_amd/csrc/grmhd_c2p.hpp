@@ -1,0 +1,200 @@
+// One zone of the conservative-to-primitive inversion, wavefront reductions
+// and per-block partials (device code shared by the inversion kernel and the
+// learned-guess pass over deferred zones).
+#pragma once
+#include "grmhd_device.hpp"
+#include "grmhd_kernels.hpp"
+
+namespace grmhd {
+
+// ------------------------------------------------------------------ wavefront reductions
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ long long wave_max_ll(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    long long w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void zone_of(const Geom& G, long t, int& i, int& j, int& k) {
+  i = (int)(t % G.n[0]);
+  const long r = t / G.n[0];
+  j = (int)(r % G.n[1]);
+  k = (int)(r / G.n[1]);
+}
+
+// Centred field B^d = I_d(face field) / sqrt(gamma) at element c.
+template <class MET>
+__device__ __forceinline__ void centred_b(const Geom& G, const double* __restrict__ cons, long c,
+                                          const MET& m, double B[3]) {
+  double f[6];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double* fp = cons + (long)(C_BF1 + d) * G.field + c;
+    const long st = G.stride(d);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) f[s] = fp[(s - 3) * st];
+    B[d] = m.undens(fd_interp(f));
+  }
+}
+
+// Inversion of interior zone t (flattened, x^1 fastest): Newton from the
+// warm or cold guess per cp.guess, y_alt > 0 a second candidate start (the
+// smaller residual wins; a failed learned start is rerun from the warm one),
+// then floors and the W cap.  With defer_tol > 0 a zone whose warm start has a
+// larger relative residual is left untouched and true is returned.  Adds the
+// zone's counters to st (fail, iterations, iterations max, floor_rho,
+// floor_p, W cap, learned fallback, learned chosen) and, with want_cfl, sets
+// cfl_v to its sum over d of max|lambda_d| / dx_d.
+template <class MET>
+__device__ __forceinline__ bool c2p_zone(const Geom& G, const C2PParams& cp, double* __restrict__ prim,
+                                         double* __restrict__ cons, const double* __restrict__ tab,
+                                         long t, double y_alt, double defer_tol, bool want_cfl,
+                                         long long st[8], double& cfl_v) {
+  int i, j, k;
+  zone_of(G, t, i, j, k);
+  const long c = G.idx(i, j, k);
+  MET m;
+  if constexpr (!MET::flat) m.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
+  double B[3];
+  centred_b(G, cons, c, m, B);
+  const double dd = m.undens(cons[C_D * G.field + c]);
+  const double S[3] = {m.undens(cons[C_S1 * G.field + c]), m.undens(cons[C_S2 * G.field + c]),
+                       m.undens(cons[C_S3 * G.field + c])};
+  const double tau = m.undens(cons[C_TAU * G.field + c]);
+  double rho = prim[P_RHO * G.field + c];
+  double p = prim[P_P * G.field + c];
+  double u[3] = {prim[P_U1 * G.field + c], prim[P_U2 * G.field + c], prim[P_U3 * G.field + c]};
+  double ywarm;
+  {
+    double ul[3];
+    m.lower(u, ul);
+    const double uu = ul[0] * u[0] + ul[1] * u[1] + ul[2] * u[2];
+    const double h = 1.0 + G.gam / (G.gam - 1.0) * p / rho;
+    ywarm = rho * h * (1.0 + uu);
+  }
+  const double y0 = cp.guess == 1 ? G.gam * (tau + dd) : ywarm;
+  NewtonOut<double> r = newton<double>(dd, S, tau, B, m, G.gam, y0, cp.tol, cp.maxit, y_alt, defer_tol);
+  if (r.deferred) return true;
+  if (r.alt) st[7] += 1;
+  if (r.alt && !r.ok) {
+    const int it0 = r.iters;
+    r = newton<double>(dd, S, tau, B, m, G.gam, ywarm, cp.tol, cp.maxit);
+    r.iters += it0;
+    st[6] += 1;
+  }
+  if (r.ok) {
+    rho = r.rho;
+    p = r.p;
+    u[0] = r.u[0]; u[1] = r.u[1]; u[2] = r.u[2];
+  }
+  st[0] += r.ok ? 0 : 1;
+  st[1] += r.iters;
+  st[2] = st[2] > r.iters ? st[2] : r.iters;
+  bool floored = false;
+  if (cp.rho_fl_a > 0.0 || cp.p_fl_a > 0.0 || cp.w_max > 0.0) {
+    const double rr = cp.coord == 1 ? exp(G.x0[0] + (i + 0.5) * G.dx[0]) : 1.0;
+    if (!r.ok) {
+      // failed zone -> atmosphere at rest
+      rho = cp.rho_fl_a * pow(rr, cp.rho_fl_n);
+      p = cp.p_fl_a * pow(rr, cp.p_fl_n);
+      u[0] = u[1] = u[2] = 0.0;
+      floored = true;
+    }
+    if (cp.rho_fl_a > 0.0) {
+      const double rfl = cp.rho_fl_a * pow(rr, cp.rho_fl_n);
+      if (rho < rfl) { rho = rfl; floored = true; st[3] += 1; }
+    }
+    if (cp.p_fl_a > 0.0) {
+      const double pfl = cp.p_fl_a * pow(rr, cp.p_fl_n);
+      if (p < pfl) { p = pfl; floored = true; st[4] += 1; }
+    }
+    if (cp.w_max > 0.0) {
+      double ul[3];
+      m.lower(u, ul);
+      const double uu = ul[0] * u[0] + ul[1] * u[1] + ul[2] * u[2];
+      const double wcur = sqrt(1.0 + uu);
+      if (wcur > cp.w_max) {
+        const double fac = sqrt((cp.w_max * cp.w_max - 1.0) / uu);
+        u[0] *= fac; u[1] *= fac; u[2] *= fac;
+        floored = true;
+        st[5] += 1;
+      }
+    }
+  }
+  prim[P_RHO * G.field + c] = rho;
+  prim[P_P * G.field + c] = p;
+  prim[P_U1 * G.field + c] = u[0];
+  prim[P_U2 * G.field + c] = u[1];
+  prim[P_U3 * G.field + c] = u[2];
+  prim[P_B1 * G.field + c] = B[0];
+  prim[P_B2 * G.field + c] = B[1];
+  prim[P_B3 * G.field + c] = B[2];
+  if (floored || want_cfl) {
+    PState<double> s;
+    s.rho = rho; s.p = p;
+    for (int q = 0; q < 3; ++q) { s.u[q] = u[q]; s.B[q] = B[q]; }
+    make_state(s, m, G.gam);
+    if (floored) {
+      double cc[5];
+      cons_of(s, m, cc);
+      for (int q = 0; q < 5; ++q) cons[(long)q * G.field + c] = cc[q];
+    }
+    if (want_cfl) {
+      double tot = 0.0;
+      for (int d = 0; d < 3; ++d) {
+        double lp, lm;
+        speeds_of(s, m, d, G.gam, lp, lm);
+        tot = tot + fmax(fabs(lp), fabs(lm)) / G.dx[d];
+      }
+      cfl_v = tot;
+    }
+  }
+  return false;
+}
+
+// Per-block partials of the counters (C2P_NSTAT each, written at slot) and,
+// with cfl_partials, of the CFL speed sum (256-thread workgroups).
+__device__ __forceinline__ void c2p_block_partials(const long long st[8], double cfl_v,
+                                                   long long* __restrict__ partials,
+                                                   double* __restrict__ cfl_partials, int slot) {
+  if (cfl_partials) {
+    __shared__ double shc[4];
+    const double w = wave_max(cfl_v);
+    if ((threadIdx.x & 63) == 0) shc[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) cfl_partials[slot] = fmax(fmax(shc[0], shc[1]), fmax(shc[2], shc[3]));
+  }
+  __shared__ long long sh[4][8];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  long long rr[8];
+  for (int q = 0; q < 8; ++q) rr[q] = q == 2 ? wave_max_ll(st[q]) : wave_sum_ll(st[q]);
+  if (lane == 0)
+    for (int q = 0; q < 8; ++q) sh[wv][q] = rr[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int w = 0; w < 4; ++w)
+      for (int q = 0; q < 8; ++q) o[q] = q == 2 ? (sh[w][q] > o[q] ? sh[w][q] : o[q]) : o[q] + sh[w][q];
+    long long* dst = partials + (long)slot * C2P_NSTAT;
+    for (int q = 0; q < 8; ++q) dst[q] = o[q];
+  }
+}
+
+}  // namespace grmhd

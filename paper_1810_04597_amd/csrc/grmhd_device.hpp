@@ -389,15 +389,19 @@ struct NewtonOut {
   T rho, p, u[3];
   int iters;
   bool ok;
-  bool alt;     // the iteration started from y_alt
+  bool alt;       // the iteration started from y_alt
+  bool deferred;  // stopped after the first residual (defer_tol)
 };
 
 // Safeguarded Newton inversion in y = rho h W^2 (undensitised D, S_i, tau, B^i).
 // y_alt > 0: a second candidate start; the iteration starts from whichever of
 // y0 and y_alt has the smaller |residual| (one extra residual evaluation).
+// defer_tol > 0: when the first residual, relative to the magnitude of its
+// terms, exceeds defer_tol (or v^2 >= 1 there), stop at once with
+// deferred = true and nothing else set.
 template <typename T, class MET>
 GR_HD NewtonOut<T> newton(T dd, const T S[3], T tau, const T B[3], const MET& m, T gam,
-                          T y0, double tol, int maxit, T y_alt = T(-1)) {
+                          T y0, double tol, int maxit, T y_alt = T(-1), double defer_tol = 0.0) {
   using std::isfinite;
   NewtonOut<T> o;
   const T utot = tau + dd;
@@ -415,6 +419,7 @@ GR_HD NewtonOut<T> newton(T dd, const T S[3], T tau, const T B[3], const MET& m,
   T y = y0;
   if (!(y > a && y < bb)) y = 0.5 * (a + bb);
   o.alt = false;
+  o.deferred = false;
   if (valid && y_alt > a && y_alt < bb) {
     // residual of the energy equation at a candidate start; +inf where v^2 >= 1
     auto resid = [&](T yc) {
@@ -448,6 +453,12 @@ GR_HD NewtonOut<T> newton(T dd, const T S[3], T tau, const T B[3], const MET& m,
       const T dp = gf * ((1.0 - v2) - y * dv2 + dd * dv2 / (2.0 * sq));
       const T fp = 1.0 - dp + 0.5 * b2 * dv2 + sb2 / y3;
       const T fabs_ = y + fabs(p) + 0.5 * b2 * (1.0 + v2) + 0.5 * sb2 / yy + utot;
+      if (defer_tol > 0.0 && it == 1 && (bad || !(fabs(f) <= T(defer_tol) * fabs_))) {
+        o.deferred = true;
+        o.ok = false;
+        o.iters = 0;
+        return o;
+      }
       if (!bad && fabs(f) <= EPS4 * fabs_) { conv = true; break; }
       const bool below = bad || (f < 0.0);
       if (below) a = y; else bb = y;

@@ -12,10 +12,14 @@ struct C2PParams {
   int guess;            // 0 warm, 1 cold, 2 learned
   int coord;            // 0 Cartesian, 1 log-spherical (r = exp(x^1))
   double rho_fl_a, rho_fl_n, p_fl_a, p_fl_n, w_max;
+  double defer_tol;     // learned guess: relative warm residual above which a zone is deferred
 };
 
 // Per-block partial results of the inversion (reduced on the device).
-constexpr int C2P_NSTAT = 8;   // fail, iters_sum, iters_max, floor_rho, floor_p, wcap, learned fallback, spare
+constexpr int C2P_NSTAT = 8;   // fail, iters_sum, iters_max, floor_rho, floor_p, wcap, learned fallback, learned chosen
+// Workgroups of the learned-guess pass over the deferred zones; its per-block
+// partials follow the inversion's nblk partials.
+constexpr int C2P_LIST_BLOCKS = 512;
 constexpr int DIAG_NSUM = 8;   // plain sums of the 8 conserved fields
 constexpr int DIAG_NMAX = 8;   // max|divB|, -rho_min, rho_max, -p_min, p_max, w_max, max|B|, nonfinite
 
@@ -36,9 +40,14 @@ void launch_update(const Geom& G, bool flat, int mode, const double* prim, doubl
                    const double* tab, double a, double b, double dt_host, const double* d_dt,
                    double* out, int save_n, hipStream_t s);
 void launch_advance(double* d_dt, const double* src, double dt_host, hipStream_t s);
+// Inversion of all interior zones; per-block counters into partials[0, nblk),
+// CFL partials (nullable) into cfl_partials[0, nblk).  list != nullptr: defer
+// zones with a poor warm start into list / list_n (learned guess).
 void launch_c2p(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
-                const double* tab, long long* stat_partials, hipStream_t s, const double* y0_learned,
-                double* cfl_partials = nullptr, double cfl = 0.0, double* d_next_dt = nullptr);
+                const double* tab, long long* partials, double* cfl_partials, int* list, int* list_n,
+                hipStream_t s);
+void launch_zero_int(int* p, hipStream_t s);
+void launch_dt_final(const double* cfl_partials, int nb, double cfl, double* d_dt, hipStream_t s);
 void launch_prim2cons(const Geom& G, bool flat, double* prim, double* cons, const double* tab,
                       hipStream_t s);
 void launch_cfl(const Geom& G, bool flat, const double* prim, const double* tab, double cfl,

@@ -86,7 +86,11 @@ void mlp_launch_reduce(const MlpState& M, int nwaves, int mode, float* grad, flo
                        hipStream_t s);
 void mlp_launch_to_bf16(const MlpState& M, hipStream_t s);
 void mlp_launch_forward(const MlpState& M, const float* feat, long n, float* out, hipStream_t s);
-void mlp_launch_guess(const Geom& G, bool flat, const double* cons, const double* tab,
-                      const MlpState& M, double* y0, hipStream_t s);
+// Learned-guess pass over the zones the inversion deferred (list / list_n):
+// network guess and inversion; per-block counters and CFL partials (nullable)
+// at [0, C2P_LIST_BLOCKS) of partials / cfl_partials.
+void mlp_launch_c2p_list(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
+                         const double* tab, const MlpState& M, const int* list, const int* list_n,
+                         long long* partials, double* cfl_partials, hipStream_t s);
 
 }  // namespace grmhd

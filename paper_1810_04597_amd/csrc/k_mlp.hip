@@ -16,6 +16,7 @@
 // the inversion.
 #include "grmhd_device.hpp"
 #include "grmhd_kernels.hpp"
+#include "grmhd_c2p.hpp"
 #include "grmhd_mlp.hpp"
 
 namespace grmhd {
@@ -552,93 +553,107 @@ __global__ __launch_bounds__(256) void k_forward(const unsigned short* __restric
   }
 }
 
-// Per-zone Newton guess y0 for the inversion from the conserved state.
-// 256 threads = 4 waves; each wave: 64 zones = 4 tiles of 16 samples.
+// Standardised network inputs of interior zone t from its conserved state
+// (mlp_features in single precision with the hardware log2 / reciprocal
+// square root: the inputs are rounded to bfloat16 next).  Zero when !valid.
 template <class MET>
-__global__ __launch_bounds__(256) void k_guess(Geom G, const double* __restrict__ cons,
-                                               const double* __restrict__ tab,
-                                               const unsigned short* __restrict__ wb,
-                                               const float* __restrict__ wf,
-                                               const float* __restrict__ norm,
-                                               double* __restrict__ y0out) {
-  const long t = flat_thread();
-  const long total = (long)G.n[0] * G.n[1] * G.n[2];
-  const bool live = t < total;
-  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
-  float f[8];
-  double utot = 1.0;
-  long c = 0;
+__device__ __forceinline__ void zone_features(const Geom& G, const double* __restrict__ cons,
+                                              const double* __restrict__ tab,
+                                              const float* __restrict__ norm, long t, bool valid,
+                                              float f[8], double& utot) {
   for (int q = 0; q < 8; ++q) f[q] = 0.f;
-  if (live) {
-    int i = (int)(t % G.n[0]);
-    const long r = t / G.n[0];
-    int j = (int)(r % G.n[1]);
-    int k = (int)(r / G.n[1]);
-    c = G.idx(i, j, k);
-    MET m;
-    if constexpr (!MET::flat) m.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
-    double B[3], fd6[6];
-    for (int d = 0; d < 3; ++d) {
-      const double* fp = cons + (long)(C_BF1 + d) * G.field + c;
-      const long st = G.stride(d);
-      for (int s = 0; s < 6; ++s) fd6[s] = fp[(s - 3) * st];
-      B[d] = m.undens(fd_interp(fd6));
+  utot = 1.0;
+  if (!valid) return;
+  int i, j, k;
+  zone_of(G, t, i, j, k);
+  const long c = G.idx(i, j, k);
+  MET m;
+  if constexpr (!MET::flat) m.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
+  double B[3];
+  centred_b(G, cons, c, m, B);
+  const double dd = m.undens(cons[C_D * G.field + c]);
+  const double S[3] = {m.undens(cons[C_S1 * G.field + c]), m.undens(cons[C_S2 * G.field + c]),
+                       m.undens(cons[C_S3 * G.field + c])};
+  const double tau = m.undens(cons[C_TAU * G.field + c]);
+  utot = tau + dd;
+  double Sh[3], Bh[3];
+  frame_components(m, S, B, Sh, Bh);
+  const float fdd = (float)dd, fe = (float)utot;
+  const float ie = __fdividef(1.f, fe), ise = __frsqrt_rn(fe);
+  float fr[8];
+  fr[0] = __log10f(fdd);
+  fr[1] = __log10f(__fdividef((float)tau, fdd));
+  for (int q = 0; q < 3; ++q) {
+    fr[2 + q] = (float)Sh[q] * ie;
+    fr[5 + q] = (float)Bh[q] * ise;
+  }
+  for (int q = 0; q < 8; ++q) {
+    const float v = fr[q];
+    f[q] = isfinite(v) ? (v - norm[NM_FMEAN + q]) * __fdividef(1.f, norm[NM_FSTD + q]) : 0.f;
+  }
+}
+
+// Learned-guess pass over the zones the inversion deferred (their warm start
+// had a large residual).  Each wavefront takes 64 list entries, evaluates the
+// network for them on the matrix cores (four 16-sample tiles, features of
+// lane l = sample l), and inverts each zone with the network's
+// y0 = U 10^{t0} as the second candidate start.  Per-block counters and CFL
+// partials go to slot blockIdx.x of partials / cfl_partials.
+template <class MET>
+__global__ __launch_bounds__(256) void k_c2p_list(Geom G, C2PParams cp, double* __restrict__ prim,
+                                                  double* __restrict__ cons,
+                                                  const double* __restrict__ tab,
+                                                  const unsigned short* __restrict__ wb,
+                                                  const float* __restrict__ wf,
+                                                  const float* __restrict__ norm,
+                                                  const int* __restrict__ list,
+                                                  const int* __restrict__ list_n,
+                                                  long long* __restrict__ partials,
+                                                  double* __restrict__ cfl_partials) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
+  const long n = *list_n;
+  const long nwaves = (long)gridDim.x * 4;
+  long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double cfl_v = 0.0;
+  for (long base = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; base < n; base += nwaves * 64) {
+    const long idx = base + lane;
+    const bool valid = idx < n;
+    const long t = valid ? (long)list[idx] : 0;
+    float f[8];
+    double utot;
+    zone_features<MET>(G, cons, tab, norm, t, valid, f, utot);
+    bf4 xb[4];
+#pragma unroll
+    for (int tile = 0; tile < 4; ++tile) {
+      const int src = 16 * tile + lr;
+      f4 xv;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float lo = __shfl(f[r], src, 64);
+        const float hi = __shfl(f[4 + r], src, 64);
+        xv[r] = lg == 0 ? lo : (lg == 1 ? hi : 0.f);
+      }
+      xb[tile] = pack(xv);
     }
-    const double dd = m.undens(cons[C_D * G.field + c]);
-    const double S[3] = {m.undens(cons[C_S1 * G.field + c]), m.undens(cons[C_S2 * G.field + c]),
-                         m.undens(cons[C_S3 * G.field + c])};
-    const double tau = m.undens(cons[C_TAU * G.field + c]);
-    utot = tau + dd;
-    double Sh[3], Bh[3];
-    frame_components(m, S, B, Sh, Bh);
-    // the features of mlp_features in single precision with the hardware
-    // log2 / reciprocal square root (they are rounded to bfloat16 next)
-    const float fdd = (float)dd, fe = (float)utot;
-    const float ie = __fdividef(1.f, fe), ise = __frsqrt_rn(fe);
-    float fr[8];
-    fr[0] = __log10f(fdd);
-    fr[1] = __log10f(__fdividef((float)tau, fdd));
-    for (int q = 0; q < 3; ++q) {
-      fr[2 + q] = (float)Sh[q] * ie;
-      fr[5 + q] = (float)Bh[q] * ise;
+    f4 outs[4];
+    forward4(wb, wf, xb, outs);
+    // output 0 of this lane's sample: tile lane/16, row 0 of lane lane%16
+    float o0 = 0.f;
+#pragma unroll
+    for (int tile = 0; tile < 4; ++tile) {
+      const float v = __shfl(outs[tile][0], lr, 64);
+      if (lg == tile) o0 = v;
     }
-    for (int q = 0; q < 8; ++q) {
-      const float v = fr[q];
-      f[q] = isfinite(v) ? (v - norm[NM_FMEAN + q]) * __fdividef(1.f, norm[NM_FSTD + q]) : 0.f;
+    if (valid) {
+      const float t0 = o0 * norm[NM_TSTD + 0] + norm[NM_TMEAN + 0];
+      const double y0 = utot * (double)__exp10f(t0);
+      double cv = 0.0;
+      c2p_zone<MET>(G, cp, prim, cons, tab, t, isfinite(y0) ? y0 : -1.0, 0.0, cfl_partials != nullptr,
+                    st, cv);
+      cfl_v = fmax(cfl_v, cv);
     }
   }
-  f4 outs[4];
-  bf4 xb[4];
-#pragma unroll
-  for (int tile = 0; tile < 4; ++tile) {
-    const int src = 16 * tile + lr;
-    f4 xv;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float lo = __shfl(f[r], src, 64);
-      const float hi = __shfl(f[4 + r], src, 64);
-      xv[r] = lg == 0 ? lo : (lg == 1 ? hi : 0.f);
-    }
-    xb[tile] = pack(xv);
-  }
-  forward4(wb, wf, xb, outs);
-  // outputs of this lane's zone: tile = lane/16, sample = lane%16:
-  // outputs 0..3 from lane (lane%16), r = 0..3; output 4 from lane 16 + lane%16, r = 0
-  float o5[5];
-#pragma unroll
-  for (int tile = 0; tile < 4; ++tile) {
-    float v[5];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] = __shfl(outs[tile][r], lr, 64);
-    v[4] = __shfl(outs[tile][0], 16 + lr, 64);
-    if (lg == tile)
-      for (int q = 0; q < 5; ++q) o5[q] = v[q];
-  }
-  if (!live) return;
-  // guess from the first output: y0 = U 10^{t0}
-  const float t0 = o5[0] * norm[NM_TSTD + 0] + norm[NM_TMEAN + 0];
-  const double y0 = utot * (double)__exp10f(t0);
-  y0out[c] = isfinite(y0) ? y0 : -1.0;
+  c2p_block_partials(st, cfl_v, partials, cfl_partials, blockIdx.x);
 }
 
 }  // namespace mlp
@@ -689,15 +704,15 @@ void mlp_launch_forward(const MlpState& M, const float* feat, long n, float* out
   hipLaunchKernelGGL(mlp::k_forward, dim3((unsigned)nb), dim3(256), 0, s, M.wb, M.wf, M.norm, feat, n, out);
 }
 
-void mlp_launch_guess(const Geom& G, bool flat, const double* cons, const double* tab,
-                      const MlpState& M, double* y0, hipStream_t s) {
-  const unsigned nb = zone_blocks(G);
+void mlp_launch_c2p_list(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
+                         const double* tab, const MlpState& M, const int* list, const int* list_n,
+                         long long* partials, double* cfl_partials, hipStream_t s) {
   if (flat)
-    hipLaunchKernelGGL(mlp::k_guess<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, cons, tab, M.wb,
-                       M.wf, M.norm, y0);
+    hipLaunchKernelGGL(mlp::k_c2p_list<FlatMet<double>>, dim3(C2P_LIST_BLOCKS), dim3(256), 0, s, G, cp,
+                       prim, cons, tab, M.wb, M.wf, M.norm, list, list_n, partials, cfl_partials);
   else
-    hipLaunchKernelGGL(mlp::k_guess<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, cons, tab, M.wb,
-                       M.wf, M.norm, y0);
+    hipLaunchKernelGGL(mlp::k_c2p_list<TabMet<double>>, dim3(C2P_LIST_BLOCKS), dim3(256), 0, s, G, cp,
+                       prim, cons, tab, M.wb, M.wf, M.norm, list, list_n, partials, cfl_partials);
 }
 
 }  // namespace grmhd

@@ -14,43 +14,13 @@
 //            residual or |dy| <= tol y; failed zones keep their primitives.
 #include "grmhd_device.hpp"
 #include "grmhd_kernels.hpp"
+#include "grmhd_c2p.hpp"
 
 namespace grmhd {
 
 static inline unsigned nblk(long total) { return (unsigned)((total + 255) / 256); }
 
-__device__ __forceinline__ void zone_of(const Geom& G, long t, int& i, int& j, int& k) {
-  i = (int)(t % G.n[0]);
-  const long r = t / G.n[0];
-  j = (int)(r % G.n[1]);
-  k = (int)(r / G.n[1]);
-}
-
 // ------------------------------------------------------------------ block reductions
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ long long wave_sum_ll(long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ long long wave_max_ll(long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    long long w = __shfl_xor(v, o, 64);
-    v = w > v ? w : v;
-  }
-  return v;
-}
-
 // ------------------------------------------------------------------ metric sources
 template <class MET>
 __device__ __forceinline__ void sources_of(const PState<double>& s, const MET& m,
@@ -301,158 +271,26 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
   }
 }
 
-// ------------------------------------------------------------------ centred B
-template <class MET>
-__device__ __forceinline__ void centred_b(const Geom& G, const double* __restrict__ cons, long c,
-                                          const MET& m, double B[3]) {
-  double f[6];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double* fp = cons + (long)(C_BF1 + d) * G.field + c;
-    const long st = G.stride(d);
-#pragma unroll
-    for (int s = 0; s < 6; ++s) f[s] = fp[(s - 3) * st];
-    B[d] = m.undens(fd_interp(f));
-  }
-}
-
+// ------------------------------------------------------------------ inversion
+// With list != nullptr (learned guess) zones whose warm start has a relative
+// residual above cp.defer_tol are left untouched and appended to list (their
+// order is irrelevant: each is inverted on its own in the learned-guess pass).
 template <class MET>
 __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __restrict__ prim,
                                              double* __restrict__ cons,
                                              const double* __restrict__ tab,
                                              long long* __restrict__ partials,
-                                             const double* __restrict__ y0_learned,
-                                             double* __restrict__ cfl_partials) {
+                                             double* __restrict__ cfl_partials,
+                                             int* __restrict__ list, int* __restrict__ list_n) {
   const long t = flat_thread();
-  const bool live = t < (long)G.n[0] * G.n[1] * G.n[2];
   long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double cfl_v = 0.0;
-  if (live) {
-    int i, j, k;
-    zone_of(G, t, i, j, k);
-    const long c = G.idx(i, j, k);
-    MET m;
-    if constexpr (!MET::flat) m.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
-    double B[3];
-    centred_b(G, cons, c, m, B);
-    const double dd = m.undens(cons[C_D * G.field + c]);
-    const double S[3] = {m.undens(cons[C_S1 * G.field + c]), m.undens(cons[C_S2 * G.field + c]),
-                         m.undens(cons[C_S3 * G.field + c])};
-    const double tau = m.undens(cons[C_TAU * G.field + c]);
-    double rho = prim[P_RHO * G.field + c];
-    double p = prim[P_P * G.field + c];
-    double u[3] = {prim[P_U1 * G.field + c], prim[P_U2 * G.field + c], prim[P_U3 * G.field + c]};
-    double ywarm;
-    {
-      double ul[3];
-      m.lower(u, ul);
-      const double uu = ul[0] * u[0] + ul[1] * u[1] + ul[2] * u[2];
-      const double h = 1.0 + G.gam / (G.gam - 1.0) * p / rho;
-      ywarm = rho * h * (1.0 + uu);
-    }
-    // learned guess: a second candidate start next to the warm one (the
-    // smaller residual wins); the warm start is rerun if a learned start fails
-    const double y0 = cp.guess == 1 ? G.gam * (tau + dd) : ywarm;
-    const double yalt = cp.guess == 2 ? y0_learned[c] : -1.0;
-    NewtonOut<double> r = newton<double>(dd, S, tau, B, m, G.gam, y0, cp.tol, cp.maxit, yalt);
-    st[7] = r.alt ? 1 : 0;
-    if (r.alt && !r.ok) {
-      const int it0 = r.iters;
-      r = newton<double>(dd, S, tau, B, m, G.gam, ywarm, cp.tol, cp.maxit);
-      r.iters += it0;
-      st[6] = 1;
-    }
-    if (r.ok) {
-      rho = r.rho;
-      p = r.p;
-      u[0] = r.u[0]; u[1] = r.u[1]; u[2] = r.u[2];
-    }
-    st[0] = r.ok ? 0 : 1;
-    st[1] = r.iters;
-    st[2] = r.iters;
-    bool floored = false;
-    if (cp.rho_fl_a > 0.0 || cp.p_fl_a > 0.0 || cp.w_max > 0.0) {
-      const double rr = cp.coord == 1 ? exp(G.x0[0] + (i + 0.5) * G.dx[0]) : 1.0;
-      if (!r.ok) {
-        // failed zone -> atmosphere at rest
-        rho = cp.rho_fl_a * pow(rr, cp.rho_fl_n);
-        p = cp.p_fl_a * pow(rr, cp.p_fl_n);
-        u[0] = u[1] = u[2] = 0.0;
-        floored = true;
-      }
-      if (cp.rho_fl_a > 0.0) {
-        const double rfl = cp.rho_fl_a * pow(rr, cp.rho_fl_n);
-        if (rho < rfl) { rho = rfl; floored = true; st[3] = 1; }
-      }
-      if (cp.p_fl_a > 0.0) {
-        const double pfl = cp.p_fl_a * pow(rr, cp.p_fl_n);
-        if (p < pfl) { p = pfl; floored = true; st[4] = 1; }
-      }
-      if (cp.w_max > 0.0) {
-        double ul[3];
-        m.lower(u, ul);
-        const double uu = ul[0] * u[0] + ul[1] * u[1] + ul[2] * u[2];
-        const double wcur = sqrt(1.0 + uu);
-        if (wcur > cp.w_max) {
-          const double fac = sqrt((cp.w_max * cp.w_max - 1.0) / uu);
-          u[0] *= fac; u[1] *= fac; u[2] *= fac;
-          floored = true;
-          st[5] = 1;
-        }
-      }
-    }
-    prim[P_RHO * G.field + c] = rho;
-    prim[P_P * G.field + c] = p;
-    prim[P_U1 * G.field + c] = u[0];
-    prim[P_U2 * G.field + c] = u[1];
-    prim[P_U3 * G.field + c] = u[2];
-    prim[P_B1 * G.field + c] = B[0];
-    prim[P_B2 * G.field + c] = B[1];
-    prim[P_B3 * G.field + c] = B[2];
-    if (floored || cfl_partials) {
-      PState<double> s;
-      s.rho = rho; s.p = p;
-      for (int q = 0; q < 3; ++q) { s.u[q] = u[q]; s.B[q] = B[q]; }
-      make_state(s, m, G.gam);
-      if (floored) {
-        double cc[5];
-        cons_of(s, m, cc);
-        for (int q = 0; q < 5; ++q) cons[(long)q * G.field + c] = cc[q];
-      }
-      if (cfl_partials) {
-        double tot = 0.0;
-        for (int d = 0; d < 3; ++d) {
-          double lp, lm;
-          speeds_of(s, m, d, G.gam, lp, lm);
-          tot = tot + fmax(fabs(lp), fabs(lm)) / G.dx[d];
-        }
-        cfl_v = tot;
-      }
-    }
+  if (t < (long)G.n[0] * G.n[1] * G.n[2]) {
+    const double defer = list ? cp.defer_tol : 0.0;
+    if (c2p_zone<MET>(G, cp, prim, cons, tab, t, -1.0, defer, cfl_partials != nullptr, st, cfl_v))
+      list[atomicAdd(list_n, 1)] = (int)t;
   }
-  if (cfl_partials) {
-    __shared__ double shc[4];
-    const double w = wave_max(cfl_v);
-    if ((threadIdx.x & 63) == 0) shc[threadIdx.x >> 6] = w;
-    __syncthreads();
-    if (threadIdx.x == 0) cfl_partials[blockIdx.x] = fmax(fmax(shc[0], shc[1]), fmax(shc[2], shc[3]));
-  }
-  // per-block partials: fail, iters_sum, iters_max, floor_rho, floor_p, wcap,
-  // learned fallback, learned start chosen
-  __shared__ long long sh[4][8];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  long long rr[8];
-  for (int q = 0; q < 8; ++q) rr[q] = q == 2 ? wave_max_ll(st[q]) : wave_sum_ll(st[q]);
-  if (lane == 0)
-    for (int q = 0; q < 8; ++q) sh[wv][q] = rr[q];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    long long o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int w = 0; w < 4; ++w)
-      for (int q = 0; q < 8; ++q) o[q] = q == 2 ? (sh[w][q] > o[q] ? sh[w][q] : o[q]) : o[q] + sh[w][q];
-    long long* dst = partials + (long)blockIdx.x * C2P_NSTAT;
-    for (int q = 0; q < 8; ++q) dst[q] = o[q];
-  }
+  c2p_block_partials(st, cfl_v, partials, cfl_partials, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_reduce_stats(const long long* __restrict__ partials, int nb,
@@ -840,17 +678,25 @@ void launch_advance(double* d_dt, const double* src, double dt_host, hipStream_t
 }
 
 void launch_c2p(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
-                const double* tab, long long* partials, hipStream_t s, const double* y0_learned,
-                double* cfl_partials, double cfl, double* d_next_dt) {
+                const double* tab, long long* partials, double* cfl_partials, int* list, int* list_n,
+                hipStream_t s) {
   const unsigned nb = zone_blocks(G);
   if (flat)
     hipLaunchKernelGGL(k_c2p<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab,
-                       partials, y0_learned, cfl_partials);
+                       partials, cfl_partials, list, list_n);
   else
     hipLaunchKernelGGL(k_c2p<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab,
-                       partials, y0_learned, cfl_partials);
-  if (cfl_partials)
-    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, cfl_partials, (int)nb, cfl, d_next_dt);
+                       partials, cfl_partials, list, list_n);
+}
+
+__global__ void k_zero_int(int* __restrict__ p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = 0;
+}
+
+void launch_zero_int(int* p, hipStream_t s) { hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, p); }
+
+void launch_dt_final(const double* cfl_partials, int nb, double cfl, double* d_dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, cfl_partials, nb, cfl, d_dt);
 }
 
 void launch_reduce_stats(const long long* partials, int nb, long long* out, hipStream_t s) {
