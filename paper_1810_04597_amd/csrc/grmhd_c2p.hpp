@@ -170,7 +170,21 @@ __device__ __forceinline__ bool c2p_zone(const Geom& G, const C2PParams& cp, dou
 }
 
 // Per-block partials of the counters (C2P_NSTAT each, written at slot) and,
-// with cfl_partials, of the CFL speed sum (256-thread workgroups).
+// with cfl_partials, of the CFL speed sum (256-thread workgroups).  PACKED
+// (one zone per thread, counters 0/1 and at most 2000 iterations): the six
+// 0/1 counters go in 16-bit fields of two 64-bit words and the iteration sum
+// in the upper half of the second, so a wavefront reduces two words and one
+// 32-bit maximum instead of eight words.
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
+template <bool PACKED>
 __device__ __forceinline__ void c2p_block_partials(const long long st[8], double cfl_v,
                                                    long long* __restrict__ partials,
                                                    double* __restrict__ cfl_partials, int slot) {
@@ -184,7 +198,16 @@ __device__ __forceinline__ void c2p_block_partials(const long long st[8], double
   __shared__ long long sh[4][8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   long long rr[8];
-  for (int q = 0; q < 8; ++q) rr[q] = q == 2 ? wave_max_ll(st[q]) : wave_sum_ll(st[q]);
+  if constexpr (PACKED) {
+    const long long w0 = st[0] | (st[3] << 16) | (st[4] << 32) | (st[5] << 48);
+    const long long w1 = st[6] | (st[7] << 16) | (st[1] << 32);
+    const long long s0 = wave_sum_ll(w0), s1 = wave_sum_ll(w1);
+    rr[0] = s0 & 0xffff; rr[3] = (s0 >> 16) & 0xffff; rr[4] = (s0 >> 32) & 0xffff; rr[5] = (s0 >> 48) & 0xffff;
+    rr[6] = s1 & 0xffff; rr[7] = (s1 >> 16) & 0xffff; rr[1] = s1 >> 32;
+    rr[2] = wave_max_i((int)st[2]);
+  } else {
+    for (int q = 0; q < 8; ++q) rr[q] = q == 2 ? wave_max_ll(st[q]) : wave_sum_ll(st[q]);
+  }
   if (lane == 0)
     for (int q = 0; q < 8; ++q) sh[wv][q] = rr[q];
   __syncthreads();

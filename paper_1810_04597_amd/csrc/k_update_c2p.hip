@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
     if (c2p_zone<MET>(G, cp, prim, cons, tab, t, -1.0, defer, cfl_partials != nullptr, st, cfl_v))
       list[atomicAdd(list_n, 1)] = (int)t;
   }
-  c2p_block_partials(st, cfl_v, partials, cfl_partials, blockIdx.x);
+  c2p_block_partials<true>(st, cfl_v, partials, cfl_partials, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_reduce_stats(const long long* __restrict__ partials, int nb,
