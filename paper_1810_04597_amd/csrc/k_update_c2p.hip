@@ -165,9 +165,7 @@ __device__ __forceinline__ void rk_store(double* __restrict__ cons, double* __re
 // segment instead of six times; x^1 and x^2 stencils are read per plane.
 constexpr int KZ = 16;
 
-// PART: 0 all eight fields, 1 the five hydro fields, 2 the three face fields
-// (the two halves read disjoint operands, so splitting moves no extra bytes).
-template <class MET, int PART>
+template <class MET>
 __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restrict__ prim,
                                                    double* __restrict__ cons,
                                                    double* __restrict__ cons_n,
@@ -194,32 +192,23 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
   // windows along x^3: w[s] holds stored index k - 3 + s
   double wf[5][6], w1[6], w2[6];
   long c = G.idx(i, j, k0);
-  constexpr bool HYD = PART != 2, IND = PART != 1;
 #pragma unroll
   for (int s = 0; s < 5; ++s) {
     const long cs = c + (s - 3) * sz;
-    if (HYD) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q) wf[q][s] = fz[(long)q * G.field + cs];
-    }
-    if (IND) {
-      w1[s] = e1[cs];
-      w2[s] = e2[cs];
-    }
+    for (int q = 0; q < 5; ++q) wf[q][s] = fz[(long)q * G.field + cs];
+    w1[s] = e1[cs];
+    w2[s] = e2[cs];
   }
   for (int k = k0; k < k1; ++k, c += sz) {
     const long cn = c + 2 * sz;
-    if (HYD) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q) wf[q][5] = fz[(long)q * G.field + cn];
-    }
-    if (IND) {
-      w1[5] = e1[cn];
-      w2[5] = e2[cn];
-    }
+    for (int q = 0; q < 5; ++q) wf[q][5] = fz[(long)q * G.field + cn];
+    w1[5] = e1[cn];
+    w2[5] = e2[cn];
     double f[6];
 #pragma unroll
-    for (int q = 0; q < (HYD ? 5 : 0); ++q) {
+    for (int q = 0; q < 5; ++q) {
       double L = 0.0;
       const double* fx = flux + (long)q * G.field + c;
       const double* fy = flux + (5L + q) * G.field + c;
@@ -233,21 +222,21 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
       rk_store(cons, cons_n, (long)q * G.field + c, a, b, dt, L, save_n);
     }
     // B^1: -D_2 E_3 + D_3 E_2
-    if (IND) {
+    {
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sy];
       const double L = -fd_deriv(f, idx1) + fd_deriv(w2, idx2);
       rk_store(cons, cons_n, (long)C_BF1 * G.field + c, a, b, dt, L, save_n);
     }
     // B^2: -D_3 E_1 + D_1 E_3
-    if (IND) {
+    {
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sx];
       const double L = -fd_deriv(w1, idx2) + fd_deriv(f, idx0);
       rk_store(cons, cons_n, (long)C_BF2 * G.field + c, a, b, dt, L, save_n);
     }
     // B^3: -D_1 E_2 + D_2 E_1
-    if (IND) {
+    {
       double g2[6];
 #pragma unroll
       for (int s = 0; s < 6; ++s) {
@@ -259,14 +248,10 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
     }
 #pragma unroll
     for (int s = 0; s < 5; ++s) {
-      if (HYD) {
 #pragma unroll
-        for (int q = 0; q < 5; ++q) wf[q][s] = wf[q][s + 1];
-      }
-      if (IND) {
-        w1[s] = w1[s + 1];
-        w2[s] = w2[s + 1];
-      }
+      for (int q = 0; q < 5; ++q) wf[q][s] = wf[q][s + 1];
+      w1[s] = w1[s + 1];
+      w2[s] = w2[s + 1];
     }
   }
 }
@@ -654,7 +639,7 @@ void launch_update(const Geom& G, bool flat, int mode, const double* prim, doubl
   if (flat && mode == 0) {
     const long nseg = (G.n[2] + KZ - 1) / KZ;
     const long total = (long)G.n[0] * G.n[1] * nseg;
-    hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 0>), dim3(nblk(total)), dim3(256), 0, s, G, prim,
+    hipLaunchKernelGGL(k_update_zm<FlatMet<double>>, dim3(nblk(total)), dim3(256), 0, s, G, prim,
                        cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, save_n);
   } else if (flat)
     hipLaunchKernelGGL(k_update<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
