@@ -62,6 +62,7 @@ struct grmhd_grid {
   double* d_dt = nullptr;        // [0] dt of the current step, [1] time, [2] CFL dt of the state
   bool next_dt_valid = false;    // d_dt[2] holds the CFL dt of the current primitives
   int* d_list_n = nullptr;       // number of zones deferred to the learned-guess pass
+  bool img = false;              // periodic box with n >= 2 NG: ghosts written as images
   double* d_part = nullptr;      // per-block partials (cfl, diagnostics)
   long long* d_spart = nullptr;  // per-block inversion statistics
   long long* d_stats = nullptr;  // reduced inversion statistics (8)
@@ -177,6 +178,7 @@ C2PParams c2p_params(const grmhd_grid_desc& d) {
   // relative residual above 1e-2 go to the network pass; elsewhere the warm
   // start is better than the network's accuracy
   cp.defer_tol = d.c2p_guess == GRMHD_GUESS_MLP ? 1e-2 : 0.0;
+  cp.img = 0;
   return cp;
 }
 
@@ -203,6 +205,9 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** 
   h->desc = *desc;
   make_layout(*desc, h->lay, h->G);
   for (int s = 0; s < 6; ++s) h->bc.bc[s] = desc->bc[s];
+  h->img = true;
+  for (int s = 0; s < 6; ++s) h->img = h->img && desc->bc[s] == GRMHD_BC_PERIODIC;
+  for (int d = 0; d < 3; ++d) h->img = h->img && desc->n[d] >= 2 * NG;
   h->stream = (hipStream_t)hip_stream;
   h->nblk = zone_blocks(h->G);
   // reduction partials: diagnostics (nblk x 16) and CFL (nblk + learned-pass blocks)
@@ -295,9 +300,11 @@ int grmhd_prim2cons(grmhd_grid* h) {
   return hip_check("prim2cons");
 }
 
-static void rhs_pieces(grmhd_grid* h) {
+// fill_ghosts: ghost fill of the primitives first (skipped inside rk_step on
+// a periodic box, where the inversion writes the ghost images itself).
+static void rhs_pieces(grmhd_grid* h, bool fill_ghosts = true) {
   const bool fp32 = h->desc.precision == GRMHD_FP32_FLUX;
-  h->timed(0, [&] { launch_bc_centred(h->G, h->bc, h->prim, NPRIM, h->stream); });
+  if (fill_ghosts) h->timed(0, [&] { launch_bc_centred(h->G, h->bc, h->prim, NPRIM, h->stream); });
   for (int d = 0; d < 3; ++d)
     h->timed(1 + d, [&] {
       launch_sweep(d, h->G, h->flat, fp32, h->prim, h->cons, h->tab, h->flux(), h->ctd(), h->stream);
@@ -366,16 +373,20 @@ int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used) {
   h->next_dt_valid = false;
   // U^n is saved by the first stage's update (a = 0, so U^(1) needs only U^n).
   const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
-  const C2PParams cp = c2p_params(h->desc);
+  // periodic box: the update and the inversion write the ghost images of
+  // what they produce, so the stage needs no separate ghost fills
+  C2PParams cp = c2p_params(h->desc);
+  const bool img = h->img && h->flat;
+  cp.img = img ? 1 : 0;
   for (int s = 0; s < 3; ++s) {
-    rhs_pieces(h);
+    rhs_pieces(h, !img);
     h->timed(7, [&] {
       launch_update(h->G, h->flat, 0, h->prim, h->cons, h->cons_n(), h->flux(), h->edges(), h->tab,
-                    A[s], B[s], dt, dt_src, nullptr, s == 0 ? 1 : 0, h->stream);
+                    A[s], B[s], dt, dt_src, nullptr, s == 0 ? 1 : 0, h->stream, img ? 1 : 0);
     });
     // dt and time are recorded once the last update has consumed d_dt[2]
     if (s == 2) h->timed(12, [&] { launch_advance(h->d_dt, dt_src, dt, h->stream); });
-    h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
+    if (!img) h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
     c2p_with_guess(h, cp, s == 2 && device_dt);
   }
   h->step += 1;
@@ -397,7 +408,8 @@ int grmhd_cons2prim(grmhd_grid* h, int64_t* n_fail, int strict) {
   if (rc) return rc;
   if (strict && !n_fail) return fail(GRMHD_EINVAL, "strict mode needs n_fail");
   h->next_dt_valid = false;
-  const C2PParams cp = c2p_params(h->desc);
+  C2PParams cp = c2p_params(h->desc);
+  cp.img = h->img && h->flat ? 1 : 0;   // leaves the primitive ghosts filled, as rk_step expects
   h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
   c2p_with_guess(h, cp);
   rc = hip_check("cons2prim");

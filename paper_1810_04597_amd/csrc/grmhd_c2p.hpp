@@ -39,6 +39,32 @@ __device__ __forceinline__ void zone_of(const Geom& G, long t, int& i, int& j, i
   k = (int)(r / G.n[1]);
 }
 
+// Periodic ghost images of interior element (i, j, k) when every direction is
+// periodic and every n >= 2 NG: per direction the offset 0 and, within NG of
+// a boundary, +-n.  Writes v[f] to field fields[f] of each image other than
+// the element itself (at most seven).
+template <int NF>
+__device__ __forceinline__ void write_images(const Geom& G, double* __restrict__ base, int i, int j,
+                                             int k, const int fields[NF], const double v[NF]) {
+  int off[3][2], cnt[3];
+  const int x[3] = {i, j, k};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    off[d][0] = 0;
+    cnt[d] = 1;
+    if (x[d] < NG) { off[d][1] = G.n[d]; cnt[d] = 2; }
+    else if (x[d] >= G.n[d] - NG) { off[d][1] = -G.n[d]; cnt[d] = 2; }
+  }
+  for (int a = 0; a < cnt[0]; ++a)
+    for (int b = 0; b < cnt[1]; ++b)
+      for (int c = 0; c < cnt[2]; ++c) {
+        if (a == 0 && b == 0 && c == 0) continue;
+        const long e = G.idx(i + off[0][a], j + off[1][b], k + off[2][c]);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) base[(long)fields[f] * G.field + e] = v[f];
+      }
+}
+
 // Centred field B^d = I_d(face field) / sqrt(gamma) at element c.
 template <class MET>
 __device__ __forceinline__ void centred_b(const Geom& G, const double* __restrict__ cons, long c,
@@ -146,6 +172,11 @@ __device__ __forceinline__ bool c2p_zone(const Geom& G, const C2PParams& cp, dou
   prim[P_B1 * G.field + c] = B[0];
   prim[P_B2 * G.field + c] = B[1];
   prim[P_B3 * G.field + c] = B[2];
+  if (cp.img) {
+    constexpr int pf[8] = {P_RHO, P_U1, P_U2, P_U3, P_P, P_B1, P_B2, P_B3};
+    const double pv[8] = {rho, u[0], u[1], u[2], p, B[0], B[1], B[2]};
+    write_images<8>(G, prim, i, j, k, pf, pv);
+  }
   if (floored || want_cfl) {
     PState<double> s;
     s.rho = rho; s.p = p;

@@ -13,6 +13,7 @@ struct C2PParams {
   int coord;            // 0 Cartesian, 1 log-spherical (r = exp(x^1))
   double rho_fl_a, rho_fl_n, p_fl_a, p_fl_n, w_max;
   double defer_tol;     // learned guess: relative warm residual above which a zone is deferred
+  int img;              // all directions periodic, n >= 2 NG: also write the ghost images
 };
 
 // Per-block partial results of the inversion (reduced on the device).
@@ -35,10 +36,12 @@ void launch_edge(int e, const Geom& G, bool flat, bool fp32, const double* cons,
                  const double* ctd, double* edges, hipStream_t s);
 // mode 0: RK combine into cons (needs cons_n, a, b, dt on device);
 // mode 1: write L into out (cons layout).
+// img (flat metric, mode 0): all directions periodic with n >= 2 NG; the new
+// face fields are also written to their ghost images (no separate face fill).
 void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* cons,
                    double* cons_n, const double* flux, const double* edges,
                    const double* tab, double a, double b, double dt_host, const double* d_dt,
-                   double* out, int save_n, hipStream_t s);
+                   double* out, int save_n, hipStream_t s, int img = 0);
 void launch_advance(double* d_dt, const double* src, double dt_host, hipStream_t s);
 // Inversion of all interior zones; per-block counters into partials[0, nblk),
 // CFL partials (nullable) into cfl_partials[0, nblk).  list != nullptr: defer

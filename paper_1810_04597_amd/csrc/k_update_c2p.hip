@@ -150,13 +150,16 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
   }
 }
 
-// RK stage store; save_n (first stage, a = 0): U^n is this value, saved
-__device__ __forceinline__ void rk_store(double* __restrict__ cons, double* __restrict__ cons_n, long o,
-                                         double a, double b, double dt, double L, int save_n) {
+// RK stage store; save_n (first stage, a = 0): U^n is this value, saved.
+// Returns the stored value.
+__device__ __forceinline__ double rk_store(double* __restrict__ cons, double* __restrict__ cons_n, long o,
+                                           double a, double b, double dt, double L, int save_n) {
   const double old = cons[o];
   const double un = save_n ? old : cons_n[o];
   if (save_n) cons_n[o] = old;
-  cons[o] = a * un + b * (old + dt * L);
+  const double v = a * un + b * (old + dt * L);
+  cons[o] = v;
+  return v;
 }
 
 // z-marching variant (flat metric): one thread per (i, j) column segment of
@@ -173,7 +176,8 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
                                                    const double* __restrict__ edges,
                                                    const double* __restrict__ tab, double a,
                                                    double b, double dt_host,
-                                                   const double* __restrict__ d_dt, int save_n) {
+                                                   const double* __restrict__ d_dt, int save_n,
+                                                   int img) {
   const long t = flat_thread();
   const int nseg = (G.n[2] + KZ - 1) / KZ;
   if (t >= (long)G.n[0] * G.n[1] * nseg) return;
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
     for (int q = 0; q < 5; ++q) wf[q][5] = fz[(long)q * G.field + cn];
     w1[5] = e1[cn];
     w2[5] = e2[cn];
-    double f[6];
+    double f[6], bf[3];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       double L = 0.0;
@@ -226,14 +230,14 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sy];
       const double L = -fd_deriv(f, idx1) + fd_deriv(w2, idx2);
-      rk_store(cons, cons_n, (long)C_BF1 * G.field + c, a, b, dt, L, save_n);
+      bf[0] = rk_store(cons, cons_n, (long)C_BF1 * G.field + c, a, b, dt, L, save_n);
     }
     // B^2: -D_3 E_1 + D_1 E_3
     {
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sx];
       const double L = -fd_deriv(w1, idx2) + fd_deriv(f, idx0);
-      rk_store(cons, cons_n, (long)C_BF2 * G.field + c, a, b, dt, L, save_n);
+      bf[1] = rk_store(cons, cons_n, (long)C_BF2 * G.field + c, a, b, dt, L, save_n);
     }
     // B^3: -D_1 E_2 + D_2 E_1
     {
@@ -244,7 +248,11 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
         g2[s] = e1[c + (s - 3) * sy];
       }
       const double L = -fd_deriv(f, idx0) + fd_deriv(g2, idx1);
-      rk_store(cons, cons_n, (long)C_BF3 * G.field + c, a, b, dt, L, save_n);
+      bf[2] = rk_store(cons, cons_n, (long)C_BF3 * G.field + c, a, b, dt, L, save_n);
+    }
+    if (img) {
+      constexpr int ff[3] = {C_BF1, C_BF2, C_BF3};
+      write_images<3>(G, cons, i, j, k, ff, bf);
     }
 #pragma unroll
     for (int s = 0; s < 5; ++s) {
@@ -634,13 +642,13 @@ void launch_bc_faces(const Geom& G, const BCSpec& bc, double* cons, hipStream_t 
 void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* cons,
                    double* cons_n, const double* flux, const double* edges,
                    const double* tab, double a, double b, double dt_host, const double* d_dt,
-                   double* out, int save_n, hipStream_t s) {
+                   double* out, int save_n, hipStream_t s, int img) {
   const unsigned nb = zone_blocks(G);
   if (flat && mode == 0) {
     const long nseg = (G.n[2] + KZ - 1) / KZ;
     const long total = (long)G.n[0] * G.n[1] * nseg;
     hipLaunchKernelGGL(k_update_zm<FlatMet<double>>, dim3(nblk(total)), dim3(256), 0, s, G, prim,
-                       cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, save_n);
+                       cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, save_n, img);
   } else if (flat)
     hipLaunchKernelGGL(k_update<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
                        cons_n, flux, edges, tab, a, b, dt_host, d_dt, out, save_n);
