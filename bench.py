@@ -163,6 +163,20 @@ def torus_report(args):
     ms = e0.elapsed_time(e1)
     prof = G.profile(reset=True)
     dg = G.diagnostics()
+    # fluxes through the spheres (accretion rate -F_D, magnetic flux) at the
+    # first shell outside the horizon r+ = 1 + sqrt(1 - a^2), and their cost
+    import math
+    import numpy as np
+    sh = G.shell_fluxes()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(G.stream)
+    for _ in range(10):
+        G.shell_fluxes()
+    ev1.record(G.stream)
+    torch.cuda.synchronize()
+    r = np.exp(g.x0[0] + (np.arange(n1) + 0.5) * g.dx[0])
+    ih = int(np.argmax(r > 1.0 + math.sqrt(1.0 - 0.9 ** 2)))
     out = {"metric": "zone-updates/s per RK3 step, KS torus %dx%dx%d (FP64)" % (n1, n2, n3),
            "value": g.zones * args.steps / (ms / 1e3), "unit": "zone-updates/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
@@ -172,7 +186,11 @@ def torus_report(args):
            "kernels": {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in prof.items()},
            "diag": {k: dg[k] for k in ("t", "max_divb", "rho_min", "rho_max", "w_max", "n_floor_rho",
                                        "n_floor_p", "n_wcap", "n_c2p_fail", "newton_iters_sum",
-                                       "newton_iters_max", "n_nonfinite")}}
+                                       "newton_iters_max", "n_nonfinite")},
+           "shell_fluxes": {"r_horizon_shell": float(r[ih]), "mdot": float(-sh["F_D"][ih]),
+                            "energy_flux": float(sh["F_tau"][ih]), "phi_abs": float(sh["Phi"][ih]),
+                            "phi_signed": float(sh["Phi_s"][ih]),
+                            "call_ms_incl_copy": ev0.elapsed_time(ev1) / 10}}
     G.close()
     print(json.dumps(out))
 

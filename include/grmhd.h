@@ -181,6 +181,20 @@ int grmhd_compute_dt(grmhd_grid* h, double* dt);
  * order (deterministic). */
 int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out);
 
+/* Fluxes through the surfaces x^1 = const of the bound state, for each
+ * interior x^1 index i (synchronises; deterministic order).  A diagnostic of
+ * the torus use case (paper, Introduction and Fig. 1: accretion onto the
+ * black hole): with x^1 = ln r the densitised x^1-fluxes include sqrt(gamma)
+ * and the Jacobian, so summing them times dx^2 dx^3 over a shell gives the
+ * flux through the sphere.  host_out (host, n_doubles >= 4 n1) receives
+ *   [0, n1)     F_D   = sum F^1[D] dx^2 dx^3 at cell centres (accretion rate -F_D)
+ *   [n1, 2n1)   F_tau = sum F^1[tau] dx^2 dx^3 at cell centres
+ *   [2n1, 3n1)  Phi   = 1/2 sum |B_face^1| dx^2 dx^3 at the upper x^1 face of cell i
+ *   [3n1, 4n1)  sum B_face^1 dx^2 dx^3 (signed; 0 for a closed field)
+ * with the pointwise fluxes of the stored primitives (including the centred
+ * field).  EINVAL on NULL or a short buffer. */
+int grmhd_shell_fluxes(grmhd_grid* h, double* host_out, size_t n_doubles);
+
 /* Learned Newton initial guess (a training-system pattern layered on the
  * method; the paper has no counterpart).  An MLP 8 -> 64 -> 64 -> 64 -> 5
  * (tanh hidden layers, linear output) runs on BF16 matrix cores with FP32

@@ -15,7 +15,7 @@ METRIC_NCOMP = 88
 
 EXPORTS = ("grmhd_init_grid", "grmhd_get_layout", "grmhd_bind_fields", "grmhd_set_metric",
            "grmhd_curl_potential", "grmhd_prim2cons", "grmhd_rhs", "grmhd_rk_step",
-           "grmhd_cons2prim", "grmhd_compute_dt", "grmhd_diagnostics", "grmhd_destroy",
+           "grmhd_cons2prim", "grmhd_compute_dt", "grmhd_diagnostics", "grmhd_shell_fluxes", "grmhd_destroy",
            "grmhd_last_error", "grmhd_set_profiling", "grmhd_get_profile",
            "grmhd_profile_class_name", "grmhd_mlp_set_weights", "grmhd_mlp_get_weights",
            "grmhd_mlp_datagen", "grmhd_mlp_gradient", "grmhd_mlp_train_step", "grmhd_mlp_forward",
@@ -95,6 +95,7 @@ def lib():
     L.grmhd_cons2prim.argtypes = [P, C.POINTER(C.c_int64), C.c_int]
     L.grmhd_compute_dt.argtypes = [P, D]
     L.grmhd_diagnostics.argtypes = [P, C.POINTER(Diag)]
+    L.grmhd_shell_fluxes.argtypes = [P, C.POINTER(C.c_double), C.c_size_t]
     L.grmhd_destroy.argtypes = [P]
     L.grmhd_destroy.restype = None
     L.grmhd_last_error.restype = C.c_char_p

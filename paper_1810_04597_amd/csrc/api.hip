@@ -210,9 +210,11 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** 
   for (int d = 0; d < 3; ++d) h->img = h->img && desc->n[d] >= 2 * NG;
   h->stream = (hipStream_t)hip_stream;
   h->nblk = zone_blocks(h->G);
-  // reduction partials: diagnostics (nblk x 16) and CFL (nblk + learned-pass blocks)
-  const size_t part = std::max((size_t)h->nblk * (DIAG_NSUM + DIAG_NMAX),
-                               (size_t)h->nblk + C2P_LIST_BLOCKS) * sizeof(double);
+  // reduction partials: diagnostics (nblk x 16), CFL (nblk + learned-pass
+  // blocks), shell fluxes (chunk partials, then the 4 n1 results)
+  const size_t part = std::max(std::max((size_t)h->nblk * (DIAG_NSUM + DIAG_NMAX),
+                                        (size_t)h->nblk + C2P_LIST_BLOCKS),
+                               (size_t)(shell_part_doubles(h->G) + 4L * desc->n[0])) * sizeof(double);
   const size_t spart = ((size_t)h->nblk + C2P_LIST_BLOCKS) * C2P_NSTAT * sizeof(long long);
   hipError_t e = hipSuccess;
   e = hipMalloc(&h->d_dt, 3 * sizeof(double));
@@ -436,6 +438,20 @@ int grmhd_compute_dt(grmhd_grid* h, double* dt) {
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
   return hip_check("compute_dt");
+}
+
+int grmhd_shell_fluxes(grmhd_grid* h, double* host_out, size_t n_doubles) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!host_out) return fail(GRMHD_EINVAL, "host_out is NULL");
+  if (n_doubles < (size_t)4 * h->G.n[0]) return fail(GRMHD_EINVAL, "host_out needs 4 n1 doubles");
+  double* res = h->d_part + shell_part_doubles(h->G);
+  launch_shell(h->G, h->flat, h->prim, h->cons, h->tab, h->d_part, res, h->stream);
+  hipError_t e = hipMemcpyAsync(host_out, res, (size_t)4 * h->G.n[0] * sizeof(double),
+                                hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  return hip_check("shell_fluxes");
 }
 
 int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out) {

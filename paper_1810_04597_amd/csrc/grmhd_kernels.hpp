@@ -50,6 +50,11 @@ void launch_c2p(const Geom& G, bool flat, const C2PParams& cp, double* prim, dou
                 const double* tab, long long* partials, double* cfl_partials, int* list, int* list_n,
                 hipStream_t s);
 void launch_zero_int(int* p, hipStream_t s);
+// Shell fluxes through x^1 = const: out[4 n1] = F_D, F_tau, Phi (|B|/2), Phi
+// signed; part: shell_part_doubles(G) doubles of chunk partials.
+void launch_shell(const Geom& G, bool flat, const double* prim, const double* cons, const double* tab,
+                  double* part, double* out, hipStream_t s);
+long shell_part_doubles(const Geom& G);
 void launch_dt_final(const double* cfl_partials, int nb, double cfl, double* d_dt, hipStream_t s);
 void launch_prim2cons(const Geom& G, bool flat, double* prim, double* cons, const double* tab,
                       hipStream_t s);

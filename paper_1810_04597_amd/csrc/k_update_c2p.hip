@@ -720,6 +720,80 @@ void launch_curl(const Geom& G, const double* a1, const double* a2, const double
   hipLaunchKernelGGL(k_curl, dim3(zone_blocks(G)), dim3(256), 0, s, G, a1, a2, a3, cons);
 }
 
+// ------------------------------------------------------------------ shell fluxes
+// Over each x^1 shell i and its (j, k): the pointwise x^1-fluxes of D and tau
+// of the cell-centred state, |B_face^1| and B_face^1 at the upper x^1 face,
+// each times dx^2 dx^3 (flux through the sphere r = r_i in (ln r, theta,
+// phi)).  Workgroup (i, chunk) sums a fixed chunk of the shell into part;
+// k_shell_final adds the chunks of a shell in order (deterministic).
+// out: [F_D (n1), F_tau (n1), Phi = |B|/2 (n1), Phi_signed (n1)].
+constexpr int SHELL_CHUNKS = 16;
+
+template <class MET>
+__global__ __launch_bounds__(256) void k_shell(Geom G, const double* __restrict__ prim,
+                                               const double* __restrict__ cons,
+                                               const double* __restrict__ tab,
+                                               double* __restrict__ part) {
+  const int i = blockIdx.x, ch = blockIdx.y;
+  const long m2 = (long)G.n[1] * G.n[2];
+  const long q0 = m2 * ch / SHELL_CHUNKS, q1 = m2 * (ch + 1) / SHELL_CHUNKS;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long q = q0 + threadIdx.x; q < q1; q += 256) {
+    const int j = (int)(q % G.n[1]), k = (int)(q / G.n[1]);
+    const long c = G.idx(i, j, k);
+    MET m;
+    if constexpr (!MET::flat) m.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
+    PState<double> st;
+    st.rho = prim[P_RHO * G.field + c];
+    st.p = prim[P_P * G.field + c];
+    for (int a = 0; a < 3; ++a) {
+      st.u[a] = prim[(P_U1 + a) * G.field + c];
+      st.B[a] = prim[(P_B1 + a) * G.field + c];
+    }
+    make_state(st, m, G.gam);
+    double f[5];
+    flux_of(st, m, 0, f);
+    const double bf = cons[(long)C_BF1 * G.field + c];
+    acc[0] += f[0];
+    acc[1] += f[4];
+    acc[2] += fabs(bf);
+    acc[3] += bf;
+  }
+  __shared__ double sh[4][4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int a = 0; a < 4; ++a) {
+    const double w = wave_sum(acc[a]);
+    if (lane == 0) sh[wv][a] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int a = threadIdx.x;
+    part[((long)a * G.n[0] + i) * SHELL_CHUNKS + ch] = (sh[0][a] + sh[1][a]) + (sh[2][a] + sh[3][a]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_shell_final(Geom G, const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= 4L * G.n[0]) return;
+  double v = 0.0;
+  for (int ch = 0; ch < SHELL_CHUNKS; ++ch) v += part[e * SHELL_CHUNKS + ch];
+  v *= G.dx[1] * G.dx[2];
+  out[e] = e / G.n[0] == 2 ? 0.5 * v : v;
+}
+
+void launch_shell(const Geom& G, bool flat, const double* prim, const double* cons, const double* tab,
+                  double* part, double* out, hipStream_t s) {
+  const dim3 grid(G.n[0], SHELL_CHUNKS);
+  if (flat)
+    hipLaunchKernelGGL(k_shell<FlatMet<double>>, grid, dim3(256), 0, s, G, prim, cons, tab, part);
+  else
+    hipLaunchKernelGGL(k_shell<TabMet<double>>, grid, dim3(256), 0, s, G, prim, cons, tab, part);
+  hipLaunchKernelGGL(k_shell_final, dim3((unsigned)((4L * G.n[0] + 255) / 256)), dim3(256), 0, s, G, part, out);
+}
+
+long shell_part_doubles(const Geom& G) { return 4L * G.n[0] * SHELL_CHUNKS; }
+
 void launch_diag(const Geom& G, bool flat, const double* prim, const double* cons,
                  const double* tab, double* partials, double* out, hipStream_t s) {
   const unsigned nb = zone_blocks(G);

@@ -111,6 +111,14 @@ class Grid:
         L.check(self.lib.grmhd_diagnostics(self.h, C.byref(d)))
         return d.as_dict()
 
+    def shell_fluxes(self):
+        """{F_D, F_tau, Phi, Phi_s}: fluxes through the x^1 = const shells (numpy, n1 each)."""
+        n1 = self.spec.n[0]
+        buf = (C.c_double * (4 * n1))()
+        L.check(self.lib.grmhd_shell_fluxes(self.h, buf, C.c_size_t(4 * n1)))
+        a = np.frombuffer(buf, dtype=np.float64).copy()
+        return {"F_D": a[0:n1], "F_tau": a[n1:2 * n1], "Phi": a[2 * n1:3 * n1], "Phi_s": a[3 * n1:]}
+
     # ------------------------------------------------------------ learned guess
     def mlp_set_weights(self, flat, norm):
         flat = np.ascontiguousarray(flat, dtype=np.float32)

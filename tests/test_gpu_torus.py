@@ -120,3 +120,35 @@ def test_torus_ten_steps_within_oracle_envelope():
         assert np.max(diff[body]) < 1e-2 * scale, (k, report[k])
     print("torus envelope report (gpu q99, oracle q99, body max):", report)
     assert G.diagnostics()["n_nonfinite"] == 0
+
+
+def _shell_close(gs, os_):
+    for a, scale in (("F_D", "scale_D"), ("F_tau", "scale_tau"), ("Phi", "scale_B"), ("Phi_s", "scale_B")):
+        err = np.abs(gs[a] - os_[a]) / np.maximum(os_[scale], 1e-300)
+        assert err.max() < 1e-12, (a, err.max())
+
+
+@gpu
+def test_shell_fluxes_match_oracle():
+    """Fluxes through the x^1 = const shells (accretion rate, energy and
+    magnetic flux) on the 32 x 16 x 16 torus, initially and after one step:
+    every shell within 1e-12 of the sum of |terms|."""
+    _torch()
+    from oracle.diagnostics import shell_fluxes
+    g, d, tab, s, G = _pair_torus(32, 16, 16)
+    _shell_close(G.shell_fluxes(), shell_fluxes(s))
+    dt = s.cfl_dt()
+    s.rk_step(dt)
+    G.rk_step(dt)
+    _shell_close(G.shell_fluxes(), shell_fluxes(s))
+
+
+@gpu
+def test_shell_fluxes_full_size_torus():
+    """The same diagnostic on the full 256 x 128 x 128 torus (initial state;
+    the oracle evaluates the pointwise fluxes of the whole grid)."""
+    _torch()
+    from oracle.diagnostics import shell_fluxes
+    g, d, tab, s, G = _pair_torus(256, 128, 128)
+    _shell_close(G.shell_fluxes(), shell_fluxes(s))
+    G.close()
