@@ -195,6 +195,51 @@ def torus_report(args):
     print(json.dumps(out))
 
 
+def torus_long_report(args):
+    """Long Kerr-Schild torus run (device CFL step): every --every steps the
+    diagnostics and the fluxes through the first sphere outside the horizon
+    (accretion rate -F_D, magnetic flux); wall time per step over the run."""
+    import math
+    import numpy as np
+    import torch
+    from workloads.torus import torus
+    from paper_1810_04597_amd.grid import Grid
+    n1, n2, n3 = (int(x) for x in args.torus.split(","))
+    g, d, tab = torus(n1, n2, n3)
+    G = Grid(g, tables=tab)
+    G.curl_potential(d)
+    G.set_primitives(d)
+    r = np.exp(g.x0[0] + (np.arange(n1) + 0.5) * g.dx[0])
+    ih = int(np.argmax(r > 1.0 + math.sqrt(1.0 - 0.9 ** 2)))
+    series = []
+    w0 = time.perf_counter()
+    for s in range(1, args.steps + 1):
+        G.rk_step()
+        if s % args.every == 0 or s == args.steps:
+            dg = G.diagnostics()
+            sh = G.shell_fluxes()
+            rec = {"step": s, "t": dg["t"], "dt": dg["dt"], "mdot_horizon": float(-sh["F_D"][ih]),
+                   "phi_horizon": float(sh["Phi"][ih]), "max_divb": dg["max_divb"],
+                   "sum_D": dg["sum_cons"][0], "w_max": dg["w_max"], "n_c2p_fail": dg["n_c2p_fail"],
+                   "n_nonfinite": dg["n_nonfinite"], "newton_iters_max": dg["newton_iters_max"]}
+            series.append(rec)
+            print("bench: step %d t %.3f mdot %.3e divb %.2e" % (s, rec["t"], rec["mdot_horizon"], rec["max_divb"]),
+                  file=sys.stderr, flush=True)
+            if dg["n_nonfinite"]:
+                break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    out = {"metric": "long torus run, KS %dx%dx%d (FP64)" % (n1, n2, n3), "value": series[-1]["t"],
+           "unit": "t (M)", "n_gpus": 1, "steps": series[-1]["step"], "warmup": 0,
+           "ms_per_step": 1e3 * wall / series[-1]["step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "Kerr-Schild a=0.9 torus %dx%dx%d, device CFL, diagnostics every %d steps"
+                                  % (n1, n2, n3, args.every), "r_shell": float(r[ih])},
+           "series": series}
+    G.close()
+    print(json.dumps(out))
+
+
 def learned_report(args):
     """Train the learned Newton guess on the GPU (seeded samples, own kernels),
     then run the Kerr-Schild torus with three forms on the same GPU: plain
@@ -314,7 +359,7 @@ def main():
                     help="after the timed steps, one plain device copy of CALIB_COPY_BYTES "
                          "(reference for scaling the HBM traffic counters)")
     ap.add_argument("--profile-kernels", action="store_true", default=True)
-    ap.add_argument("--mode", default="step", choices=["step", "precision", "learned", "torus"],
+    ap.add_argument("--mode", default="step", choices=["step", "precision", "learned", "torus", "torus-long"],
                     help="step: the FP64 RK3 step (default); precision: FP32-flux form "
                          "against FP64 on the same grid, fixed dt, per-field error; learned: "
                          "train the Newton-guess network on the GPU, then the Kerr-Schild "
@@ -322,6 +367,7 @@ def main():
     ap.add_argument("--train-samples", type=int, default=1 << 22)
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--torus", default="384,192,192")
+    ap.add_argument("--every", type=int, default=250, help="torus-long: steps between diagnostics")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (a single grid block per device); "
@@ -334,6 +380,8 @@ def main():
         return learned_report(args)
     if args.mode == "torus":
         return torus_report(args)
+    if args.mode == "torus-long":
+        return torus_long_report(args)
 
     import torch
     from workloads import box
