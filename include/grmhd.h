@@ -162,7 +162,9 @@ int grmhd_rhs(grmhd_grid* h, double* rhs_out);
  * same.  bind_fields, set_metric, curl_potential, prim2cons and cons2prim
  * drop the stored value; a caller that writes the bound prim/cons directly
  * calls one of the latter two before stepping, as the state must be made
- * consistent anyway.  dt_used (nullable) receives the step taken
+ * consistent anyway (they also leave the ghost zones filled: on a fully
+ * periodic grid with every n >= 10 the step itself writes ghost images
+ * instead of running separate ghost fills).  dt_used (nullable) receives the step taken
  * (synchronises). */
 int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used);
 

@@ -36,7 +36,7 @@ constexpr int SCR_CONS_N = 0;    // 8 fields
 constexpr int SCR_FLUX = 8;      // 3 x 5 fields
 constexpr int SCR_CTD = 23;      // 3 x 6 fields
 constexpr int SCR_EDGE = 41;     // 3 fields
-constexpr int SCR_GUESS = 44;    // 1 field: list of zones deferred to the learned-guess pass (int)
+constexpr int SCR_LIST = 44;     // 1 field: list of zones deferred to the learned-guess pass (int)
 constexpr int SCR_NFIELDS = 45;
 constexpr int MLP_MAX_WAVES = 256;
 
@@ -95,7 +95,7 @@ struct grmhd_grid {
   double* flux() const { return scratch + (long)SCR_FLUX * G.field; }
   double* ctd() const { return scratch + (long)SCR_CTD * G.field; }
   double* edges() const { return scratch + (long)SCR_EDGE * G.field; }
-  int* list() const { return reinterpret_cast<int*>(scratch + (long)SCR_GUESS * G.field); }
+  int* list() const { return reinterpret_cast<int*>(scratch + (long)SCR_LIST * G.field); }
   MlpState mlp;
   bool mlp_alloc = false;
 };
