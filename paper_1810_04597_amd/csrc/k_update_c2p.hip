@@ -150,13 +150,22 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
   }
 }
 
-// RK stage store; save_n (first stage, a = 0): U^n is this value, saved.
+// RK stage store; SAVE (first stage, a = 0): U^n is this value, saved.
 // Returns the stored value.
+// SAVE is a template argument so that a z-iteration of the update below is
+// one basic block: the scheduler can then issue every field's stencil loads
+// ahead of the earlier fields' stores instead of waiting field by field.
+template <int SAVE>
 __device__ __forceinline__ double rk_store(double* __restrict__ cons, double* __restrict__ cons_n, long o,
-                                           double a, double b, double dt, double L, int save_n) {
+                                           double a, double b, double dt, double L) {
   const double old = cons[o];
-  const double un = save_n ? old : cons_n[o];
-  if (save_n) cons_n[o] = old;
+  double un;
+  if constexpr (SAVE) {
+    un = old;
+    cons_n[o] = old;
+  } else {
+    un = cons_n[o];
+  }
   const double v = a * un + b * (old + dt * L);
   cons[o] = v;
   return v;
@@ -168,7 +177,7 @@ __device__ __forceinline__ double rk_store(double* __restrict__ cons, double* __
 // segment instead of six times; x^1 and x^2 stencils are read per plane.
 constexpr int KZ = 16;
 
-template <class MET>
+template <class MET, int SAVE>
 __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restrict__ prim,
                                                    double* __restrict__ cons,
                                                    double* __restrict__ cons_n,
@@ -176,8 +185,7 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
                                                    const double* __restrict__ edges,
                                                    const double* __restrict__ tab, double a,
                                                    double b, double dt_host,
-                                                   const double* __restrict__ d_dt, int save_n,
-                                                   int img) {
+                                                   const double* __restrict__ d_dt, int img) {
   const long t = flat_thread();
   const int nseg = (G.n[2] + KZ - 1) / KZ;
   if (t >= (long)G.n[0] * G.n[1] * nseg) return;
@@ -223,21 +231,21 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
       for (int s = 0; s < 6; ++s) f[s] = fy[(s - 3) * sy];
       L = L - fd_deriv(f, idx1);
       L = L - fd_deriv(wf[q], idx2);
-      rk_store(cons, cons_n, (long)q * G.field + c, a, b, dt, L, save_n);
+      rk_store<SAVE>(cons, cons_n, (long)q * G.field + c, a, b, dt, L);
     }
     // B^1: -D_2 E_3 + D_3 E_2
     {
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sy];
       const double L = -fd_deriv(f, idx1) + fd_deriv(w2, idx2);
-      bf[0] = rk_store(cons, cons_n, (long)C_BF1 * G.field + c, a, b, dt, L, save_n);
+      bf[0] = rk_store<SAVE>(cons, cons_n, (long)C_BF1 * G.field + c, a, b, dt, L);
     }
     // B^2: -D_3 E_1 + D_1 E_3
     {
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sx];
       const double L = -fd_deriv(w1, idx2) + fd_deriv(f, idx0);
-      bf[1] = rk_store(cons, cons_n, (long)C_BF2 * G.field + c, a, b, dt, L, save_n);
+      bf[1] = rk_store<SAVE>(cons, cons_n, (long)C_BF2 * G.field + c, a, b, dt, L);
     }
     // B^3: -D_1 E_2 + D_2 E_1
     {
@@ -248,7 +256,7 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
         g2[s] = e1[c + (s - 3) * sy];
       }
       const double L = -fd_deriv(f, idx0) + fd_deriv(g2, idx1);
-      bf[2] = rk_store(cons, cons_n, (long)C_BF3 * G.field + c, a, b, dt, L, save_n);
+      bf[2] = rk_store<SAVE>(cons, cons_n, (long)C_BF3 * G.field + c, a, b, dt, L);
     }
     if (img) {
       constexpr int ff[3] = {C_BF1, C_BF2, C_BF3};
@@ -647,8 +655,12 @@ void launch_update(const Geom& G, bool flat, int mode, const double* prim, doubl
   if (flat && mode == 0) {
     const long nseg = (G.n[2] + KZ - 1) / KZ;
     const long total = (long)G.n[0] * G.n[1] * nseg;
-    hipLaunchKernelGGL(k_update_zm<FlatMet<double>>, dim3(nblk(total)), dim3(256), 0, s, G, prim,
-                       cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, save_n, img);
+    if (save_n)
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 1>), dim3(nblk(total)), dim3(256), 0, s, G,
+                         prim, cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, img);
+    else
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 0>), dim3(nblk(total)), dim3(256), 0, s, G,
+                         prim, cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, img);
   } else if (flat)
     hipLaunchKernelGGL(k_update<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
                        cons_n, flux, edges, tab, a, b, dt_host, d_dt, out, save_n);

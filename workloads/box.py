@@ -109,6 +109,38 @@ def turbulent_box(n, seed=SEED, ng=5, method="auto"):
     return grid, data
 
 
+def _eval_direct_shape(phi, n, offs):
+    """g on an n[0] x n[1] x n[2] grid at positions (m_a + offs_a)/n_a,
+    [k][j][i] order (direct sum over the modes)."""
+    x = [(np.arange(n[a]) + offs[a]) / n[a] for a in range(3)]
+    out = np.zeros((n[2], n[1], n[0]))
+    for m, k in enumerate(MODES):
+        out += np.cos(2 * np.pi * (k[2] * x[2][:, None, None] + k[1] * x[1][None, :, None]
+                                   + k[0] * x[0][None, None, :]) + phi[m])
+    return out
+
+
+def turbulent_box_shape(n1, n2, n3, seed=SEED, ng=5):
+    """The turbulent box's continuous fields sampled on a periodic unit box
+    with n1 x n2 x n3 zones (spacings 1/n_a): the same fields as
+    turbulent_box(n) when n1 = n2 = n3 = n.  Returns (grid, data)."""
+    from .grid import GridSpec, CART, BC_PERIODIC
+    n = (n1, n2, n3)
+    assert min(n) >= ng
+    grid = GridSpec(n=n, ng=ng, coord=CART, x0=(0.0, 0.0, 0.0),
+                    dx=tuple(1.0 / x for x in n), bc=(BC_PERIODIC,) * 6)
+    ph = phases(seed)
+    sc = normalisation(seed)
+    rho = 1.0 + sc["rho"] * _eval_direct_shape(ph["drho"], n, CENTRE)
+    v = [sc["v"] * _eval_direct_shape(ph[f], n, CENTRE) for f in ("dv1", "dv2", "dv3")]
+    w = 1.0 / np.sqrt(1.0 - (v[0] ** 2 + v[1] ** 2 + v[2] ** 2))
+    data = {"rho": rho, "u1": w * v[0], "u2": w * v[1], "u3": w * v[2],
+            "p": np.full((n3, n2, n1), 0.1)}
+    for f in ("A1", "A2", "A3"):
+        data[f] = _wrap_ghosts(sc["A"] * _eval_direct_shape(ph[f], n, EDGE_OFFS[f]), ng)
+    return grid, data
+
+
 def entropy_wave(n, t=0.0, ng=5, amp=0.2, v=(0.3, 0.2, 0.1), p=1.0,
                  b=(0.3, 0.2, 0.1)):
     """Smooth entropy wave rho = 1 + amp sin(2 pi (x+y+z - (v1+v2+v3) t)) with
