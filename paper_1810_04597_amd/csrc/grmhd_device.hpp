@@ -110,7 +110,10 @@ GR_HD T minmod4(T w, T x, T y, T z) {
 // Limited left state at the face between q0 and qp1 from q_{j-2..j+2}.
 template <typename T>
 GR_HD T mp5(T qm2, T qm1, T q0, T qp1, T qp2) {
-  const T ql = (T(3) * qm2 - T(20) * qm1 + T(90) * q0 + T(60) * qp1 - T(5) * qp2) * T(1.0 / 128.0);
+  // interpolant (3, -20, 90, 60, -5)/128 with the power-of-two scale folded
+  // into the weights (the same value: scaling by 2^-7 commutes with rounding)
+  const T ql = T(3.0 / 128) * qm2 - T(20.0 / 128) * qm1 + T(90.0 / 128) * q0 +
+               T(60.0 / 128) * qp1 - T(5.0 / 128) * qp2;
   const T qmp = q0 + minmod(qp1 - q0, T(4) * (q0 - qm1));
   if ((ql - q0) * (ql - qmp) <= T(0)) return ql;
   const T dm1 = qm2 - T(2) * qm1 + q0;
@@ -121,8 +124,10 @@ GR_HD T mp5(T qm2, T qm1, T q0, T qp1, T qp2) {
   const T qul = q0 + T(4) * (q0 - qm1);
   const T qmd = T(0.5) * (q0 + qp1) - T(0.5) * dm4p;
   const T qlc = q0 + T(0.5) * (q0 - qm1) + T(4.0 / 3.0) * dm4m;
-  const T qmin = fmax(fmin(fmin(q0, qp1), qmd), fmin(fmin(q0, qul), qlc));
-  const T qmax = fmin(fmax(fmax(q0, qp1), qmd), fmax(fmax(q0, qul), qlc));
+  // max(min(q0, qp1, qmd), min(q0, qul, qlc)) and its mirror, with q0
+  // factored out (min distributes over max): the same values, fewer operations
+  const T qmin = fmin(q0, fmax(fmin(qp1, qmd), fmin(qul, qlc)));
+  const T qmax = fmax(q0, fmin(fmax(qp1, qmd), fmax(qul, qlc)));
   // median(ql, qmin, qmax), written in the scheme as ql + minmod(qmin - ql,
   // qmax - ql); both bounding intervals contain q0, so qmin <= qmax and the
   // median is the clamp (equal up to the rounding of ql + (qmin - ql)).

@@ -21,6 +21,37 @@
 
 namespace grmhd {
 
+// Lane map.  MP5's limiter branch is needed by a few percent of the
+// reconstructions, and those cluster in space: a wavefront that spans one
+// 64-position row almost always holds one of them and runs the branch for
+// all its lanes, while a compact patch of the same 64 positions more often
+// holds none and skips it.  So every kernel here hands each wavefront a patch
+// of PX consecutive x^1 positions times PY rows of a second axis.
+constexpr int PX = 16, PY = 64 / PX;
+
+// Direct (unstaged) kernels: a 256-thread workgroup covers PX x^1 positions
+// times 4 PY positions of the middle axis at one position of the slow axis;
+// wavefront w owns middle-axis rows w PY .. w PY + PY - 1 of the tile.
+struct TilePos {
+  int a, m, s;
+  bool ok;
+};
+__device__ __forceinline__ TilePos tile_pos(int ext0, int extm) {
+  const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+  const unsigned nt0 = (ext0 + PX - 1) / PX, ntm = (extm + 4 * PY - 1) / (4 * PY);
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  TilePos p;
+  p.a = (int)(b % nt0) * PX + lane % PX;
+  const unsigned r = b / nt0;
+  p.m = (int)(r % ntm) * (4 * PY) + w * PY + lane / PX;
+  p.s = (int)(r / ntm);
+  p.ok = p.a < ext0 && p.m < extm;
+  return p;
+}
+static inline unsigned tile_blocks(long ext0, long extm, long exts) {
+  return (unsigned)(((ext0 + PX - 1) / PX) * ((extm + 4 * PY - 1) / (4 * PY)) * exts);
+}
+
 template <int DIR, class MET, typename T>
 __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict__ prim,
                                                const double* __restrict__ cons,
@@ -30,17 +61,15 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
   int ext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) ext[a] = (a == DIR) ? G.n[a] + 5 : G.dims[a];
-  const long t = flat_thread();
-  const long total = (long)ext[0] * ext[1] * ext[2];
-  if (t >= total) return;
-  // traversal order: x^1 fastest; for the x^3 sweep x^3 comes next, so the
-  // six planes of a stencil are read by neighbouring workgroups (L2 reuse)
+  // tiles: x^1 fastest; for the x^3 sweep x^3 comes next, so the six planes
+  // of a stencil are read by neighbouring workgroups (L2 reuse)
   constexpr int MID = DIR == 2 ? 2 : 1, SLOW = DIR == 2 ? 1 : 2;
+  const TilePos tp = tile_pos(ext[0], ext[MID]);
+  if (!tp.ok) return;
   int ii[3];
-  ii[0] = (int)(t % ext[0]);
-  const long r = t / ext[0];
-  ii[MID] = (int)(r % ext[MID]);
-  ii[SLOW] = (int)(r / ext[MID]);
+  ii[0] = tp.a;
+  ii[MID] = tp.m;
+  ii[SLOW] = tp.s;
 #pragma unroll
   for (int a = 0; a < 3; ++a) ii[a] += (a == DIR) ? -3 : -NG;
   const long c = G.idx(ii[0], ii[1], ii[2]);
@@ -91,6 +120,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
 // face row.  Workgroups of one column follow each other along DIR.
 // One wavefront per face row (SX = 64); SF face rows per workgroup.
 constexpr int SX = 64;
+constexpr int LPAD = 0;   // extra doubles per LDS row
 
 template <int DIR, int SF, class MET, typename T>
 __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __restrict__ prim,
@@ -102,7 +132,7 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   constexpr int TB = DIR == 1 ? 2 : 1;          // the transverse axis other than x^1
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
   constexpr int SR = SF + 5, NRR = (SR + SF - 1) / SF;
-  __shared__ T sh[7][SR][SX];
+  __shared__ T sh[7][SR][SX + LPAD];
   const int nA = G.dims[0];
   const long M = (long)nA * G.dims[TB];
   const int nface = G.n[DIR] + 5;               // faces -3 .. n + 1
@@ -114,10 +144,10 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   const int tx = threadIdx.x % SX, ty = __builtin_amdgcn_readfirstlane(threadIdx.x / SX);
   const long mm = mt * SX + tx;
   const bool m_ok = mm < M;
-  const long mc = m_ok ? mm : M - 1;            // clamped: every staging load is in bounds
+  const unsigned mc = (unsigned)(m_ok ? mm : M - 1);   // clamped: every staging load is in bounds
   int ii[3];
-  ii[0] = (int)(mc % nA) - NG;
-  ii[TB] = (int)(mc / nA) - NG;
+  ii[0] = (int)(mc % (unsigned)nA) - NG;
+  ii[TB] = (int)(mc / (unsigned)nA) - NG;
   ii[DIR] = 0;
   const long base = G.idx(ii[0], ii[1], ii[2]);
   const long st = G.stride(DIR);
@@ -146,10 +176,18 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
         if (ty + SF * rr < SR) sh[v][ty + SF * rr][tx] = stage[v][rr];
   }
   __syncthreads();
-  const int f = f0 + ty;
-  if (!m_ok || f > G.n[DIR] + 1) return;
+  // compute: wavefront w takes tile positions PX w .. PX w + PX - 1 times the
+  // SF face rows, a PX x PY patch
+  static_assert(SF == PY && SX == (SX * SF / 64) * PX, "one PX x PY patch per wavefront");
+  const int lane = threadIdx.x % 64;
+  const int cx = PX * (int)(threadIdx.x / 64) + lane % PX, cy = lane / PX;
+  const int f = f0 + cy;
+  // lane x of every wavefront staged tile position x: take its indices
+  ii[0] = __shfl(ii[0], cx);
+  ii[TB] = __shfl(ii[TB], cx);
+  if (mt * SX + cx >= M || f > G.n[DIR] + 1) return;
   ii[DIR] = f;
-  const long c = base + f * st;
+  const long c = G.idx(ii[0], ii[1], ii[2]);
   const T gam = T(G.gam);
   MET m;
   if constexpr (!MET::flat) {
@@ -160,7 +198,7 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
 #pragma unroll
   for (int v = 0; v < 7; ++v)
 #pragma unroll
-    for (int s = 0; s < 6; ++s) q[v][s] = sh[v][ty + s][tx];
+    for (int s = 0; s < 6; ++s) q[v][s] = sh[v][cy + s][cx];
   const double bface = cons[(long)(C_BF1 + DIR) * G.field + c];
   T bn;
   bool axis = false;
@@ -189,16 +227,14 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
   int ext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) ext[a] = (a == E) ? G.n[a] : G.n[a] + 5;
-  const long t = flat_thread();
-  const long total = (long)ext[0] * ext[1] * ext[2];
-  if (t >= total) return;
-  // families 1 and 2 reconstruct along x^3: traverse x^3 before x^2
+  // families 1 and 2 reconstruct along x^3: tiles traverse x^3 before x^2
   constexpr int MID = E == 2 ? 1 : 2, SLOW = E == 2 ? 2 : 1;
+  const TilePos tp = tile_pos(ext[0], ext[MID]);
+  if (!tp.ok) return;
   int ii[3];
-  ii[0] = (int)(t % ext[0]);
-  const long r = t / ext[0];
-  ii[MID] = (int)(r % ext[MID]);
-  ii[SLOW] = (int)(r / ext[MID]);
+  ii[0] = tp.a;
+  ii[MID] = tp.m;
+  ii[SLOW] = tp.s;
 #pragma unroll
   for (int a = 0; a < 3; ++a) ii[a] += (a == E) ? 0 : -3;
   const long b = G.idx(ii[0], ii[1], ii[2]);
@@ -243,7 +279,7 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   static_assert(E == 0 || E == 2, "families whose d-face inputs vary across rows");
   constexpr int D = (E + 1) % 3, C = (E + 2) % 3, B = 3 - C;   // B: the non-x^1 axis that is not C
   constexpr int SR = SF + 5, NRR = (SR + SF - 1) / SF;
-  __shared__ T sh[5][SR][SX];
+  __shared__ T sh[5][SR][SX + LPAD];
   const int extA = (E == 0) ? G.n[0] : G.n[0] + 5, offA = (E == 0) ? 0 : -3;
   const int extB = (B == E) ? G.n[B] : G.n[B] + 5, offB = (B == E) ? 0 : -3;
   const long M = (long)extA * extB;
@@ -256,10 +292,10 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   const int tx = threadIdx.x % SX, ty = __builtin_amdgcn_readfirstlane(threadIdx.x / SX);
   const long mm = mt * SX + tx;
   const bool m_ok = mm < M;
-  const long mc = m_ok ? mm : M - 1;            // clamped: every staging load is in bounds
+  const unsigned mc = (unsigned)(m_ok ? mm : M - 1);   // clamped: every staging load is in bounds
   int ii[3];
-  ii[0] = (int)(mc % extA) + offA;
-  ii[B] = (int)(mc / extA) + offB;
+  ii[0] = (int)(mc % (unsigned)extA) + offA;
+  ii[B] = (int)(mc / (unsigned)extA) + offB;
   ii[C] = 0;
   const long base = G.idx(ii[0], ii[1], ii[2]);
   const long sd = G.stride(D), sc = G.stride(C);
@@ -284,15 +320,23 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
         if (ty + SF * rr < SR) sh[v][ty + SF * rr][tx] = stage[v][rr];
   }
   __syncthreads();
-  const int cc = c0 + ty;
-  if (!m_ok || cc > G.n[C] + 1) return;
+  // compute: wavefront w takes tile positions PX w .. PX w + PX - 1 times the
+  // SF edge rows, a PX x PY patch
+  static_assert(SF == PY && SX == (SX * SF / 64) * PX, "one PX x PY patch per wavefront");
+  const int lane = threadIdx.x % 64;
+  const int cx = PX * (int)(threadIdx.x / 64) + lane % PX, cy = lane / PX;
+  const int cc = c0 + cy;
+  // lane x of every wavefront staged tile position x: take its indices
+  ii[0] = __shfl(ii[0], cx);
+  ii[B] = __shfl(ii[B], cx);
+  if (mt * SX + cx >= M || cc > G.n[C] + 1) return;
   ii[C] = cc;
-  const long b = base + cc * sc;
+  const long b = G.idx(ii[0], ii[1], ii[2]);
   T qd[5][6], qc[6];
 #pragma unroll
   for (int v = 0; v < 5; ++v)
 #pragma unroll
-    for (int s2 = 0; s2 < 6; ++s2) qd[v][s2] = sh[v][ty + s2][tx];
+    for (int s2 = 0; s2 < 6; ++s2) qd[v][s2] = sh[v][cy + s2][cx];
   {
     const double* bcs = cons + (long)(C_BF1 + C) * G.field;
 #pragma unroll
@@ -313,17 +357,15 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
 // ------------------------------------------------------------------ launchers
 constexpr int SWEEP_SF = 4;   // face rows per workgroup of the staged sweeps
 constexpr int EDGE_SF = 4;    // edge rows per workgroup of the staged edge fields
-static inline unsigned nblocks(long total) { return (unsigned)((total + 255) / 256); }
 
 template <class MET, typename T>
 static void launch_sweep_t(int d, const Geom& G, const double* prim, const double* cons,
                            const double* tab, double* flux, double* ctd, hipStream_t s) {
-  long total = 1;
-  for (int a = 0; a < 3; ++a) total *= (a == d) ? G.n[a] + 5 : G.dims[a];
   double* fl = flux + (long)d * 5 * G.field;
   double* cd = ctd + (long)d * 6 * G.field;
   if (d == 0) {
-    hipLaunchKernelGGL((k_sweep<0, MET, T>), dim3(nblocks(total)), dim3(256), 0, s, G, prim, cons, tab, fl, cd);
+    hipLaunchKernelGGL((k_sweep<0, MET, T>), dim3(tile_blocks(G.n[0] + 5, G.dims[1], G.dims[2])),
+                       dim3(256), 0, s, G, prim, cons, tab, fl, cd);
     return;
   }
   // tiles: SX transverse positions x SF faces
@@ -337,14 +379,13 @@ static void launch_sweep_t(int d, const Geom& G, const double* prim, const doubl
 template <class MET, typename T>
 static void launch_edge_t(int e, const Geom& G, const double* cons, const double* tab,
                           const double* ctd, double* edges, hipStream_t s) {
-  long total = 1;
-  for (int a = 0; a < 3; ++a) total *= (a == e) ? G.n[a] : G.n[a] + 5;
   const int d = (e + 1) % 3, c = (e + 2) % 3;
   const double* cd = ctd + (long)d * 6 * G.field;
   const double* cc = ctd + (long)c * 6 * G.field;
   double* ed = edges + (long)e * G.field;
   if (e == 1) {
-    hipLaunchKernelGGL((k_edge<1, MET, T>), dim3(nblocks(total)), dim3(256), 0, s, G, cons, tab, cd, cc, ed);
+    hipLaunchKernelGGL((k_edge<1, MET, T>), dim3(tile_blocks(G.n[0] + 5, G.n[2] + 5, G.n[1])),
+                       dim3(256), 0, s, G, cons, tab, cd, cc, ed);
     return;
   }
   // staged families: tiles of SX positions (x^1 and the remaining axis) x SF edges along c
