@@ -52,6 +52,22 @@ static inline unsigned tile_blocks(long ext0, long extm, long exts) {
   return (unsigned)(((ext0 + PX - 1) / PX) * ((extm + 4 * PY - 1) / (4 * PY)) * exts);
 }
 
+// Flattened map (x^1 fastest, then the middle axis): one 64-position row
+// segment per wavefront, no idle lanes at the tile edges.  The x^1 sweep on
+// a tabulated metric, whose faces also load their metric from table rows,
+// measured faster with it.
+__device__ __forceinline__ TilePos flat_pos(int ext0, int extm, int exts) {
+  const long t = flat_thread();
+  TilePos p;
+  p.ok = t < (long)ext0 * extm * exts;
+  const long tc = p.ok ? t : 0;
+  p.a = (int)(tc % ext0);
+  const long r = tc / ext0;
+  p.m = (int)(r % extm);
+  p.s = (int)(r / extm);
+  return p;
+}
+
 template <int DIR, class MET, typename T>
 __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict__ prim,
                                                const double* __restrict__ cons,
@@ -64,7 +80,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
   // tiles: x^1 fastest; for the x^3 sweep x^3 comes next, so the six planes
   // of a stencil are read by neighbouring workgroups (L2 reuse)
   constexpr int MID = DIR == 2 ? 2 : 1, SLOW = DIR == 2 ? 1 : 2;
-  const TilePos tp = tile_pos(ext[0], ext[MID]);
+  const TilePos tp = MET::flat ? tile_pos(ext[0], ext[MID]) : flat_pos(ext[0], ext[MID], ext[SLOW]);
   if (!tp.ok) return;
   int ii[3];
   ii[0] = tp.a;
@@ -364,8 +380,9 @@ static void launch_sweep_t(int d, const Geom& G, const double* prim, const doubl
   double* fl = flux + (long)d * 5 * G.field;
   double* cd = ctd + (long)d * 6 * G.field;
   if (d == 0) {
-    hipLaunchKernelGGL((k_sweep<0, MET, T>), dim3(tile_blocks(G.n[0] + 5, G.dims[1], G.dims[2])),
-                       dim3(256), 0, s, G, prim, cons, tab, fl, cd);
+    const long nf = (long)(G.n[0] + 5) * G.dims[1] * G.dims[2];
+    const unsigned nb = MET::flat ? tile_blocks(G.n[0] + 5, G.dims[1], G.dims[2]) : (unsigned)((nf + 255) / 256);
+    hipLaunchKernelGGL((k_sweep<0, MET, T>), dim3(nb), dim3(256), 0, s, G, prim, cons, tab, fl, cd);
     return;
   }
   // tiles: SX transverse positions x SF faces
