@@ -33,7 +33,7 @@ import numpy as np
 
 from . import fd
 from .fd import take, deriv, interp
-from .mp5 import face_states
+from .recon import face_states, METHODS as RECON_METHODS
 from .physics import state, flux, cons, speeds, prim2cons
 from .hll import hll_speeds, hll_flux
 from .c2p import newton, warm_guess
@@ -106,9 +106,13 @@ class Solver:
     """precision: "fp64", or "fp32" for the precision form in which the
     reconstruction, face physics, HLL flux and edge field are evaluated in
     float32 from float32-rounded inputs and widened to float64 afterwards
-    (derivatives, sources, RK combine and inversion stay float64)."""
+    (derivatives, sources, RK combine and inversion stay float64).
+    recon: interface reconstruction, "mp5" (default), "weno5" or "plm"."""
 
-    def __init__(self, grid, tables=None, precision="fp64"):
+    def __init__(self, grid, tables=None, precision="fp64", recon="mp5"):
+        if recon not in RECON_METHODS:
+            raise ValueError("unknown reconstruction %r" % (recon,))
+        self.recon = recon
         self.grid = grid
         self.ftype = np.float32 if precision == "fp32" else np.float64
         self.g = grid.ng
@@ -196,7 +200,7 @@ class Solver:
         gam = ft(gam)
         rec = {}
         for k in ("rho", "p", "u1", "u2", "u3"):
-            rec[k] = face_states(P[k], d, lo, hi, g, take)
+            rec[k] = face_states(P[k], d, lo, hi, g, take, self.recon)
         # positivity: a reconstructed rho or p is kept at or above a tenth of
         # the value of the cell on its side of the face (continuous bound)
         for k in ("rho", "p"):
@@ -206,7 +210,7 @@ class Solver:
             rec[k] = (np.maximum(l, ft(POS_FRAC) * cj), np.maximum(r, ft(POS_FRAC) * cj1))
         for t in range(3):
             if t != d:
-                rec["B%d" % (t + 1)] = face_states(P["B%d" % (t + 1)], d, lo, hi, g, take)
+                rec["B%d" % (t + 1)] = face_states(P["B%d" % (t + 1)], d, lo, hi, g, take, self.recon)
         mf = {k: v.astype(ft) for k, v in Metric.sel(self.met.loc[FACE_LOC[d]], d, lo, hi, g).items()}
         sg = mf["sqrtg"]
         bn_face = take(self.U["Bf%d" % (d + 1)], d, lo, hi, g).astype(ft)
@@ -250,7 +254,7 @@ class Solver:
         UB = {k: self.U[k].astype(ft) for k in FACE}
         # reconstruct d-face data along c to the edge (side b)
         def along_c(q):
-            l, r = face_states(q, c, -3, nc + 2, g, take)
+            l, r = face_states(q, c, -3, nc + 2, g, take, self.recon)
             return take(l, d, -3, nd + 2, g), take(r, d, -3, nd + 2, g)
         vd = {("L", b): x for b, x in zip("LR", along_c(D["vdL"]))}
         vd.update({("R", b): x for b, x in zip("LR", along_c(D["vdR"]))})
@@ -258,7 +262,7 @@ class Solver:
         vc.update({("R", b): x for b, x in zip("LR", along_c(D["vcR"]))})
         bd = dict(zip("LR", along_c(UB["Bf%d" % (d + 1)])))
         # reconstruct B^c (c-faces) along d (side a)
-        l, r = face_states(UB["Bf%d" % (c + 1)], d, -3, nd + 2, g, take)
+        l, r = face_states(UB["Bf%d" % (c + 1)], d, -3, nd + 2, g, take, self.recon)
         bc = {"L": take(l, c, -3, nc + 2, g), "R": take(r, c, -3, nc + 2, g)}
         # speeds: max over the two faces adjacent to the edge
         def adj(q, along, other, n_along, n_other):

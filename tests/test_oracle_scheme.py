@@ -130,6 +130,61 @@ def test_rhs_operator_fifth_order():
     assert orders[-1] >= 4.7, (errs, orders)
 
 
+def _rhs_errors(recon, ns):
+    linf, l1 = [], []
+    for n in ns:
+        g, d = box.entropy_wave_1d(n, axis=0)
+        s = Solver(g, recon=recon)
+        s.set_face_fields(d)
+        s.set_primitives(d)
+        L = s.rhs()
+        x = (np.arange(n) + 0.5) / n
+        v = np.array([0.3, 0.2, 0.1])
+        w = 1 / np.sqrt(1 - v @ v)
+        e = L["D"][0, 0] - w * (-v[0] * 0.2 * 2 * np.pi * np.cos(2 * np.pi * x))
+        linf.append(np.max(np.abs(e)))
+        l1.append(np.mean(np.abs(e)))
+    order = lambda a: [np.log2(a[i] / a[i + 1]) for i in range(len(a) - 1)]
+    return order(linf), order(l1)
+
+
+def test_rhs_operator_order_weno5():
+    # WENO5's nonlinear weights keep fifth order on the smooth wave
+    linf, l1 = _rhs_errors("weno5", (16, 32, 64))
+    assert linf[-1] >= 4.7 and l1[-1] >= 4.7, (linf, l1)
+
+
+def test_rhs_operator_order_plm():
+    # second order in L1; first order in the maximum norm, because the MC
+    # limiter reduces the reconstruction to the cell value at the extrema
+    linf, l1 = _rhs_errors("plm", (16, 32, 64))
+    assert l1[-1] >= 1.9, l1
+    assert 0.9 < linf[-1] < 1.1, linf
+
+
+@pytest.mark.parametrize("recon", ["weno5", "plm"])
+def test_conservation_and_divb_other_reconstructions(recon):
+    g, d = box.turbulent_box(12)
+    s = Solver(g, recon=recon)
+    s.curl_potential(d)
+    s.set_primitives(d)
+    d0 = s.diagnostics()
+    for _ in range(3):
+        s.rk_step()
+    d1 = s.diagnostics()
+    for grp in (("D",), ("tau",), ("S1", "S2", "S3"), ("Bf1", "Bf2", "Bf3")):
+        scale = sum(np.abs(s.interior(s.U[k])).sum() for k in grp)
+        for k in grp:
+            assert abs(d1["sum_" + k] - d0["sum_" + k]) <= 1e-13 * scale, k
+    assert d1["max_divb"] <= 1e-12
+
+
+def test_unknown_reconstruction_rejected():
+    g, _ = box.turbulent_box(8)
+    with pytest.raises(ValueError):
+        Solver(g, recon="ppm")
+
+
 # ------------------------------------------------------------ metric tables
 def test_kerr_schild_tables_pins():
     gr = torus_grid(16, 12, 4)
