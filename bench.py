@@ -137,6 +137,53 @@ def precision_report(args):
     print(json.dumps(out))
 
 
+def recon_report(args):
+    """The three reconstructions on the turbulent box: each grid starts from
+    the same seeded data, runs args.warmup steps, then args.steps timed RK3
+    steps with the device CFL step; per-kernel HIP-event averages."""
+    import torch
+    from workloads import box
+    from paper_1810_04597_amd.grid import Grid
+    n = args.n
+    g, d = box.turbulent_box(n)
+    res = {}
+    for name in ("mp5", "weno5", "plm"):
+        G = Grid(g, recon=name)
+        G.curl_potential(d)
+        G.set_primitives(d)
+        for _ in range(args.warmup):
+            G.rk_step()
+        G.synchronize()
+        G.set_profiling(True)
+        G.profile(reset=True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(G.stream)
+        for _ in range(args.steps):
+            G.rk_step()
+        e1.record(G.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        prof = G.profile(reset=True)
+        dg = G.diagnostics()
+        res[name] = {"ms_per_step": ms / args.steps,
+                     "zone_updates_per_s": n ** 3 * args.steps / (ms / 1e3),
+                     "kernels_avg_ms": {k: t / c for k, (t, c) in prof.items()},
+                     "max_divb": dg["max_divb"], "n_c2p_fail": dg["n_c2p_fail"], "t": dg["t"]}
+        G.close()
+        del G
+        print("bench: %s done" % name, file=sys.stderr, flush=True)
+    out = {"metric": "zone-updates/s per RK3 step by reconstruction (%d^3)" % n,
+           "value": res["mp5"]["zone_updates_per_s"], "unit": "zone-updates/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["mp5"]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "turbulent SRMHD box %d^3, device CFL 0.4, seed 1810" % n},
+           "recon": res}
+    print(json.dumps(out))
+
+
 def torus_report(args):
     """Plain FP64 GRMHD torus (Kerr-Schild a = 0.9, tabulated metric, floors,
     device CFL step): zone-updates/s and per-kernel times."""
@@ -359,11 +406,13 @@ def main():
                     help="after the timed steps, one plain device copy of CALIB_COPY_BYTES "
                          "(reference for scaling the HBM traffic counters)")
     ap.add_argument("--profile-kernels", action="store_true", default=True)
-    ap.add_argument("--mode", default="step", choices=["step", "precision", "learned", "torus", "torus-long"],
+    ap.add_argument("--mode", default="step",
+                    choices=["step", "precision", "learned", "torus", "torus-long", "recon"],
                     help="step: the FP64 RK3 step (default); precision: FP32-flux form "
                          "against FP64 on the same grid, fixed dt, per-field error; learned: "
                          "train the Newton-guess network on the GPU, then the Kerr-Schild "
-                         "torus in plain FP64 vs FP32 flux + learned guess")
+                         "torus in plain FP64 vs FP32 flux + learned guess; recon: the step "
+                         "with MP5, WENO5 and PLM-MC reconstruction")
     ap.add_argument("--train-samples", type=int, default=1 << 22)
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--torus", default="384,192,192")
@@ -382,6 +431,8 @@ def main():
         return torus_report(args)
     if args.mode == "torus-long":
         return torus_long_report(args)
+    if args.mode == "recon":
+        return recon_report(args)
 
     import torch
     from workloads import box

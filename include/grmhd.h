@@ -61,6 +61,13 @@ enum { GRMHD_CART = 0, GRMHD_LOGSPH = 1 };          /* (x,y,z) | (ln r, theta, p
 enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_AXIS = 2 };
 enum { GRMHD_FP64 = 0, GRMHD_FP32_FLUX = 1 };
 enum { GRMHD_GUESS_WARM = 0, GRMHD_GUESS_COLD = 1, GRMHD_GUESS_MLP = 2 };
+/* Interface reconstruction (paper, Introduction: high-order reconstruction
+ * algorithms), applied to point values at cell centres on the six cells
+ * f-2 .. f+3 around face f+1/2: MP5 (Suresh & Huynh 1997, point-value
+ * interpolant, zero limiter tolerance; the default), WENO5 (Jiang & Shu 1996
+ * indicators, point-value form, eps = 1e-6), PLM with the monotonized-central
+ * limiter (second order, the lower-order member). */
+enum { GRMHD_RECON_MP5 = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_PLM = 2 };
 enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_TABLE_AXISYM = 1 };
 
 /* Number of float64 components of an axisymmetric metric table per (j, i):
@@ -81,7 +88,7 @@ typedef struct {
   int32_t precision;       /* GRMHD_FP64 | GRMHD_FP32_FLUX                       */
   int32_t c2p_guess;       /* GRMHD_GUESS_WARM | _COLD | _MLP                     */
   int32_t newton_maxit;    /* e.g. 50                                             */
-  int32_t reserved;        /* must be 0                                           */
+  int32_t recon;           /* GRMHD_RECON_MP5 (0) | _WENO5 | _PLM                 */
   double x0[3];            /* lower interior edge in code coordinates            */
   double dx[3];            /* uniform spacing (> 0)                              */
   double gamma_ad;         /* ideal-gas index (> 1)                              */

@@ -10,6 +10,8 @@ CART, LOGSPH = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_AXIS = 0, 1, 2
 FP64, FP32_FLUX = 0, 1
 GUESS_WARM, GUESS_COLD, GUESS_MLP = 0, 1, 2
+RECON_MP5, RECON_WENO5, RECON_PLM = 0, 1, 2
+RECON = {"mp5": RECON_MP5, "weno5": RECON_WENO5, "plm": RECON_PLM}
 METRIC_MINKOWSKI, METRIC_TABLE_AXISYM = 0, 1
 METRIC_NCOMP = 88
 
@@ -28,7 +30,7 @@ PROF_NCLASS = 16
 class GridDesc(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("ng", C.c_int32), ("coord", C.c_int32),
                 ("bc", C.c_int32 * 6), ("precision", C.c_int32), ("c2p_guess", C.c_int32),
-                ("newton_maxit", C.c_int32), ("reserved", C.c_int32),
+                ("newton_maxit", C.c_int32), ("recon", C.c_int32),
                 ("x0", C.c_double * 3), ("dx", C.c_double * 3), ("gamma_ad", C.c_double),
                 ("cfl", C.c_double), ("rho_fl_a", C.c_double), ("rho_fl_n", C.c_double),
                 ("p_fl_a", C.c_double), ("p_fl_n", C.c_double), ("w_max", C.c_double),
@@ -125,7 +127,7 @@ def check(rc):
     return rc
 
 
-def make_desc(grid, precision=FP64, guess=GUESS_WARM):
+def make_desc(grid, precision=FP64, guess=GUESS_WARM, recon=RECON_MP5):
     """GridDesc from a workloads.GridSpec-like object."""
     d = GridDesc()
     for a in range(3):
@@ -139,7 +141,7 @@ def make_desc(grid, precision=FP64, guess=GUESS_WARM):
     d.precision = precision
     d.c2p_guess = guess
     d.newton_maxit = grid.newton_maxit
-    d.reserved = 0
+    d.recon = recon
     d.gamma_ad = grid.gamma_ad
     d.cfl = grid.cfl
     d.rho_fl_a, d.rho_fl_n = grid.rho_fl_a, grid.rho_fl_n

@@ -11,6 +11,10 @@
 
 #include "grmhd.h"
 #include "grmhd_kernels.hpp"
+
+static_assert(GRMHD_RECON_MP5 == grmhd::RECON_MP5 && GRMHD_RECON_WENO5 == grmhd::RECON_WENO5 &&
+                  GRMHD_RECON_PLM == grmhd::RECON_PLM,
+              "reconstruction codes of the ABI and the kernels agree");
 #include "grmhd_mlp.hpp"
 
 using namespace grmhd;
@@ -134,7 +138,8 @@ int validate(const grmhd_grid_desc* d) {
   if (!(d->newton_tol > 0.0)) return fail(GRMHD_EINVAL, "newton_tol must be > 0");
   if (d->rho_fl_a < 0.0 || d->p_fl_a < 0.0) return fail(GRMHD_EINVAL, "negative floor");
   if (d->w_max != 0.0 && !(d->w_max > 1.0)) return fail(GRMHD_EINVAL, "w_max must be 0 or > 1");
-  if (d->reserved != 0) return fail(GRMHD_EINVAL, "reserved must be 0");
+  if (d->recon != GRMHD_RECON_MP5 && d->recon != GRMHD_RECON_WENO5 && d->recon != GRMHD_RECON_PLM)
+    return fail(GRMHD_EINVAL, "bad recon");
   return GRMHD_OK;
 }
 
@@ -309,10 +314,13 @@ static void rhs_pieces(grmhd_grid* h, bool fill_ghosts = true) {
   if (fill_ghosts) h->timed(0, [&] { launch_bc_centred(h->G, h->bc, h->prim, NPRIM, h->stream); });
   for (int d = 0; d < 3; ++d)
     h->timed(1 + d, [&] {
-      launch_sweep(d, h->G, h->flat, fp32, h->prim, h->cons, h->tab, h->flux(), h->ctd(), h->stream);
+      launch_sweep(d, h->G, h->flat, fp32, h->desc.recon, h->prim, h->cons, h->tab, h->flux(), h->ctd(),
+                   h->stream);
     });
   for (int e = 0; e < 3; ++e)
-    h->timed(4 + e, [&] { launch_edge(e, h->G, h->flat, fp32, h->cons, h->tab, h->ctd(), h->edges(), h->stream); });
+    h->timed(4 + e, [&] {
+      launch_edge(e, h->G, h->flat, fp32, h->desc.recon, h->cons, h->tab, h->ctd(), h->edges(), h->stream);
+    });
 }
 
 // with_cfl: also reduce the CFL time step of the inverted state into d_dt[2].

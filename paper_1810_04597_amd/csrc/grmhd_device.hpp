@@ -141,6 +141,56 @@ GR_HD void mp5_lr(const T c[6], T& l, T& r) {
   r = mp5(c[5], c[4], c[3], c[2], c[1]);
 }
 
+// WENO5 in point-value form (Jiang & Shu 1996 smoothness indicators): the
+// three quadratic interpolants at the face, combined with the weights
+// d_k / (eps + beta_k)^2 normalised, d = (1, 10, 5)/16 (whose linear
+// combination is the degree-4 interpolant above), eps = 1e-6.  Written with
+// one division: w_k p_k summed over the common denominator.
+template <typename T>
+GR_HD T weno5(T qm2, T qm1, T q0, T qp1, T qp2) {
+  const T p0 = T(3.0 / 8) * qm2 - T(10.0 / 8) * qm1 + T(15.0 / 8) * q0;
+  const T p1 = T(-1.0 / 8) * qm1 + T(6.0 / 8) * q0 + T(3.0 / 8) * qp1;
+  const T p2 = T(3.0 / 8) * q0 + T(6.0 / 8) * qp1 - T(1.0 / 8) * qp2;
+  const T c0 = qm2 - T(2) * qm1 + q0, e0 = qm2 - T(4) * qm1 + T(3) * q0;
+  const T c1 = qm1 - T(2) * q0 + qp1, e1 = qm1 - qp1;
+  const T c2 = q0 - T(2) * qp1 + qp2, e2 = T(3) * q0 - T(4) * qp1 + qp2;
+  const T s0 = T(1e-6) + T(13.0 / 12) * c0 * c0 + T(0.25) * e0 * e0;
+  const T s1 = T(1e-6) + T(13.0 / 12) * c1 * c1 + T(0.25) * e1 * e1;
+  const T s2 = T(1e-6) + T(13.0 / 12) * c2 * c2 + T(0.25) * e2 * e2;
+  // alpha_k = d_k / s_k^2; multiply numerator and denominator by (s0 s1 s2)^2
+  const T q0s = s0 * s0, q1s = s1 * s1, q2s = s2 * s2;
+  const T a0 = T(1.0 / 16) * (q1s * q2s), a1 = T(10.0 / 16) * (q0s * q2s), a2 = T(5.0 / 16) * (q0s * q1s);
+  return (a0 * p0 + a1 * p1 + a2 * p2) / (a0 + a1 + a2);
+}
+
+// PLM with the monotonized-central limiter (van Leer 1977): the cell value
+// plus half the slope minmod(2 dl, 2 dr, (dl + dr)/2).
+template <typename T>
+GR_HD T plm_mc(T qm1, T q0, T qp1) {
+  const T dl = q0 - qm1, dr = qp1 - q0;
+  const T m = fmin(fmin(fabs(dl + dl), fabs(dr + dr)), fabs(T(0.5) * (dl + dr)));
+  const int sl = sign_word(dl), sr = sign_word(dr);
+  // same sign and neither zero (a zero difference gives m = 0 anyway)
+  const T slope = (sl ^ sr) >= 0 ? (sl < 0 ? -m : m) : T(0);
+  return q0 + T(0.5) * slope;
+}
+
+// Interface reconstructions: RECON_MP5 (default), RECON_WENO5, RECON_PLM.
+constexpr int RECON_MP5 = 0, RECON_WENO5 = 1, RECON_PLM = 2;
+
+template <int RC, typename T>
+GR_HD void recon_lr(const T c[6], T& l, T& r) {
+  if constexpr (RC == RECON_WENO5) {
+    l = weno5(c[0], c[1], c[2], c[3], c[4]);
+    r = weno5(c[5], c[4], c[3], c[2], c[1]);
+  } else if constexpr (RC == RECON_PLM) {
+    l = plm_mc(c[1], c[2], c[3]);
+    r = plm_mc(c[4], c[3], c[2]);
+  } else {
+    mp5_lr(c, l, r);
+  }
+}
+
 // ------------------------------------------------------------------ FD operators
 // Sixth-order staggered derivative at m from f_{m-5/2..m+5/2} = f[0..5]
 // (stored indices m-3 .. m+2).
@@ -304,23 +354,23 @@ GR_HD T hll(T fl, T fr, T ul, T ur, T ap, T am, T inv_s, bool tiny) {
 constexpr double POS_FRAC = 0.1;
 // q[v][s]: six cells f-2 .. f+3 of the reconstructed variables in the order
 // rho, p, u^1, u^2, u^3, B^{d+1}, B^{d+2}; bn: normal B at the face.
-template <int DIR, typename T, class M>
+template <int DIR, int RC = RECON_MP5, typename T, class M>
 GR_HD void face_body(const T q[7][6], T bn, bool axis, const M& m, T gam, T fh[5], T ctd[6]) {
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
   PState<T> sl, sr;
   // rho and p states are kept at or above POS_FRAC times the cell value on
   // their side of the face (a continuous positivity bound)
-  mp5_lr(q[0], sl.rho, sr.rho);
+  recon_lr<RC>(q[0], sl.rho, sr.rho);
   sl.rho = fmax(sl.rho, T(POS_FRAC) * q[0][2]);
   sr.rho = fmax(sr.rho, T(POS_FRAC) * q[0][3]);
-  mp5_lr(q[1], sl.p, sr.p);
+  recon_lr<RC>(q[1], sl.p, sr.p);
   sl.p = fmax(sl.p, T(POS_FRAC) * q[1][2]);
   sr.p = fmax(sr.p, T(POS_FRAC) * q[1][3]);
-  mp5_lr(q[2], sl.u[0], sr.u[0]);
-  mp5_lr(q[3], sl.u[1], sr.u[1]);
-  mp5_lr(q[4], sl.u[2], sr.u[2]);
-  mp5_lr(q[5], sl.B[T1], sr.B[T1]);
-  mp5_lr(q[6], sl.B[T2], sr.B[T2]);
+  recon_lr<RC>(q[2], sl.u[0], sr.u[0]);
+  recon_lr<RC>(q[3], sl.u[1], sr.u[1]);
+  recon_lr<RC>(q[4], sl.u[2], sr.u[2]);
+  recon_lr<RC>(q[5], sl.B[T1], sr.B[T1]);
+  recon_lr<RC>(q[6], sl.B[T2], sr.B[T2]);
   sl.B[DIR] = bn;
   sr.B[DIR] = bn;
   make_state(sl, m, gam);
@@ -354,17 +404,17 @@ GR_HD void face_body(const T q[7][6], T bn, bool axis, const M& m, T gam, T fh[5
 // Edge field of family E (d = E+1, c = E+2 mod 3).  qd[v][s]: six d-faces
 // along c of v^d_L, v^d_R, v^c_L, v^c_R, B^d; qc[s]: six c-faces along d of
 // B^c; a*: speeds of the two adjacent faces of each family.
-template <int E, typename T, class M>
+template <int E, int RC = RECON_MP5, typename T, class M>
 GR_HD T edge_body(const T qd[5][6], const T qc[6], T apd0, T apd1, T amd0, T amd1,
                   T apc0, T apc1, T amc0, T amc1, const M& m) {
   constexpr int D = (E + 1) % 3, C = (E + 2) % 3;
   T vd[2][2], vc[2][2], bd[2], bc[2];   // [a][b]
-  mp5_lr(qd[0], vd[0][0], vd[0][1]);
-  mp5_lr(qd[1], vd[1][0], vd[1][1]);
-  mp5_lr(qd[2], vc[0][0], vc[0][1]);
-  mp5_lr(qd[3], vc[1][0], vc[1][1]);
-  mp5_lr(qd[4], bd[0], bd[1]);
-  mp5_lr(qc, bc[0], bc[1]);
+  recon_lr<RC>(qd[0], vd[0][0], vd[0][1]);
+  recon_lr<RC>(qd[1], vd[1][0], vd[1][1]);
+  recon_lr<RC>(qd[2], vc[0][0], vc[0][1]);
+  recon_lr<RC>(qd[3], vc[1][0], vc[1][1]);
+  recon_lr<RC>(qd[4], bd[0], bd[1]);
+  recon_lr<RC>(qc, bc[0], bc[1]);
   const T apd = fmax(apd0, apd1), amd = fmax(amd0, amd1);
   const T apc = fmax(apc0, apc1), amc = fmax(amc0, amc1);
   const T sdd = apd + amd, scc = apc + amc;

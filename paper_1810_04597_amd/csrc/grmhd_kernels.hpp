@@ -30,10 +30,11 @@ struct BCSpec {
 
 void launch_bc_centred(const Geom& G, const BCSpec& bc, double* prim, int nfields, hipStream_t s);
 void launch_bc_faces(const Geom& G, const BCSpec& bc, double* cons, hipStream_t s);
-void launch_sweep(int d, const Geom& G, bool flat, bool fp32, const double* prim,
+// recon: RECON_MP5 | RECON_WENO5 | RECON_PLM (grmhd_device.hpp)
+void launch_sweep(int d, const Geom& G, bool flat, bool fp32, int recon, const double* prim,
                   const double* cons, const double* tab, double* flux, double* ctd, hipStream_t s);
-void launch_edge(int e, const Geom& G, bool flat, bool fp32, const double* cons, const double* tab,
-                 const double* ctd, double* edges, hipStream_t s);
+void launch_edge(int e, const Geom& G, bool flat, bool fp32, int recon, const double* cons,
+                 const double* tab, const double* ctd, double* edges, hipStream_t s);
 // mode 0: RK combine into cons (needs cons_n, a, b, dt on device);
 // mode 1: write L into out (cons layout).
 // img (flat metric, mode 0): all directions periodic with n >= 2 NG; the new

@@ -68,7 +68,7 @@ __device__ __forceinline__ TilePos flat_pos(int ext0, int extm, int exts) {
   return p;
 }
 
-template <int DIR, class MET, typename T>
+template <int DIR, class MET, typename T, int RC>
 __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict__ prim,
                                                const double* __restrict__ cons,
                                                const double* __restrict__ tab,
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
     bn = axis ? T(0) : T(bface) / m.sg;
   }
   T fh[5], cd[6];
-  face_body<DIR>(q, bn, axis, m, gam, fh, cd);
+  face_body<DIR, RC>(q, bn, axis, m, gam, fh, cd);
 #pragma unroll
   for (int q5 = 0; q5 < 5; ++q5) flux[(long)q5 * G.field + c] = double(fh[q5]);
 #pragma unroll
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
 constexpr int SX = 64;
 constexpr int LPAD = 0;   // extra doubles per LDS row
 
-template <int DIR, int SF, class MET, typename T>
+template <int DIR, int SF, class MET, typename T, int RC>
 __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __restrict__ prim,
                                                    const double* __restrict__ cons,
                                                    const double* __restrict__ tab,
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
     bn = axis ? T(0) : T(bface) / m.sg;
   }
   T fh[5], cd[6];
-  face_body<DIR>(q, bn, axis, m, gam, fh, cd);
+  face_body<DIR, RC>(q, bn, axis, m, gam, fh, cd);
 #pragma unroll
   for (int q5 = 0; q5 < 5; ++q5) flux[(long)q5 * G.field + c] = double(fh[q5]);
 #pragma unroll
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
 }
 
 // Edge field of family E.  ctd_d / ctd_c: per-face data of the d and c sweeps.
-template <int E, class MET, typename T>
+template <int E, class MET, typename T, int RC>
 __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__ cons,
                                               const double* __restrict__ tab,
                                               const double* __restrict__ ctd_d,
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
     constexpr int loc = E == 2 ? LOC_E3 : (E == 0 ? LOC_F2 : LOC_F1);
     m.load(tab, G.tab_plane, loc, G.tidx(ii[0], ii[1]));
   }
-  const T ee = edge_body<E>(qd, qc, T(ctd_d[4 * G.field + b]), T(ctd_d[4 * G.field + b + sc]),
+  const T ee = edge_body<E, RC>(qd, qc, T(ctd_d[4 * G.field + b]), T(ctd_d[4 * G.field + b + sc]),
                             T(ctd_d[5 * G.field + b]), T(ctd_d[5 * G.field + b + sc]),
                             T(ctd_c[4 * G.field + b]), T(ctd_c[4 * G.field + b + sd]),
                             T(ctd_c[5 * G.field + b]), T(ctd_c[5 * G.field + b + sd]), m);
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
 // SX consecutive positions (flattened, x^1 fastest) times SF edges along c;
 // the SF + 5 rows of the five inputs are staged once per workgroup.  The
 // c-face B (along d) and the four speeds are read directly.
-template <int E, int SF, class MET, typename T>
+template <int E, int SF, class MET, typename T, int RC>
 __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __restrict__ cons,
                                                       const double* __restrict__ tab,
                                                       const double* __restrict__ ctd_d,
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
     constexpr int loc = E == 2 ? LOC_E3 : LOC_F2;
     m.load(tab, G.tab_plane, loc, G.tidx(ii[0], ii[1]));
   }
-  const T ee = edge_body<E>(qd, qc, T(ctd_d[4 * G.field + b]), T(ctd_d[4 * G.field + b + sc]),
+  const T ee = edge_body<E, RC>(qd, qc, T(ctd_d[4 * G.field + b]), T(ctd_d[4 * G.field + b + sc]),
                             T(ctd_d[5 * G.field + b]), T(ctd_d[5 * G.field + b + sc]),
                             T(ctd_c[4 * G.field + b]), T(ctd_c[4 * G.field + b + sd]),
                             T(ctd_c[5 * G.field + b]), T(ctd_c[5 * G.field + b + sd]), m);
@@ -374,7 +374,7 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
 constexpr int SWEEP_SF = 4;   // face rows per workgroup of the staged sweeps
 constexpr int EDGE_SF = 4;    // edge rows per workgroup of the staged edge fields
 
-template <class MET, typename T>
+template <class MET, typename T, int RC>
 static void launch_sweep_t(int d, const Geom& G, const double* prim, const double* cons,
                            const double* tab, double* flux, double* ctd, hipStream_t s) {
   double* fl = flux + (long)d * 5 * G.field;
@@ -382,18 +382,18 @@ static void launch_sweep_t(int d, const Geom& G, const double* prim, const doubl
   if (d == 0) {
     const long nf = (long)(G.n[0] + 5) * G.dims[1] * G.dims[2];
     const unsigned nb = MET::flat ? tile_blocks(G.n[0] + 5, G.dims[1], G.dims[2]) : (unsigned)((nf + 255) / 256);
-    hipLaunchKernelGGL((k_sweep<0, MET, T>), dim3(nb), dim3(256), 0, s, G, prim, cons, tab, fl, cd);
+    hipLaunchKernelGGL((k_sweep<0, MET, T, RC>), dim3(nb), dim3(256), 0, s, G, prim, cons, tab, fl, cd);
     return;
   }
   // tiles: SX transverse positions x SF faces
   constexpr int SF = SWEEP_SF;
   const long M = (long)G.dims[0] * G.dims[d == 1 ? 2 : 1];
   const long tiles = ((M + SX - 1) / SX) * ((G.n[d] + 5 + SF - 1) / SF);
-  if (d == 1) hipLaunchKernelGGL((k_sweep_lds<1, SF, MET, T>), dim3(tiles), dim3(SX * SF), 0, s, G, prim, cons, tab, fl, cd);
-  if (d == 2) hipLaunchKernelGGL((k_sweep_lds<2, SF, MET, T>), dim3(tiles), dim3(SX * SF), 0, s, G, prim, cons, tab, fl, cd);
+  if (d == 1) hipLaunchKernelGGL((k_sweep_lds<1, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, prim, cons, tab, fl, cd);
+  if (d == 2) hipLaunchKernelGGL((k_sweep_lds<2, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, prim, cons, tab, fl, cd);
 }
 
-template <class MET, typename T>
+template <class MET, typename T, int RC>
 static void launch_edge_t(int e, const Geom& G, const double* cons, const double* tab,
                           const double* ctd, double* edges, hipStream_t s) {
   const int d = (e + 1) % 3, c = (e + 2) % 3;
@@ -401,7 +401,7 @@ static void launch_edge_t(int e, const Geom& G, const double* cons, const double
   const double* cc = ctd + (long)c * 6 * G.field;
   double* ed = edges + (long)e * G.field;
   if (e == 1) {
-    hipLaunchKernelGGL((k_edge<1, MET, T>), dim3(tile_blocks(G.n[0] + 5, G.n[2] + 5, G.n[1])),
+    hipLaunchKernelGGL((k_edge<1, MET, T, RC>), dim3(tile_blocks(G.n[0] + 5, G.n[2] + 5, G.n[1])),
                        dim3(256), 0, s, G, cons, tab, cd, cc, ed);
     return;
   }
@@ -410,24 +410,41 @@ static void launch_edge_t(int e, const Geom& G, const double* cons, const double
   const int B = 3 - c;
   const long M = (long)((e == 0) ? G.n[0] : G.n[0] + 5) * ((B == e) ? G.n[B] : G.n[B] + 5);
   const long tiles = ((M + SX - 1) / SX) * ((G.n[c] + 5 + SF - 1) / SF);
-  if (e == 0) hipLaunchKernelGGL((k_edge_lds<0, SF, MET, T>), dim3(tiles), dim3(SX * SF), 0, s, G, cons, tab, cd, cc, ed);
-  if (e == 2) hipLaunchKernelGGL((k_edge_lds<2, SF, MET, T>), dim3(tiles), dim3(SX * SF), 0, s, G, cons, tab, cd, cc, ed);
+  if (e == 0) hipLaunchKernelGGL((k_edge_lds<0, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, cons, tab, cd, cc, ed);
+  if (e == 2) hipLaunchKernelGGL((k_edge_lds<2, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, cons, tab, cd, cc, ed);
 }
 
-void launch_sweep(int d, const Geom& G, bool flat, bool fp32, const double* prim, const double* cons,
-                  const double* tab, double* flux, double* ctd, hipStream_t s) {
-  if (flat && !fp32) launch_sweep_t<FlatMet<double>, double>(d, G, prim, cons, tab, flux, ctd, s);
-  if (flat && fp32) launch_sweep_t<FlatMet<float>, float>(d, G, prim, cons, tab, flux, ctd, s);
-  if (!flat && !fp32) launch_sweep_t<TabMet<double>, double>(d, G, prim, cons, tab, flux, ctd, s);
-  if (!flat && fp32) launch_sweep_t<TabMet<float>, float>(d, G, prim, cons, tab, flux, ctd, s);
+template <int RC>
+static void launch_sweep_r(int d, const Geom& G, bool flat, bool fp32, const double* prim,
+                           const double* cons, const double* tab, double* flux, double* ctd,
+                           hipStream_t s) {
+  if (flat && !fp32) launch_sweep_t<FlatMet<double>, double, RC>(d, G, prim, cons, tab, flux, ctd, s);
+  if (flat && fp32) launch_sweep_t<FlatMet<float>, float, RC>(d, G, prim, cons, tab, flux, ctd, s);
+  if (!flat && !fp32) launch_sweep_t<TabMet<double>, double, RC>(d, G, prim, cons, tab, flux, ctd, s);
+  if (!flat && fp32) launch_sweep_t<TabMet<float>, float, RC>(d, G, prim, cons, tab, flux, ctd, s);
 }
 
-void launch_edge(int e, const Geom& G, bool flat, bool fp32, const double* cons, const double* tab,
-                 const double* ctd, double* edges, hipStream_t s) {
-  if (flat && !fp32) launch_edge_t<FlatMet<double>, double>(e, G, cons, tab, ctd, edges, s);
-  if (flat && fp32) launch_edge_t<FlatMet<float>, float>(e, G, cons, tab, ctd, edges, s);
-  if (!flat && !fp32) launch_edge_t<TabMet<double>, double>(e, G, cons, tab, ctd, edges, s);
-  if (!flat && fp32) launch_edge_t<TabMet<float>, float>(e, G, cons, tab, ctd, edges, s);
+template <int RC>
+static void launch_edge_r(int e, const Geom& G, bool flat, bool fp32, const double* cons,
+                          const double* tab, const double* ctd, double* edges, hipStream_t s) {
+  if (flat && !fp32) launch_edge_t<FlatMet<double>, double, RC>(e, G, cons, tab, ctd, edges, s);
+  if (flat && fp32) launch_edge_t<FlatMet<float>, float, RC>(e, G, cons, tab, ctd, edges, s);
+  if (!flat && !fp32) launch_edge_t<TabMet<double>, double, RC>(e, G, cons, tab, ctd, edges, s);
+  if (!flat && fp32) launch_edge_t<TabMet<float>, float, RC>(e, G, cons, tab, ctd, edges, s);
+}
+
+void launch_sweep(int d, const Geom& G, bool flat, bool fp32, int recon, const double* prim,
+                  const double* cons, const double* tab, double* flux, double* ctd, hipStream_t s) {
+  if (recon == RECON_WENO5) launch_sweep_r<RECON_WENO5>(d, G, flat, fp32, prim, cons, tab, flux, ctd, s);
+  else if (recon == RECON_PLM) launch_sweep_r<RECON_PLM>(d, G, flat, fp32, prim, cons, tab, flux, ctd, s);
+  else launch_sweep_r<RECON_MP5>(d, G, flat, fp32, prim, cons, tab, flux, ctd, s);
+}
+
+void launch_edge(int e, const Geom& G, bool flat, bool fp32, int recon, const double* cons,
+                 const double* tab, const double* ctd, double* edges, hipStream_t s) {
+  if (recon == RECON_WENO5) launch_edge_r<RECON_WENO5>(e, G, flat, fp32, cons, tab, ctd, edges, s);
+  else if (recon == RECON_PLM) launch_edge_r<RECON_PLM>(e, G, flat, fp32, cons, tab, ctd, edges, s);
+  else launch_edge_r<RECON_MP5>(e, G, flat, fp32, cons, tab, ctd, edges, s);
 }
 
 }  // namespace grmhd

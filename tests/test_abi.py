@@ -55,7 +55,8 @@ def _desc(L, **kw):
     ("c2p_guess", 3, "bad c2p_guess"),
     ("newton_maxit", 0, "bad newton_maxit"),
     ("gamma_ad", 1.0, "gamma_ad"),
-    ("reserved", 1, "reserved"),
+    ("recon", 3, "bad recon"),
+    ("recon", -1, "bad recon"),
 ])
 def test_descriptor_validation_before_any_device_call(field, value, msg):
     L, lib = _lib()
