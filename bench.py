@@ -184,6 +184,88 @@ def recon_report(args):
     print(json.dumps(out))
 
 
+def split_report(args):
+    """Split inversion (Newton load balance).  (a) Inversions with a large
+    spread of Newton iterations: the Kerr-Schild torus (args.torus) whose
+    stored primitives are replaced by a uniform state (a poor warm start),
+    and the same with the cold start Gamma U, each timed for first-pass
+    limits K = 0 (one pass), 2, 3, 4, 6 (the inversion's and the second
+    pass's HIP-event times, median of 5 calls, the same conserved state each
+    call).  (b) The regular FP64 box step with K = 0 and K = 3."""
+    import torch
+    from workloads.torus import torus
+    from workloads import box
+    from paper_1810_04597_amd.grid import Grid
+    from paper_1810_04597_amd import _lib as L
+    n1, n2, n3 = (int(x) for x in args.torus.split(","))
+    g, d, tab = torus(n1, n2, n3)
+    inv = {}
+    for label, guess in (("poor_warm", L.GUESS_WARM), ("cold", L.GUESS_COLD)):
+        G = Grid(g, tables=tab, guess=guess)
+        G.curl_potential(d)
+        G.set_primitives(d)
+        cons0 = G.cons.clone()
+        res = {}
+        for k in (0, 2, 3, 4, 6):
+            G.set_newton_split(k)
+            times = []
+            for rep in range(5):
+                G.cons.copy_(cons0)
+                for f, val in ((0, 1.0), (1, 0.0), (2, 0.0), (3, 0.0), (4, 1.0)):
+                    G._interior(G.field_view(G.prim, f)).fill_(val)
+                G.synchronize()
+                G.set_profiling(True)
+                G.profile(reset=True)
+                nf = G.cons2prim()
+                prof = G.profile(reset=True)
+                G.set_profiling(False)
+                times.append((prof["cons2prim"][0], prof.get("newton_split", (0.0, 0))[0]))
+            times.sort(key=lambda x: x[0] + x[1])
+            dg = G.diagnostics()
+            first, second = times[len(times) // 2]
+            res["K=%d" % k] = {"first_pass_ms": first, "second_pass_ms": second,
+                               "total_ms": first + second, "n_fail": nf,
+                               "iters_per_zone": dg["newton_iters_sum"] / g.zones,
+                               "iters_max_per_pass": dg["newton_iters_max"]}
+        G.close()
+        del G
+        inv[label] = res
+        print("bench: split %s done" % label, file=sys.stderr, flush=True)
+    del d
+    gb, db = box.turbulent_box(args.n)
+    step = {}
+    for k in (0, 3):
+        G = Grid(gb)
+        G.set_newton_split(k)
+        G.curl_potential(db)
+        G.set_primitives(db)
+        for _ in range(args.warmup):
+            G.rk_step()
+        G.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(G.stream)
+        for _ in range(args.steps):
+            G.rk_step()
+        e1.record(G.stream)
+        torch.cuda.synchronize()
+        step["K=%d" % k] = e0.elapsed_time(e1) / args.steps
+        G.close()
+        del G
+    base = inv["poor_warm"]["K=0"]["total_ms"]
+    best = min(inv["poor_warm"].items(), key=lambda kv: kv[1]["total_ms"])
+    out = {"metric": "inversion time, split vs one pass, KS torus %dx%dx%d, poor warm start" % (n1, n2, n3),
+           "value": best[1]["total_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": step["K=3"], "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "Kerr-Schild a=0.9 torus %dx%dx%d, stored primitives uniform "
+                                  "(rho = p = 1, u = 0) before the inversion; box %d^3 step" % (n1, n2, n3, args.n)},
+           "best_K": best[0], "speedup_vs_one_pass": base / best[1]["total_ms"],
+           "inversion": inv, "box_step_ms": step}
+    print(json.dumps(out))
+
+
 def torus_report(args):
     """Plain FP64 GRMHD torus (Kerr-Schild a = 0.9, tabulated metric, floors,
     device CFL step): zone-updates/s and per-kernel times."""
@@ -407,12 +489,13 @@ def main():
                          "(reference for scaling the HBM traffic counters)")
     ap.add_argument("--profile-kernels", action="store_true", default=True)
     ap.add_argument("--mode", default="step",
-                    choices=["step", "precision", "learned", "torus", "torus-long", "recon"],
+                    choices=["step", "precision", "learned", "torus", "torus-long", "recon", "split"],
                     help="step: the FP64 RK3 step (default); precision: FP32-flux form "
                          "against FP64 on the same grid, fixed dt, per-field error; learned: "
                          "train the Newton-guess network on the GPU, then the Kerr-Schild "
                          "torus in plain FP64 vs FP32 flux + learned guess; recon: the step "
-                         "with MP5, WENO5 and PLM-MC reconstruction")
+                         "with MP5, WENO5 and PLM-MC reconstruction; split: the split "
+                         "(load-balanced) Newton inversion against one pass")
     ap.add_argument("--train-samples", type=int, default=1 << 22)
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--torus", default="384,192,192")
@@ -433,6 +516,8 @@ def main():
         return torus_long_report(args)
     if args.mode == "recon":
         return recon_report(args)
+    if args.mode == "split":
+        return split_report(args)
 
     import torch
     from workloads import box

@@ -204,6 +204,22 @@ int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out);
  * field).  EINVAL on NULL or a short buffer. */
 int grmhd_shell_fluxes(grmhd_grid* h, double* host_out, size_t n_doubles);
 
+/* Split inversion (load balance of the Newton iteration; paper, section on
+ * the OpenMP optimisation: uneven work per zone left threads idle and the
+ * fix was a guided schedule).  On the GPU the cost of a wavefront is its
+ * slowest zone's iteration count, so with iters > 0 every inversion first
+ * runs at most iters Newton iterations per zone; zones not converged by then
+ * are appended to a list with their current iterate, and a second pass of
+ * compact wavefronts finishes each from that iterate (the warm guess is the
+ * fallback if it fails).  The roots, floors and counters are those of the
+ * one-pass inversion; grmhd_diag.newton_iters_sum counts the iterations of
+ * both passes, newton_iters_max is the largest count of either pass.
+ * iters = 0 (the default) turns it off.
+ * EINVAL unless 0 <= iters < newton_maxit, or when iters > 0 with
+ * c2p_guess = GRMHD_GUESS_MLP (whose deferral already forms a second pass).
+ * Enqueued on the grid's stream; no allocation. */
+int grmhd_set_newton_split(grmhd_grid* h, int32_t iters);
+
 /* Learned Newton initial guess (a training-system pattern layered on the
  * method; the paper has no counterpart).  An MLP 8 -> 64 -> 64 -> 64 -> 5
  * (tanh hidden layers, linear output) runs on BF16 matrix cores with FP32

@@ -46,7 +46,7 @@ constexpr int MLP_MAX_WAVES = 256;
 
 const char* const PROF_NAMES[GRMHD_PROF_NCLASS] = {
     "bc_centred", "sweep_x1", "sweep_x2", "sweep_x3", "edge_x1", "edge_x2", "edge_x3",
-    "update", "bc_faces", "cons2prim", "cfl", "reserved", "advance", "rhs_out",
+    "update", "bc_faces", "cons2prim", "cfl", "newton_split", "advance", "rhs_out",
     "learned_guess", "learned_train"};
 }  // namespace
 
@@ -100,6 +100,10 @@ struct grmhd_grid {
   double* ctd() const { return scratch + (long)SCR_CTD * G.field; }
   double* edges() const { return scratch + (long)SCR_EDGE * G.field; }
   int* list() const { return reinterpret_cast<int*>(scratch + (long)SCR_LIST * G.field); }
+  // last iterates of the zones a split inversion deferred: the first flux
+  // field, whose contents are dead while an inversion runs
+  double* list_y() const { return scratch + (long)SCR_FLUX * G.field; }
+  int split_it = 0;   // Newton iterations of the first pass of a split inversion (0: off)
   MlpState mlp;
   bool mlp_alloc = false;
 };
@@ -184,6 +188,7 @@ C2PParams c2p_params(const grmhd_grid_desc& d) {
   // start is better than the network's accuracy
   cp.defer_tol = d.c2p_guess == GRMHD_GUESS_MLP ? 1e-2 : 0.0;
   cp.img = 0;
+  cp.split_it = 0;
   return cp;
 }
 
@@ -334,16 +339,30 @@ static void c2p_with_guess(grmhd_grid* h, const C2PParams& cp, bool with_cfl = f
     h->timed(9, [&] {
       launch_zero_int(h->d_list_n, h->stream);
       launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, cflp, h->list(), h->d_list_n,
-                 h->stream);
+                 nullptr, h->stream);
     });
     h->timed(14, [&] {
       mlp_launch_c2p_list(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->mlp, h->list(), h->d_list_n,
                           h->d_spart + (long)nb * C2P_NSTAT, cflp ? cflp + nb : nullptr, h->stream);
     });
     if (with_cfl) launch_dt_final(cflp, nb + C2P_LIST_BLOCKS, h->desc.cfl, h->d_dt + 2, h->stream);
+  } else if (h->split_it > 0) {
+    C2PParams c1 = cp;
+    c1.split_it = h->split_it;
+    h->timed(9, [&] {
+      launch_zero_int(h->d_list_n, h->stream);
+      launch_c2p(h->G, h->flat, c1, h->prim, h->cons, h->tab, h->d_spart, cflp, h->list(), h->d_list_n,
+                 h->list_y(), h->stream);
+    });
+    h->timed(11, [&] {
+      launch_c2p_split(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->list(), h->d_list_n, h->list_y(),
+                       h->d_spart + (long)nb * C2P_NSTAT, cflp ? cflp + nb : nullptr, h->stream);
+    });
+    if (with_cfl) launch_dt_final(cflp, nb + C2P_LIST_BLOCKS, h->desc.cfl, h->d_dt + 2, h->stream);
   } else {
     h->timed(9, [&] {
-      launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, cflp, nullptr, nullptr, h->stream);
+      launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, cflp, nullptr, nullptr, nullptr,
+                 h->stream);
     });
     if (with_cfl) launch_dt_final(cflp, nb, h->desc.cfl, h->d_dt + 2, h->stream);
   }
@@ -624,6 +643,21 @@ int grmhd_mlp_forward(grmhd_grid* h, const float* feat, int64_t n, float* out) {
   if (!h->mlp.weights_set) return fail(GRMHD_ESTATE, "weights not set");
   mlp_launch_forward(h->mlp, feat, (long)n, out, h->stream);
   return hip_check("mlp_forward");
+}
+
+int grmhd_set_newton_split(grmhd_grid* h, int32_t iters) {
+  if (!h) return fail(GRMHD_EINVAL, "grid handle is NULL");
+  if (iters < 0 || iters >= h->desc.newton_maxit)
+    return fail(GRMHD_EINVAL, "split iterations must be in [0, newton_maxit)");
+  if (iters > 0 && h->desc.c2p_guess == GRMHD_GUESS_MLP)
+    return fail(GRMHD_EINVAL, "the split inversion is not combined with the learned guess");
+  if (iters == h->split_it) return GRMHD_OK;
+  h->split_it = iters;
+  // the second pass's counter slots must read zero whenever it does not run
+  hipError_t e = hipMemsetAsync(h->d_spart + (long)h->nblk * C2P_NSTAT, 0,
+                                (size_t)C2P_LIST_BLOCKS * C2P_NSTAT * sizeof(long long), h->stream);
+  if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  return GRMHD_OK;
 }
 
 int grmhd_set_profiling(grmhd_grid* h, int on) {

@@ -88,11 +88,17 @@ __device__ __forceinline__ void centred_b(const Geom& G, const double* __restric
 // zone's counters to st (fail, iterations, iterations max, floor_rho,
 // floor_p, W cap, learned fallback, learned chosen) and, with want_cfl, sets
 // cfl_v to its sum over d of max|lambda_d| / dx_d.
+// y_start > 0 replaces the warm or cold guess (a zone finished from the
+// iterate at which the first pass deferred it; the warm start is the fallback
+// if that fails).  With cp.split_it > 0 a zone not converged after that many
+// iterations is deferred (true) with its iterate in *y_last and its
+// iterations counted.
 template <class MET>
 __device__ __forceinline__ bool c2p_zone(const Geom& G, const C2PParams& cp, double* __restrict__ prim,
                                          double* __restrict__ cons, const double* __restrict__ tab,
                                          long t, double y_alt, double defer_tol, bool want_cfl,
-                                         long long st[8], double& cfl_v) {
+                                         long long st[8], double& cfl_v, double y_start = -1.0,
+                                         double* y_last = nullptr) {
   int i, j, k;
   zone_of(G, t, i, j, k);
   const long c = G.idx(i, j, k);
@@ -115,9 +121,19 @@ __device__ __forceinline__ bool c2p_zone(const Geom& G, const C2PParams& cp, dou
     const double h = 1.0 + G.gam / (G.gam - 1.0) * p / rho;
     ywarm = rho * h * (1.0 + uu);
   }
-  const double y0 = cp.guess == 1 ? G.gam * (tau + dd) : ywarm;
-  NewtonOut<double> r = newton<double>(dd, S, tau, B, m, G.gam, y0, cp.tol, cp.maxit, y_alt, defer_tol);
-  if (r.deferred) return true;
+  const double y0 = y_start > 0.0 ? y_start : (cp.guess == 1 ? G.gam * (tau + dd) : ywarm);
+  NewtonOut<double> r = newton<double>(dd, S, tau, B, m, G.gam, y0, cp.tol, cp.maxit, y_alt, defer_tol,
+                                       cp.split_it);
+  if (r.deferred) {
+    st[1] += r.iters;
+    if (y_last) *y_last = r.y_last;
+    return true;
+  }
+  if (y_start > 0.0 && !r.ok) {
+    const int it0 = r.iters;
+    r = newton<double>(dd, S, tau, B, m, G.gam, ywarm, cp.tol, cp.maxit);
+    r.iters += it0;
+  }
   if (r.alt) st[7] += 1;
   if (r.alt && !r.ok) {
     const int it0 = r.iters;

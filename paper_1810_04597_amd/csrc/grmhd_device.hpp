@@ -445,7 +445,8 @@ struct NewtonOut {
   int iters;
   bool ok;
   bool alt;       // the iteration started from y_alt
-  bool deferred;  // stopped after the first residual (defer_tol)
+  bool deferred;  // stopped early: first residual (defer_tol) or split_it iterations
+  T y_last;       // the iterate when deferred by split_it
 };
 
 // Safeguarded Newton inversion in y = rho h W^2 (undensitised D, S_i, tau, B^i).
@@ -454,9 +455,13 @@ struct NewtonOut {
 // defer_tol > 0: when the first residual, relative to the magnitude of its
 // terms, exceeds defer_tol (or v^2 >= 1 there), stop at once with
 // deferred = true and nothing else set.
+// split_it > 0: a zone not converged after split_it iterations stops with
+// deferred = true, iters = split_it and its current iterate in y_last (a
+// later pass finishes it from there).
 template <typename T, class MET>
 GR_HD NewtonOut<T> newton(T dd, const T S[3], T tau, const T B[3], const MET& m, T gam,
-                          T y0, double tol, int maxit, T y_alt = T(-1), double defer_tol = 0.0) {
+                          T y0, double tol, int maxit, T y_alt = T(-1), double defer_tol = 0.0,
+                          int split_it = 0) {
   using std::isfinite;
   NewtonOut<T> o;
   const T utot = tau + dd;
@@ -494,6 +499,13 @@ GR_HD NewtonOut<T> newton(T dd, const T S[3], T tau, const T B[3], const MET& m,
   const T EPS4 = T(4.0 * 2.220446049250313e-16);
   if (valid) {
     for (; it < maxit;) {
+      if (split_it > 0 && it == split_it) {
+        o.deferred = true;
+        o.ok = false;
+        o.iters = it;
+        o.y_last = y;
+        return o;
+      }
       ++it;
       const T yy = y * y;
       const T v2 = (s2 + sb2 * (2.0 * y + b2) / yy) / ((y + b2) * (y + b2));

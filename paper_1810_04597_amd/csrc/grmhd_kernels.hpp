@@ -14,6 +14,7 @@ struct C2PParams {
   double rho_fl_a, rho_fl_n, p_fl_a, p_fl_n, w_max;
   double defer_tol;     // learned guess: relative warm residual above which a zone is deferred
   int img;              // all directions periodic, n >= 2 NG: also write the ghost images
+  int split_it;         // > 0: defer zones not converged after this many iterations to a second pass
 };
 
 // Per-block partial results of the inversion (reduced on the device).
@@ -47,9 +48,16 @@ void launch_advance(double* d_dt, const double* src, double dt_host, hipStream_t
 // Inversion of all interior zones; per-block counters into partials[0, nblk),
 // CFL partials (nullable) into cfl_partials[0, nblk).  list != nullptr: defer
 // zones with a poor warm start into list / list_n (learned guess).
+// list / list_n: zones deferred by the learned-guess residual test or by
+// cp.split_it (appended in any order); list_y: their last iterates (split).
 void launch_c2p(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
                 const double* tab, long long* partials, double* cfl_partials, int* list, int* list_n,
-                hipStream_t s);
+                double* list_y, hipStream_t s);
+// Second pass of a split inversion: the listed zones, each from its stored
+// iterate, C2P_LIST_BLOCKS workgroups (partials at their block index).
+void launch_c2p_split(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
+                      const double* tab, const int* list, const int* list_n, const double* list_y,
+                      long long* partials, double* cfl_partials, hipStream_t s);
 void launch_zero_int(int* p, hipStream_t s);
 // Shell fluxes through x^1 = const: out[4 n1] = F_D, F_tau, Phi (|B|/2), Phi
 // signed; part: shell_part_doubles(G) doubles of chunk partials.

@@ -282,16 +282,46 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
                                              const double* __restrict__ tab,
                                              long long* __restrict__ partials,
                                              double* __restrict__ cfl_partials,
-                                             int* __restrict__ list, int* __restrict__ list_n) {
+                                             int* __restrict__ list, int* __restrict__ list_n,
+                                             double* __restrict__ list_y) {
   const long t = flat_thread();
   long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double cfl_v = 0.0;
   if (t < (long)G.n[0] * G.n[1] * G.n[2]) {
     const double defer = list ? cp.defer_tol : 0.0;
-    if (c2p_zone<MET>(G, cp, prim, cons, tab, t, -1.0, defer, cfl_partials != nullptr, st, cfl_v))
-      list[atomicAdd(list_n, 1)] = (int)t;
+    double yl = -1.0;
+    if (c2p_zone<MET>(G, cp, prim, cons, tab, t, -1.0, defer, cfl_partials != nullptr, st, cfl_v, -1.0,
+                      &yl)) {
+      const int pos = atomicAdd(list_n, 1);
+      list[pos] = (int)t;
+      if (list_y) list_y[pos] = yl;
+    }
   }
   c2p_block_partials<true>(st, cfl_v, partials, cfl_partials, blockIdx.x);
+}
+
+// Second pass of the split inversion: the zones the first pass deferred after
+// cp.split_it iterations (cp.split_it is 0 here), grid-stride over the list,
+// each from the iterate it stopped at.  Slow zones, which would hold a whole
+// wavefront in the first pass, run here in compact wavefronts.
+template <class MET>
+__global__ __launch_bounds__(256) void k_c2p_split(Geom G, C2PParams cp, double* __restrict__ prim,
+                                                   double* __restrict__ cons,
+                                                   const double* __restrict__ tab,
+                                                   const int* __restrict__ list,
+                                                   const int* __restrict__ list_n,
+                                                   const double* __restrict__ list_y,
+                                                   long long* __restrict__ partials,
+                                                   double* __restrict__ cfl_partials) {
+  long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double cfl_v = 0.0;
+  const long n = *list_n;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (long)gridDim.x * blockDim.x) {
+    double cv = 0.0;
+    c2p_zone<MET>(G, cp, prim, cons, tab, list[idx], -1.0, 0.0, cfl_partials != nullptr, st, cv, list_y[idx]);
+    cfl_v = fmax(cfl_v, cv);
+  }
+  c2p_block_partials<false>(st, cfl_v, partials, cfl_partials, blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_reduce_stats(const long long* __restrict__ partials, int nb,
@@ -684,14 +714,28 @@ void launch_advance(double* d_dt, const double* src, double dt_host, hipStream_t
 
 void launch_c2p(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
                 const double* tab, long long* partials, double* cfl_partials, int* list, int* list_n,
-                hipStream_t s) {
+                double* list_y, hipStream_t s) {
   const unsigned nb = zone_blocks(G);
   if (flat)
     hipLaunchKernelGGL(k_c2p<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab,
-                       partials, cfl_partials, list, list_n);
+                       partials, cfl_partials, list, list_n, list_y);
   else
     hipLaunchKernelGGL(k_c2p<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, cp, prim, cons, tab,
-                       partials, cfl_partials, list, list_n);
+                       partials, cfl_partials, list, list_n, list_y);
+}
+
+void launch_c2p_split(const Geom& G, bool flat, const C2PParams& cp, double* prim, double* cons,
+                      const double* tab, const int* list, const int* list_n, const double* list_y,
+                      long long* partials, double* cfl_partials, hipStream_t s) {
+  C2PParams c2 = cp;
+  c2.split_it = 0;
+  c2.defer_tol = 0.0;
+  if (flat)
+    hipLaunchKernelGGL(k_c2p_split<FlatMet<double>>, dim3(C2P_LIST_BLOCKS), dim3(256), 0, s, G, c2, prim,
+                       cons, tab, list, list_n, list_y, partials, cfl_partials);
+  else
+    hipLaunchKernelGGL(k_c2p_split<TabMet<double>>, dim3(C2P_LIST_BLOCKS), dim3(256), 0, s, G, c2, prim,
+                       cons, tab, list, list_n, list_y, partials, cfl_partials);
 }
 
 __global__ void k_zero_int(int* __restrict__ p) {

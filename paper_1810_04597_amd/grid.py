@@ -187,6 +187,11 @@ class Grid:
         self.synchronize()
         return out
 
+    def set_newton_split(self, iters):
+        """Split inversion: at most iters Newton iterations in the first pass,
+        the rest of the slow zones in a second, compact pass (0: off)."""
+        L.check(self.lib.grmhd_set_newton_split(self.h, int(iters)))
+
     def set_profiling(self, on=True):
         L.check(self.lib.grmhd_set_profiling(self.h, 1 if on else 0))
 
