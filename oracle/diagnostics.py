@@ -1,4 +1,8 @@
-"""Shell fluxes through x^1 = const surfaces (oracle, FP64).
+"""Torus-run diagnostics (oracle, FP64): shell fluxes through x^1 = const
+surfaces and the MRI resolution.  Test infrastructure: only the tests, the
+smoke check and the benchmark's CPU baseline use it.
+
+Shell fluxes.
 
 A diagnostic of the torus runs (accretion rate, energy flux and magnetic flux
 through spheres; the paper's torus use case, Introduction and Fig. 1), not
@@ -48,3 +52,57 @@ def shell_fluxes(solver):
             "Phi_s": bf.sum(axis=(0, 1)) * area,
             "scale_D": shell(sd), "scale_tau": shell(st_),
             "scale_B": np.abs(bf).sum(axis=(0, 1)) * area}
+
+
+def fluid_frame(st, m):
+    """Four-velocity u^mu = (W / alpha, W (v^i - beta^i / alpha)), the field
+    in the fluid frame b^mu (b^t, b^i as below), b^2 and the angular velocity
+    Omega = u^3 / u^t of a state (physics.state) with 3+1 metric m."""
+    al = m["alpha"]
+    beta = (m["beta1"], m["beta2"], m["beta3"])
+    w_l = st["W"]
+    bt = w_l * st["vB"] / al
+    b = [st["B"][d] / w_l + bt * (al * st["v"][d] - beta[d]) for d in range(3)]
+    return {"ut": w_l / al, "u": [w_l * (st["v"][d] - beta[d] / al) for d in range(3)],
+            "bt": bt, "b": b, "b2": st["B2"] / w_l ** 2 + st["vB"] ** 2,
+            "Omega": al * st["v"][2] - beta[2]}
+
+
+def mri_quality(solver, rho_cut, q_min=8.0):
+    """MRI resolution of the current state (a diagnostic of the torus runs,
+    whose turbulence is driven by the magneto-rotational instability): the
+    number of zones per wavelength of the fastest-growing MRI mode along x^2
+    (theta) and x^3 (phi),
+
+      Q_d = lambda_d / Delta x^(d),   lambda_d = 2 pi |b^(d)| / (|Omega| sqrt(rho h + b^2)),
+
+    with b^mu the field in the fluid frame, b^(d) = sqrt(g_dd) b^d its
+    orthonormal component, Delta x^(d) = sqrt(g_dd) dx^d the proper zone
+    width (the metric factors cancel: Q_d = 2 pi |b^d| / (|Omega| dx^d
+    sqrt(rho h + b^2))), and Omega = u^3 / u^t the angular velocity.  In
+    3+1 form (v the Eulerian velocity, W its Lorentz factor):
+      b^t = W (v_i B^i) / alpha,  b^i = B^i / W + b^t (alpha v^i - beta^i),
+      b^2 = B^2 / W^2 + (v_i B^i)^2,  Omega = alpha v^3 - beta^3.
+    Per x^1 shell i, over the body zones (rho > rho_cut), with the mass weight
+    w = rho sqrt(gamma): sum w Q_2, sum w Q_3, sum w, the number of body zones
+    and the numbers with Q_2 >= q_min and Q_3 >= q_min.  Returns the per-zone
+    Q_2, Q_3 and those six shell arrays."""
+    g = solver.grid
+    m = solver.centre_metric()
+    P = {k: solver.interior(v) for k, v in solver.P.items()}
+    st = physics.state(P["rho"], (P["u1"], P["u2"], P["u3"]), P["p"],
+                       (P["B1"], P["B2"], P["B3"]), m, g.gamma_ad)
+    ff = fluid_frame(st, m)
+    bcon, b2, omega = ff["b"], ff["b2"], ff["Omega"]
+    den = np.abs(omega) * np.sqrt(P["rho"] * st["h"] + b2)
+    q2 = 2.0 * np.pi * np.abs(bcon[1]) / (den * g.dx[1])
+    q3 = 2.0 * np.pi * np.abs(bcon[2]) / (den * g.dx[2])
+    body = P["rho"] > rho_cut
+    wt = np.broadcast_to(P["rho"] * m["sqrtg"], q2.shape)
+    z = np.zeros_like(q2)
+    shell = lambda a: np.where(body, a, z).sum(axis=(0, 1))
+    return {"Q2": q2, "Q3": q3,
+            "wQ2": shell(wt * q2), "wQ3": shell(wt * q3), "w": shell(wt),
+            "n_body": body.sum(axis=(0, 1)).astype(np.float64),
+            "n_Q2_ok": (body & (q2 >= q_min)).sum(axis=(0, 1)).astype(np.float64),
+            "n_Q3_ok": (body & (q3 >= q_min)).sum(axis=(0, 1)).astype(np.float64)}
