@@ -326,8 +326,10 @@ def torus_report(args):
 
 def torus_long_report(args):
     """Long Kerr-Schild torus run (device CFL step): every --every steps the
-    diagnostics and the fluxes through the first sphere outside the horizon
-    (accretion rate -F_D, magnetic flux); wall time per step over the run."""
+    diagnostics, the fluxes through the first sphere outside the horizon
+    (accretion rate -F_D, magnetic flux) and the MRI resolution of the torus
+    body (rho > --mri-rho-cut: mass-weighted mean Q along theta and phi, the
+    fraction of body zones with Q >= 8); wall time per step over the run."""
     import math
     import numpy as np
     import torch
@@ -347,8 +349,12 @@ def torus_long_report(args):
         if s % args.every == 0 or s == args.steps:
             dg = G.diagnostics()
             sh = G.shell_fluxes()
+            mq = G.mri_quality(args.mri_rho_cut)
             rec = {"step": s, "t": dg["t"], "dt": dg["dt"], "mdot_horizon": float(-sh["F_D"][ih]),
                    "phi_horizon": float(sh["Phi"][ih]), "max_divb": dg["max_divb"],
+                   "max_divb_norm": dg["max_divb_norm"],
+                   "mri_Q2": mq["Q2_mean"], "mri_Q3": mq["Q3_mean"],
+                   "mri_frac_Q2_ok": mq["frac_Q2_ok"], "mri_frac_Q3_ok": mq["frac_Q3_ok"],
                    "sum_D": dg["sum_cons"][0], "w_max": dg["w_max"], "n_c2p_fail": dg["n_c2p_fail"],
                    "n_nonfinite": dg["n_nonfinite"], "newton_iters_max": dg["newton_iters_max"]}
             series.append(rec)
@@ -500,6 +506,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--torus", default="384,192,192")
     ap.add_argument("--every", type=int, default=250, help="torus-long: steps between diagnostics")
+    ap.add_argument("--mri-rho-cut", type=float, default=1e-2,
+                    help="torus-long: density above which a zone counts as torus body")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (a single grid block per device); "

@@ -204,6 +204,23 @@ int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out);
  * field).  EINVAL on NULL or a short buffer. */
 int grmhd_shell_fluxes(grmhd_grid* h, double* host_out, size_t n_doubles);
 
+/* MRI resolution of the stored state (a diagnostic of the torus runs, whose
+ * turbulence the magneto-rotational instability drives; paper, Introduction
+ * and Fig. 1): per zone, the number of zones per wavelength of the
+ * fastest-growing MRI mode along x^2 and x^3,
+ *   Q_d = 2 pi |b^d| / (|Omega| dx^d sqrt(rho h + b^2)),
+ * with the field in the fluid frame b^t = W (v.B) / alpha,
+ * b^i = B^i / W + b^t (alpha v^i - beta^i), b^2 = B^2 / W^2 + (v.B)^2 and the
+ * angular velocity Omega = u^3 / u^t = alpha v^3 - beta^3.  Over the body
+ * zones (rho > rho_cut >= 0), with the weight w = rho sqrt(gamma), host_out
+ * (host, n_doubles >= 6 n1) receives per x^1 shell i:
+ *   [0, n1) sum w Q_2, [n1, 2n1) sum w Q_3, [2n1, 3n1) sum w,
+ *   [3n1, 4n1) body zones, [4n1, 5n1) zones with Q_2 >= q_min,
+ *   [5n1, 6n1) zones with Q_3 >= q_min.
+ * Sums in a fixed order (deterministic).  EINVAL on NULL, a short buffer or
+ * a negative rho_cut. */
+int grmhd_mri_quality(grmhd_grid* h, double rho_cut, double q_min, double* host_out, size_t n_doubles);
+
 /* Split inversion (load balance of the Newton iteration; paper, section on
  * the OpenMP optimisation: uneven work per zone left threads idle and the
  * fix was a guided schedule).  On the GPU the cost of a wavefront is its

@@ -95,8 +95,10 @@ def mri_quality(solver, rho_cut, q_min=8.0):
     ff = fluid_frame(st, m)
     bcon, b2, omega = ff["b"], ff["b2"], ff["Omega"]
     den = np.abs(omega) * np.sqrt(P["rho"] * st["h"] + b2)
-    q2 = 2.0 * np.pi * np.abs(bcon[1]) / (den * g.dx[1])
-    q3 = 2.0 * np.pi * np.abs(bcon[2]) / (den * g.dx[2])
+    # gas at rest without field (Omega = b = 0, outside any body) gives 0/0
+    with np.errstate(invalid="ignore", divide="ignore"):
+        q2 = 2.0 * np.pi * np.abs(bcon[1]) / (den * g.dx[1])
+        q3 = 2.0 * np.pi * np.abs(bcon[2]) / (den * g.dx[2])
     body = P["rho"] > rho_cut
     wt = np.broadcast_to(P["rho"] * m["sqrtg"], q2.shape)
     z = np.zeros_like(q2)

@@ -224,7 +224,9 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** 
   // blocks), shell fluxes (chunk partials, then the 4 n1 results)
   const size_t part = std::max(std::max((size_t)h->nblk * (DIAG_NSUM + DIAG_NMAX),
                                         (size_t)h->nblk + C2P_LIST_BLOCKS),
-                               (size_t)(shell_part_doubles(h->G) + 4L * desc->n[0])) * sizeof(double);
+                               (size_t)std::max(shell_part_doubles(h->G) + 4L * desc->n[0],
+                                                mri_part_doubles(h->G) + 6L * desc->n[0])) *
+                      sizeof(double);
   const size_t spart = ((size_t)h->nblk + C2P_LIST_BLOCKS) * C2P_NSTAT * sizeof(long long);
   hipError_t e = hipSuccess;
   e = hipMalloc(&h->d_dt, 3 * sizeof(double));
@@ -479,6 +481,21 @@ int grmhd_shell_fluxes(grmhd_grid* h, double* host_out, size_t n_doubles) {
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
   return hip_check("shell_fluxes");
+}
+
+int grmhd_mri_quality(grmhd_grid* h, double rho_cut, double q_min, double* host_out, size_t n_doubles) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!host_out) return fail(GRMHD_EINVAL, "host_out is NULL");
+  if (n_doubles < (size_t)6 * h->G.n[0]) return fail(GRMHD_EINVAL, "host_out needs 6 n1 doubles");
+  if (!(rho_cut >= 0.0)) return fail(GRMHD_EINVAL, "rho_cut must be >= 0");
+  double* res = h->d_part + mri_part_doubles(h->G);
+  launch_mri(h->G, h->flat, h->prim, h->tab, rho_cut, q_min, h->d_part, res, h->stream);
+  hipError_t e = hipMemcpyAsync(host_out, res, (size_t)6 * h->G.n[0] * sizeof(double),
+                                hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  return hip_check("mri_quality");
 }
 
 int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out) {

@@ -64,6 +64,11 @@ void launch_zero_int(int* p, hipStream_t s);
 void launch_shell(const Geom& G, bool flat, const double* prim, const double* cons, const double* tab,
                   double* part, double* out, hipStream_t s);
 long shell_part_doubles(const Geom& G);
+// MRI resolution sums per x^1 shell (6 n1 doubles into out; part holds
+// mri_part_doubles(G) chunk partials).
+void launch_mri(const Geom& G, bool flat, const double* prim, const double* tab, double rho_cut,
+                double q_min, double* part, double* out, hipStream_t s);
+long mri_part_doubles(const Geom& G);
 void launch_dt_final(const double* cfl_partials, int nb, double cfl, double* d_dt, hipStream_t s);
 void launch_prim2cons(const Geom& G, bool flat, double* prim, double* cons, const double* tab,
                       hipStream_t s);

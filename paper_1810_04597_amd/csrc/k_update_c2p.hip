@@ -850,6 +850,90 @@ void launch_shell(const Geom& G, bool flat, const double* prim, const double* co
 
 long shell_part_doubles(const Geom& G) { return 4L * G.n[0] * SHELL_CHUNKS; }
 
+// ------------------------------------------------------------------ MRI resolution
+// Per zone of the stored state: the field in the fluid frame (b^t = W v.B /
+// alpha, b^i = B^i / W + b^t (alpha v^i - beta^i), b^2 = B^2 / W^2 + (v.B)^2),
+// the angular velocity Omega = alpha v^3 - beta^3 (u^3 / u^t), and the
+// number of zones per fastest-growing MRI wavelength along x^2 and x^3,
+// Q_d = 2 pi |b^d| / (|Omega| dx^d sqrt(rho h + b^2)).  Over the body zones
+// (rho > rho_cut), with the weight w = rho sqrt(gamma), workgroup (i, chunk)
+// sums w Q_2, w Q_3, w, the zone count and the counts with Q_2, Q_3 >= q_min
+// over a fixed chunk of shell i; k_mri_final adds the chunks in order.
+// out: those six sums per shell, each an n1 array.
+constexpr int MRI_NSUM = 6;
+
+template <class MET>
+__global__ __launch_bounds__(256) void k_mri(Geom G, const double* __restrict__ prim,
+                                             const double* __restrict__ tab, double rho_cut,
+                                             double q_min, double* __restrict__ part) {
+  const int i = blockIdx.x, ch = blockIdx.y;
+  const long m2 = (long)G.n[1] * G.n[2];
+  const long q0 = m2 * ch / SHELL_CHUNKS, q1 = m2 * (ch + 1) / SHELL_CHUNKS;
+  double acc[MRI_NSUM] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  MET m;
+  for (long q = q0 + threadIdx.x; q < q1; q += 256) {
+    const int j = (int)(q % G.n[1]), k = (int)(q / G.n[1]);
+    const long c = G.idx(i, j, k);
+    if constexpr (!MET::flat) m.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
+    PState<double> st;
+    st.rho = prim[P_RHO * G.field + c];
+    st.p = prim[P_P * G.field + c];
+    for (int a = 0; a < 3; ++a) {
+      st.u[a] = prim[(P_U1 + a) * G.field + c];
+      st.B[a] = prim[(P_B1 + a) * G.field + c];
+    }
+    if (!(st.rho > rho_cut)) continue;
+    make_state(st, m, G.gam);
+    const double bt = st.W * st.vB / m.alpha();
+    const double b2c = st.B[1] / st.W + bt * m.tvel(st.v[1], 1);
+    const double b3c = st.B[2] / st.W + bt * m.tvel(st.v[2], 2);
+    const double bsq = st.B2 / (st.W * st.W) + st.vB * st.vB;
+    const double den = fabs(m.tvel(st.v[2], 2)) * sqrt(st.rho * st.h + bsq);
+    const double qq2 = 2.0 * M_PI * fabs(b2c) / (den * G.dx[1]);
+    const double qq3 = 2.0 * M_PI * fabs(b3c) / (den * G.dx[2]);
+    const double w = st.rho * m.sqrtg();
+    acc[0] += w * qq2;
+    acc[1] += w * qq3;
+    acc[2] += w;
+    acc[3] += 1.0;
+    acc[4] += qq2 >= q_min ? 1.0 : 0.0;
+    acc[5] += qq3 >= q_min ? 1.0 : 0.0;
+  }
+  __shared__ double sh[4][MRI_NSUM];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int a = 0; a < MRI_NSUM; ++a) {
+    const double v = wave_sum(acc[a]);
+    if (lane == 0) sh[wv][a] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < MRI_NSUM) {
+    const int a = threadIdx.x;
+    part[((long)a * G.n[0] + i) * SHELL_CHUNKS + ch] = (sh[0][a] + sh[1][a]) + (sh[2][a] + sh[3][a]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mri_final(Geom G, const double* __restrict__ part,
+                                                   double* __restrict__ out) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)MRI_NSUM * G.n[0]) return;
+  double v = 0.0;
+  for (int ch = 0; ch < SHELL_CHUNKS; ++ch) v += part[e * SHELL_CHUNKS + ch];
+  out[e] = v;
+}
+
+void launch_mri(const Geom& G, bool flat, const double* prim, const double* tab, double rho_cut,
+                double q_min, double* part, double* out, hipStream_t s) {
+  const dim3 grid(G.n[0], SHELL_CHUNKS);
+  if (flat)
+    hipLaunchKernelGGL(k_mri<FlatMet<double>>, grid, dim3(256), 0, s, G, prim, tab, rho_cut, q_min, part);
+  else
+    hipLaunchKernelGGL(k_mri<TabMet<double>>, grid, dim3(256), 0, s, G, prim, tab, rho_cut, q_min, part);
+  hipLaunchKernelGGL(k_mri_final, dim3((unsigned)(((long)MRI_NSUM * G.n[0] + 255) / 256)), dim3(256), 0, s,
+                     G, part, out);
+}
+
+long mri_part_doubles(const Geom& G) { return (long)MRI_NSUM * G.n[0] * SHELL_CHUNKS; }
+
 void launch_diag(const Geom& G, bool flat, const double* prim, const double* cons,
                  const double* tab, double* partials, double* out, hipStream_t s) {
   const unsigned nb = zone_blocks(G);

@@ -122,6 +122,23 @@ class Grid:
         a = np.frombuffer(buf, dtype=np.float64).copy()
         return {"F_D": a[0:n1], "F_tau": a[n1:2 * n1], "Phi": a[2 * n1:3 * n1], "Phi_s": a[3 * n1:]}
 
+    def mri_quality(self, rho_cut, q_min=8.0):
+        """MRI resolution sums per x^1 shell over the zones with rho > rho_cut
+        (numpy, n1 each): wQ2, wQ3, w (w = rho sqrt(gamma)), n_body, n_Q2_ok,
+        n_Q3_ok; plus the body's weighted means Q2_mean, Q3_mean and the
+        fractions of body zones with Q >= q_min."""
+        n1 = self.spec.n[0]
+        buf = (C.c_double * (6 * n1))()
+        L.check(self.lib.grmhd_mri_quality(self.h, float(rho_cut), float(q_min), buf, C.c_size_t(6 * n1)))
+        a = np.frombuffer(buf, dtype=np.float64).copy().reshape(6, n1)
+        out = dict(zip(("wQ2", "wQ3", "w", "n_body", "n_Q2_ok", "n_Q3_ok"), a))
+        w, nb = a[2].sum(), a[3].sum()
+        out.update(Q2_mean=a[0].sum() / w if w > 0 else float("nan"),
+                   Q3_mean=a[1].sum() / w if w > 0 else float("nan"),
+                   frac_Q2_ok=a[4].sum() / nb if nb > 0 else float("nan"),
+                   frac_Q3_ok=a[5].sum() / nb if nb > 0 else float("nan"))
+        return out
+
     # ------------------------------------------------------------ learned guess
     def mlp_set_weights(self, flat, norm):
         flat = np.ascontiguousarray(flat, dtype=np.float32)

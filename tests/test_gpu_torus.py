@@ -152,3 +152,48 @@ def test_shell_fluxes_full_size_torus():
     g, d, tab, s, G = _pair_torus(256, 128, 128)
     _shell_close(G.shell_fluxes(), shell_fluxes(s))
     G.close()
+
+
+def _mri_close(gm, om, q_min):
+    """Shell sums within 1e-12 of their size; threshold counts equal except
+    for zones whose Q lies within rounding of q_min."""
+    for a in ("wQ2", "wQ3", "w"):
+        err = np.abs(gm[a] - om[a]) / np.maximum(np.abs(om[a]), 1e-300)
+        assert err.max() < 1e-12, (a, err.max())
+    assert np.array_equal(gm["n_body"], om["n_body"])
+    for a, q in (("n_Q2_ok", "Q2"), ("n_Q3_ok", "Q3")):
+        near = (np.abs(om[q] - q_min) <= 1e-10 * q_min).sum(axis=(0, 1))
+        assert np.all(np.abs(gm[a] - om[a]) <= near), a
+
+
+@gpu
+@pytest.mark.parametrize("steps", [0, 1])
+def test_mri_quality_matches_oracle(steps):
+    """MRI resolution sums of the 48x24x24 torus (body rho > 1e-2), at the
+    initial state and after one RK3 step."""
+    _torch()
+    from oracle.diagnostics import mri_quality
+    g, d, tab, s, G = _pair_torus(48, 24, 24)
+    if steps:
+        dt = s.cfl_dt()
+        s.rk_step(dt)
+        G.rk_step(dt)
+    om = mri_quality(s, 1e-2, 8.0)
+    gm = G.mri_quality(1e-2, 8.0)
+    _mri_close(gm, om, 8.0)
+    assert gm["n_body"].sum() > 0 and gm["wQ3"].sum() > 0
+
+
+@gpu
+def test_mri_quality_full_size_torus():
+    """The 256 x 128 x 128 torus (the benchmark's size): shell sums against
+    the oracle on the whole initial grid."""
+    _torch()
+    from oracle.diagnostics import mri_quality
+    g, d, tab, s, G = _pair_torus(256, 128, 128)
+    om = mri_quality(s, 1e-2, 8.0)
+    gm = G.mri_quality(1e-2, 8.0)
+    _mri_close(gm, om, 8.0)
+    print("torus 256x128x128 MRI: <Q2> %.2f <Q3> %.2f, Q2 >= 8 in %.3f, Q3 >= 8 in %.3f of %d body zones"
+          % (gm["Q2_mean"], gm["Q3_mean"], gm["frac_Q2_ok"], gm["frac_Q3_ok"], int(gm["n_body"].sum())))
+    G.close()
