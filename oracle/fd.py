@@ -13,6 +13,14 @@ I_d interpolates face values to the cell centre to sixth order.
 
 With the face m+1/2 stored at index m, the stencil of cell m reads stored
 indices m-3 .. m+2.
+
+A fourth-order member of the same family (order=4) keeps only the first
+correction, f_hat = f - Delta^2 f / 24:
+
+  (D4 f)_m = [27/24 (f_{m+1/2} - f_{m-1/2}) - 1/24 (f_{m+3/2} - f_{m-3/2})] / Delta
+  (I4 f)_m = [9 (f_{m+1/2} + f_{m-1/2}) - (f_{m+3/2} + f_{m-3/2})] / 16
+
+(stored indices m-2 .. m+1).
 """
 import numpy as np
 
@@ -28,16 +36,22 @@ def take(a, d, lo, hi, g):
     return a[tuple(sl)]
 
 
-def deriv(f, d, lo, hi, dx, g):
+def deriv(f, d, lo, hi, dx, g, order=6):
     """D_d f at positions m in [lo, hi) (cells, or edges/faces offset in d)."""
     t = lambda s: take(f, d, lo + s, hi + s, g)
+    if order == 4:
+        return (27.0 / 24.0 * (t(0) - t(-1)) - 1.0 / 24.0 * (t(1) - t(-2))) / dx
+    assert order == 6
     return (75.0 / 64.0 * (t(0) - t(-1)) - 25.0 / 384.0 * (t(1) - t(-2))
             + 3.0 / 640.0 * (t(2) - t(-3))) / dx
 
 
-def interp(f, d, lo, hi, g):
+def interp(f, d, lo, hi, g, order=6):
     """I_d f at cell positions m in [lo, hi) from faces in direction d."""
     t = lambda s: take(f, d, lo + s, hi + s, g)
+    if order == 4:
+        return (9.0 * (t(0) + t(-1)) - (t(1) + t(-2))) / 16.0
+    assert order == 6
     return (150.0 * (t(0) + t(-1)) - 25.0 * (t(1) + t(-2))
             + 3.0 * (t(2) + t(-3))) / 256.0
 

@@ -107,12 +107,19 @@ class Solver:
     reconstruction, face physics, HLL flux and edge field are evaluated in
     float32 from float32-rounded inputs and widened to float64 afterwards
     (derivatives, sources, RK combine and inversion stay float64).
-    recon: interface reconstruction, "mp5" (default), "weno5" or "plm"."""
+    recon: interface reconstruction, "mp5" (default), "weno5" or "plm".
+    deriv_order: order of the staggered derivative and interpolation, 6
+    (default) or 4; one order serves the flux derivative, the induction
+    equation, the curl of the vector potential, the centred field and div B,
+    so the discrete div B stays zero."""
 
-    def __init__(self, grid, tables=None, precision="fp64", recon="mp5"):
+    def __init__(self, grid, tables=None, precision="fp64", recon="mp5", deriv_order=6):
         if recon not in RECON_METHODS:
             raise ValueError("unknown reconstruction %r" % (recon,))
+        if deriv_order not in (4, 6):
+            raise ValueError("deriv_order must be 4 or 6")
         self.recon = recon
+        self.order = deriv_order
         self.grid = grid
         self.ftype = np.float32 if precision == "fp32" else np.float64
         self.g = grid.ng
@@ -147,8 +154,8 @@ class Solver:
         g, gr = self.g, self.grid
         for nd in range(3):
             d1, d2 = (nd + 1) % 3, (nd + 2) % 3
-            t1 = deriv(A["A%d" % (d2 + 1)], d1, 0, gr.n[d1], gr.dx[d1], g)
-            t2 = deriv(A["A%d" % (d1 + 1)], d2, 0, gr.n[d2], gr.dx[d2], g)
+            t1 = deriv(A["A%d" % (d2 + 1)], d1, 0, gr.n[d1], gr.dx[d1], g, self.order)
+            t2 = deriv(A["A%d" % (d1 + 1)], d2, 0, gr.n[d2], gr.dx[d2], g, self.order)
             t1 = _restrict_others(t1, d1, g, gr)
             t2 = _restrict_others(t2, d2, g, gr)
             f = _nan(gr.shape)
@@ -167,7 +174,7 @@ class Solver:
         sg = self.centre_metric()["sqrtg"]
         out = []
         for d in range(3):
-            bi = interp(self.U["Bf%d" % (d + 1)], d, 0, gr.n[d], g)
+            bi = interp(self.U["Bf%d" % (d + 1)], d, 0, gr.n[d], g, self.order)
             bi = _restrict_others(bi, d, g, gr)
             out.append(bi / sg)
         return out
@@ -314,7 +321,7 @@ class Solver:
         for name in HYDRO:
             tot = 0.0
             for d in range(3):
-                t = deriv(fdat[d]["F_" + name], d, 0, gr.n[d], gr.dx[d], g)
+                t = deriv(fdat[d]["F_" + name], d, 0, gr.n[d], gr.dx[d], g, self.order)
                 tot = tot - _restrict_others(t, d, g, gr)
             lh[name] = tot
         src = sources({k: self.interior(v) for k, v in self.P.items()},
@@ -324,8 +331,8 @@ class Solver:
         lf = {}
         for nd in range(3):
             d1, d2 = (nd + 1) % 3, (nd + 2) % 3
-            t1 = _restrict_others(deriv(edges[d2], d1, 0, gr.n[d1], gr.dx[d1], g), d1, g, gr)
-            t2 = _restrict_others(deriv(edges[d1], d2, 0, gr.n[d2], gr.dx[d2], g), d2, g, gr)
+            t1 = _restrict_others(deriv(edges[d2], d1, 0, gr.n[d1], gr.dx[d1], g, self.order), d1, g, gr)
+            t2 = _restrict_others(deriv(edges[d1], d2, 0, gr.n[d2], gr.dx[d2], g, self.order), d2, g, gr)
             lf["Bf%d" % (nd + 1)] = -t1 + t2
         return lh, lf, fdat, edges
 
@@ -441,7 +448,7 @@ class Solver:
         g, gr = self.g, self.grid
         tot = 0.0
         for d in range(3):
-            t = deriv(self.U["Bf%d" % (d + 1)], d, 0, gr.n[d], gr.dx[d], g)
+            t = deriv(self.U["Bf%d" % (d + 1)], d, 0, gr.n[d], gr.dx[d], g, self.order)
             tot = tot + _restrict_others(t, d, g, gr)
         return tot
 

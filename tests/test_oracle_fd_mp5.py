@@ -146,3 +146,58 @@ def test_mp5_mirror_states_on_symmetric_data():
     left = mp5.mp5(q[0], q[1], q[2], q[3], q[4])
     right = mp5.mp5(q[5], q[4], q[3], q[2], q[1])
     assert left == right
+
+
+# ---------------------------------------------------------------- fourth-order D and I
+@pytest.mark.parametrize("deg", [0, 1, 2, 3, 4])
+def test_deriv4_exact_on_polynomials(deg):
+    rng = np.random.default_rng(60 + deg)
+    coef = rng.normal(size=deg + 1)
+    n, dx = 12, 0.1
+    f, _ = _poly_faces(coef, n, dx)
+    d = fd.deriv(f[None, None, :], 0, 0, n, dx, G, order=4)[0, 0]
+    exact = np.polyval(np.polyder(coef), (np.arange(n) + 0.5) * dx)
+    assert np.max(np.abs(d - exact)) <= 1e-11 * max(1.0, np.abs(exact).max())
+
+
+def test_deriv4_not_exact_degree5_and_differs_from_deriv6():
+    coef = np.zeros(6); coef[0] = 1.0
+    n, dx = 12, 0.1
+    f, _ = _poly_faces(coef, n, dx)
+    d4 = fd.deriv(f[None, None, :], 0, 0, n, dx, G, order=4)[0, 0]
+    d6 = fd.deriv(f[None, None, :], 0, 0, n, dx, G)[0, 0]
+    xc = (np.arange(n) + 0.5) * dx
+    assert np.max(np.abs(d4 - 5 * xc ** 4)) > 1e-6
+    assert np.max(np.abs(d6 - 5 * xc ** 4)) < 1e-11
+
+
+@pytest.mark.parametrize("deg", [0, 1, 2, 3])
+def test_interp4_exact_on_polynomials(deg):
+    rng = np.random.default_rng(70 + deg)
+    coef = rng.normal(size=deg + 1)
+    n, dx = 12, 0.1
+    f, _ = _poly_faces(coef, n, dx)
+    v = fd.interp(f[None, None, :], 0, 0, n, G, order=4)[0, 0]
+    exact = np.polyval(coef, (np.arange(n) + 0.5) * dx)
+    assert np.max(np.abs(v - exact)) <= 1e-12 * max(1.0, np.abs(exact).max())
+
+
+def test_interp4_not_exact_degree4():
+    n, dx = 12, 0.1
+    f, _ = _poly_faces([1.0, 0, 0, 0, 0], n, dx)
+    v = fd.interp(f[None, None, :], 0, 0, n, G, order=4)[0, 0]
+    assert np.max(np.abs(v - ((np.arange(n) + 0.5) * dx) ** 4)) > 1e-7
+
+
+def test_deriv4_telescopes_and_converges_at_fourth_order():
+    rng = np.random.default_rng(12)
+    a = np.pad(rng.normal(size=16), G, mode="wrap")[None, None, :]
+    assert abs(fd.deriv(a, 0, 0, 16, 1.0, G, order=4).sum()) < 1e-13
+    errs = []
+    for n in (16, 32, 64):
+        dx = 1.0 / n
+        xf = (np.arange(-G, n + G) + 1.0) * dx
+        d = fd.deriv(np.sin(2 * np.pi * xf)[None, None, :], 0, 0, n, dx, G, order=4)[0, 0]
+        errs.append(np.max(np.abs(d - 2 * np.pi * np.cos(2 * np.pi * (np.arange(n) + 0.5) * dx))))
+    orders = [np.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) > 3.9 and max(orders) < 4.1, orders
