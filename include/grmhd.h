@@ -97,6 +97,12 @@ typedef struct {
   double p_fl_a, p_fl_n;      /* p floor a r^n (a = 0: off)                       */
   double w_max;            /* Lorentz-factor cap (0: off, else > 1)              */
   double newton_tol;       /* relative step tolerance, e.g. 1e-14                */
+  int32_t deriv_order;     /* staggered derivative / interpolation order: 0 or 6
+                              (sixth, the default) or 4 (fourth, the first
+                              correction only); one order serves the flux
+                              derivative, the induction equation, the curl of
+                              the vector potential, the centred field and div B */
+  int32_t reserved;        /* must be 0                                           */
 } grmhd_grid_desc;
 
 typedef struct {

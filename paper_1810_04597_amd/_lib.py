@@ -34,7 +34,7 @@ class GridDesc(C.Structure):
                 ("x0", C.c_double * 3), ("dx", C.c_double * 3), ("gamma_ad", C.c_double),
                 ("cfl", C.c_double), ("rho_fl_a", C.c_double), ("rho_fl_n", C.c_double),
                 ("p_fl_a", C.c_double), ("p_fl_n", C.c_double), ("w_max", C.c_double),
-                ("newton_tol", C.c_double)]
+                ("newton_tol", C.c_double), ("deriv_order", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Layout(C.Structure):
@@ -129,7 +129,7 @@ def check(rc):
     return rc
 
 
-def make_desc(grid, precision=FP64, guess=GUESS_WARM, recon=RECON_MP5):
+def make_desc(grid, precision=FP64, guess=GUESS_WARM, recon=RECON_MP5, deriv_order=6):
     """GridDesc from a workloads.GridSpec-like object."""
     d = GridDesc()
     for a in range(3):
@@ -150,6 +150,8 @@ def make_desc(grid, precision=FP64, guess=GUESS_WARM, recon=RECON_MP5):
     d.p_fl_a, d.p_fl_n = grid.p_fl_a, grid.p_fl_n
     d.w_max = grid.w_max
     d.newton_tol = grid.newton_tol
+    d.deriv_order = deriv_order
+    d.reserved = 0
     return d
 
 

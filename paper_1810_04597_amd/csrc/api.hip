@@ -3,6 +3,7 @@
 // strings.  All numerical work happens in the kernels.
 #include <hip/hip_runtime.h>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
@@ -12,6 +13,11 @@
 #include "grmhd.h"
 #include "grmhd_kernels.hpp"
 
+// the descriptor's layout, which the Python binding mirrors field by field
+static_assert(sizeof(grmhd_grid_desc) == 184 && offsetof(grmhd_grid_desc, recon) == 56 &&
+                  offsetof(grmhd_grid_desc, newton_tol) == 168 &&
+                  offsetof(grmhd_grid_desc, deriv_order) == 176,
+              "grmhd_grid_desc layout");
 static_assert(GRMHD_RECON_MP5 == grmhd::RECON_MP5 && GRMHD_RECON_WENO5 == grmhd::RECON_WENO5 &&
                   GRMHD_RECON_PLM == grmhd::RECON_PLM,
               "reconstruction codes of the ABI and the kernels agree");
@@ -144,6 +150,9 @@ int validate(const grmhd_grid_desc* d) {
   if (d->w_max != 0.0 && !(d->w_max > 1.0)) return fail(GRMHD_EINVAL, "w_max must be 0 or > 1");
   if (d->recon != GRMHD_RECON_MP5 && d->recon != GRMHD_RECON_WENO5 && d->recon != GRMHD_RECON_PLM)
     return fail(GRMHD_EINVAL, "bad recon");
+  if (d->deriv_order != 0 && d->deriv_order != 4 && d->deriv_order != 6)
+    return fail(GRMHD_EINVAL, "deriv_order must be 0, 4 or 6");
+  if (d->reserved != 0) return fail(GRMHD_EINVAL, "reserved must be 0");
   return GRMHD_OK;
 }
 
@@ -168,6 +177,7 @@ void make_layout(const grmhd_grid_desc& d, grmhd_layout& L, Geom& G) {
   G.field = L.field;
   G.off = L.offset;
   G.gam = d.gamma_ad;
+  G.dorder = d.deriv_order == 4 ? 4 : 6;
   G.tab_n1 = (int)L.dims[0];
   G.tab_plane = L.dims[0] * L.dims[1];
 }

@@ -76,7 +76,7 @@ __device__ __forceinline__ void centred_b(const Geom& G, const double* __restric
     const long st = G.stride(d);
 #pragma unroll
     for (int s = 0; s < 6; ++s) f[s] = fp[(s - 3) * st];
-    B[d] = m.undens(fd_interp(f));
+    B[d] = m.undens(fd_interp_rt(f, G.dorder));
   }
 }
 

@@ -53,6 +53,7 @@ struct Geom {
   long off;            // offset of interior (0,0,0)
   double dx[3], x0[3];
   double gam;          // ideal-gas index
+  int dorder;          // order of the staggered derivative and interpolation (6 or 4)
   int tab_n1;          // metric table row length (n1 + 2 NG)
   long tab_plane;      // metric table component stride
   __host__ __device__ long idx(int i, int j, int k) const {
@@ -200,6 +201,30 @@ GR_HD double fd_deriv(const double f[6], double inv_dx) {
 }
 GR_HD double fd_interp(const double f[6]) {
   return (150.0 * (f[3] + f[2]) - 25.0 * (f[4] + f[1]) + 3.0 * (f[5] + f[0])) * (1.0 / 256.0);
+}
+// Order DO = 6 (above) or 4: the fourth-order members keep only the first
+// correction, D4 = [27/24 (f_{+1/2} - f_{-1/2}) - 1/24 (f_{+3/2} - f_{-3/2})] / dx
+// and I4 = [9 (f_{+1/2} + f_{-1/2}) - (f_{+3/2} + f_{-3/2})] / 16 (f[1..4]).
+template <int DO>
+GR_HD double fd_deriv_o(const double f[6], double inv_dx) {
+  if constexpr (DO == 4)
+    return (27.0 / 24.0 * (f[3] - f[2]) - 1.0 / 24.0 * (f[4] - f[1])) * inv_dx;
+  else
+    return fd_deriv(f, inv_dx);
+}
+template <int DO>
+GR_HD double fd_interp_o(const double f[6]) {
+  if constexpr (DO == 4)
+    return (9.0 * (f[3] + f[2]) - (f[4] + f[1])) * (1.0 / 16.0);
+  else
+    return fd_interp(f);
+}
+// Run-time order (the grid's), for kernels outside the time step's hot path.
+GR_HD double fd_deriv_rt(const double f[6], double inv_dx, int order) {
+  return order == 4 ? fd_deriv_o<4>(f, inv_dx) : fd_deriv(f, inv_dx);
+}
+GR_HD double fd_interp_rt(const double f[6], int order) {
+  return order == 4 ? fd_interp_o<4>(f) : fd_interp(f);
 }
 
 // ------------------------------------------------------------------ metric policies
@@ -507,19 +532,21 @@ GR_HD NewtonOut<T> newton(T dd, const T S[3], T tau, const T B[3], const MET& m,
         return o;
       }
       ++it;
-      const T yy = y * y;
-      const T v2 = (s2 + sb2 * (2.0 * y + b2) / yy) / ((y + b2) * (y + b2));
+      // three reciprocals per iteration (1/y, 1/(y + B^2), 1/sqrt(1 - v^2));
+      // the expressions are those of the residual and its derivative
+      const T iy = 1.0 / y, iy2 = iy * iy;
+      const T yb = y + b2, iyb = 1.0 / yb, iyb2 = iyb * iyb;
+      const T num = s2 + sb2 * (2.0 * y + b2) * iy2;
+      const T v2 = num * iyb2;
       const bool bad = v2 >= 1.0;
       const T sq = sqrt(1.0 - v2);
+      const T isq = 1.0 / sq;
       const T p = gf * (y * (1.0 - v2) - dd * sq);
-      const T f = y - p + 0.5 * b2 * (1.0 + v2) - 0.5 * sb2 / yy - utot;
-      const T yb = y + b2;
-      const T y3 = yy * y;
-      const T dv2 = (-2.0 * sb2 * yb / y3 / (yb * yb) -
-                          2.0 * (s2 + sb2 * (2.0 * y + b2) / yy) / (yb * yb * yb));
-      const T dp = gf * ((1.0 - v2) - y * dv2 + dd * dv2 / (2.0 * sq));
-      const T fp = 1.0 - dp + 0.5 * b2 * dv2 + sb2 / y3;
-      const T fabs_ = y + fabs(p) + 0.5 * b2 * (1.0 + v2) + 0.5 * sb2 / yy + utot;
+      const T f = y - p + 0.5 * b2 * (1.0 + v2) - 0.5 * sb2 * iy2 - utot;
+      const T dv2 = -2.0 * iyb * (sb2 * iy2 * iy + num * iyb2);
+      const T dp = gf * ((1.0 - v2) - y * dv2 + 0.5 * dd * dv2 * isq);
+      const T fp = 1.0 - dp + 0.5 * b2 * dv2 + sb2 * iy2 * iy;
+      const T fabs_ = y + fabs(p) + 0.5 * b2 * (1.0 + v2) + 0.5 * sb2 * iy2 + utot;
       if (defer_tol > 0.0 && it == 1 && (bad || !(fabs(f) <= T(defer_tol) * fabs_))) {
         o.deferred = true;
         o.ok = false;

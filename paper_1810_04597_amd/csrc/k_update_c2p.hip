@@ -74,7 +74,7 @@ __device__ __forceinline__ void sources_of(const PState<double>& s, const MET& m
 }
 
 // ------------------------------------------------------------------ RK update
-template <class MET>
+template <class MET, int DO>
 __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* __restrict__ prim,
                                                 double* __restrict__ cons,
                                                 double* __restrict__ cons_n,
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
       const long st = G.stride(d);
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = fp[(s - 3) * st];
-      L = L - fd_deriv(f, 1.0 / G.dx[d]);
+      L = L - fd_deriv_o<DO>(f, 1.0 / G.dx[d]);
     }
     L = L + src[q];
     const long o = (long)q * G.field + c;
@@ -134,10 +134,10 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
     const long s1 = G.stride(d1), s2 = G.stride(d2);
 #pragma unroll
     for (int s = 0; s < 6; ++s) f[s] = e2[(s - 3) * s1];
-    const double t1 = fd_deriv(f, 1.0 / G.dx[d1]);
+    const double t1 = fd_deriv_o<DO>(f, 1.0 / G.dx[d1]);
 #pragma unroll
     for (int s = 0; s < 6; ++s) f[s] = e1[(s - 3) * s2];
-    const double t2 = fd_deriv(f, 1.0 / G.dx[d2]);
+    const double t2 = fd_deriv_o<DO>(f, 1.0 / G.dx[d2]);
     const double L = -t1 + t2;
     const long o = (long)(C_BF1 + nd) * G.field + c;
     if (mode == 0) {
@@ -177,7 +177,7 @@ __device__ __forceinline__ double rk_store(double* __restrict__ cons, double* __
 // segment instead of six times; x^1 and x^2 stencils are read per plane.
 constexpr int KZ = 16;
 
-template <class MET, int SAVE>
+template <class MET, int SAVE, int DO>
 __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restrict__ prim,
                                                    double* __restrict__ cons,
                                                    double* __restrict__ cons_n,
@@ -226,25 +226,25 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
       const double* fy = flux + (5L + q) * G.field + c;
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = fx[(s - 3) * sx];
-      L = L - fd_deriv(f, idx0);
+      L = L - fd_deriv_o<DO>(f, idx0);
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = fy[(s - 3) * sy];
-      L = L - fd_deriv(f, idx1);
-      L = L - fd_deriv(wf[q], idx2);
+      L = L - fd_deriv_o<DO>(f, idx1);
+      L = L - fd_deriv_o<DO>(wf[q], idx2);
       rk_store<SAVE>(cons, cons_n, (long)q * G.field + c, a, b, dt, L);
     }
     // B^1: -D_2 E_3 + D_3 E_2
     {
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sy];
-      const double L = -fd_deriv(f, idx1) + fd_deriv(w2, idx2);
+      const double L = -fd_deriv_o<DO>(f, idx1) + fd_deriv_o<DO>(w2, idx2);
       bf[0] = rk_store<SAVE>(cons, cons_n, (long)C_BF1 * G.field + c, a, b, dt, L);
     }
     // B^2: -D_3 E_1 + D_1 E_3
     {
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sx];
-      const double L = -fd_deriv(w1, idx2) + fd_deriv(f, idx0);
+      const double L = -fd_deriv_o<DO>(w1, idx2) + fd_deriv_o<DO>(f, idx0);
       bf[1] = rk_store<SAVE>(cons, cons_n, (long)C_BF2 * G.field + c, a, b, dt, L);
     }
     // B^3: -D_1 E_2 + D_2 E_1
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
         f[s] = e2[c + (s - 3) * sx];
         g2[s] = e1[c + (s - 3) * sy];
       }
-      const double L = -fd_deriv(f, idx0) + fd_deriv(g2, idx1);
+      const double L = -fd_deriv_o<DO>(f, idx0) + fd_deriv_o<DO>(g2, idx1);
       bf[2] = rk_store<SAVE>(cons, cons_n, (long)C_BF3 * G.field + c, a, b, dt, L);
     }
     if (img) {
@@ -432,9 +432,9 @@ __global__ __launch_bounds__(256) void k_curl(Geom G, const double* __restrict__
     const int d1 = (nd + 1) % 3, d2 = (nd + 2) % 3;
     const long s1 = G.stride(d1), s2 = G.stride(d2);
     for (int s = 0; s < 6; ++s) f[s] = A[d2][c + (s - 3) * s1];
-    const double t1 = fd_deriv(f, 1.0 / G.dx[d1]);
+    const double t1 = fd_deriv_rt(f, 1.0 / G.dx[d1], G.dorder);
     for (int s = 0; s < 6; ++s) f[s] = A[d1][c + (s - 3) * s2];
-    const double t2 = fd_deriv(f, 1.0 / G.dx[d2]);
+    const double t2 = fd_deriv_rt(f, 1.0 / G.dx[d2], G.dorder);
     cons[(long)(C_BF1 + nd) * G.field + c] = t1 - t2;
   }
 }
@@ -592,7 +592,7 @@ __global__ __launch_bounds__(256) void k_diag(Geom G, const double* __restrict__
       const double* fp = cons + (long)(C_BF1 + d) * G.field + c;
       const long st = G.stride(d);
       for (int s = 0; s < 6; ++s) f[s] = fp[(s - 3) * st];
-      dv = dv + fd_deriv(f, 1.0 / G.dx[d]);
+      dv = dv + fd_deriv_rt(f, 1.0 / G.dx[d], G.dorder);
     }
     MET m;
     if constexpr (!MET::flat) m.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
@@ -677,26 +677,39 @@ void launch_bc_faces(const Geom& G, const BCSpec& bc, double* cons, hipStream_t 
   hipLaunchKernelGGL(k_bc_faces, dim3(nblk(ghost_count(G, bc.bc[2] == 2))), dim3(256), 0, s, G, bc, cons);
 }
 
-void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* cons,
-                   double* cons_n, const double* flux, const double* edges,
-                   const double* tab, double a, double b, double dt_host, const double* d_dt,
-                   double* out, int save_n, hipStream_t s, int img) {
+template <int DO>
+static void launch_update_o(const Geom& G, bool flat, int mode, const double* prim, double* cons,
+                            double* cons_n, const double* flux, const double* edges,
+                            const double* tab, double a, double b, double dt_host,
+                            const double* d_dt, double* out, int save_n, hipStream_t s, int img) {
   const unsigned nb = zone_blocks(G);
   if (flat && mode == 0) {
     const long nseg = (G.n[2] + KZ - 1) / KZ;
     const long total = (long)G.n[0] * G.n[1] * nseg;
     if (save_n)
-      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 1>), dim3(nblk(total)), dim3(256), 0, s, G,
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 1, DO>), dim3(nblk(total)), dim3(256), 0, s, G,
                          prim, cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, img);
     else
-      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 0>), dim3(nblk(total)), dim3(256), 0, s, G,
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 0, DO>), dim3(nblk(total)), dim3(256), 0, s, G,
                          prim, cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, img);
   } else if (flat)
-    hipLaunchKernelGGL(k_update<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
+    hipLaunchKernelGGL((k_update<FlatMet<double>, DO>), dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
                        cons_n, flux, edges, tab, a, b, dt_host, d_dt, out, save_n);
   else
-    hipLaunchKernelGGL(k_update<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
+    hipLaunchKernelGGL((k_update<TabMet<double>, DO>), dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
                        cons_n, flux, edges, tab, a, b, dt_host, d_dt, out, save_n);
+}
+
+void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* cons,
+                   double* cons_n, const double* flux, const double* edges,
+                   const double* tab, double a, double b, double dt_host, const double* d_dt,
+                   double* out, int save_n, hipStream_t s, int img) {
+  if (G.dorder == 4)
+    launch_update_o<4>(G, flat, mode, prim, cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, out,
+                       save_n, s, img);
+  else
+    launch_update_o<6>(G, flat, mode, prim, cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, out,
+                       save_n, s, img);
 }
 
 // d_dt[0]: dt of the last step, d_dt[1]: time; src: where the device dt was read

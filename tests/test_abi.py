@@ -57,6 +57,8 @@ def _desc(L, **kw):
     ("gamma_ad", 1.0, "gamma_ad"),
     ("recon", 3, "bad recon"),
     ("recon", -1, "bad recon"),
+    ("deriv_order", 5, "deriv_order"),
+    ("reserved", 1, "reserved"),
 ])
 def test_descriptor_validation_before_any_device_call(field, value, msg):
     L, lib = _lib()
