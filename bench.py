@@ -494,6 +494,8 @@ def main():
                     help="after the timed steps, one plain device copy of CALIB_COPY_BYTES "
                          "(reference for scaling the HBM traffic counters)")
     ap.add_argument("--profile-kernels", action="store_true", default=True)
+    ap.add_argument("--eager", action="store_true",
+                    help="time steps launched one by one instead of graph replays")
     ap.add_argument("--mode", default="step",
                     choices=["step", "precision", "learned", "torus", "torus-long", "recon", "split"],
                     help="step: the FP64 RK3 step (default); precision: FP32-flux form "
@@ -538,30 +540,47 @@ def main():
     print("bench: generated %d^3 initial data in %.1f s" % (n, time.perf_counter() - t0),
           file=sys.stderr, flush=True)
     prec = L.FP64 if args.precision == "fp64" else L.FP32_FLUX
-    G = Grid(g, precision=prec)
+    # the grid's own stream (default priority), so a step can be captured
+    G = Grid(g, precision=prec, stream=torch.cuda.Stream())
     G.curl_potential(d)
     G.set_primitives(d)
     del d
     for _ in range(args.warmup):
         G.rk_step()
+    if not args.eager:
+        G.rk_steps_graph(1)         # captures the step's graph
     G.synchronize()
     print("bench: warmup done", file=sys.stderr, flush=True)
+    # the timed steps run without the library's per-launch timing events
+    # (the per-kernel breakdown comes from a later pass of the same length);
+    # by default each step is one replay of the captured graph of the step
+    stream = G.stream
+
+    def timed_steps(graph):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        t0 = time.perf_counter()
+        if graph:
+            G.rk_steps_graph(args.steps)
+        else:
+            for _ in range(args.steps):
+                G.rk_step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), time.perf_counter() - t0
+
+    ms, wall = timed_steps(not args.eager)
+    ms_eager = ms if args.eager else timed_steps(False)[0]
+    prof = {}
     if args.profile_kernels:
         G.set_profiling(True)
         G.profile(reset=True)
-    stream = G.stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    w0 = time.perf_counter()
-    for _ in range(args.steps):
-        G.rk_step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = ev0.elapsed_time(ev1)
-    prof = G.profile(reset=True) if args.profile_kernels else {}
+        for _ in range(args.steps):
+            G.rk_step()
+        prof = G.profile(reset=True)
+        G.set_profiling(False)
     diag = G.diagnostics()
     if args.calib_copy:
         src = torch.ones(CALIB_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
@@ -624,6 +643,8 @@ def main():
         "kernels": kernels,
         "algorithmic_hbm_GBs": 896.0 * value / 1e9,
         "wall_s": wall,
+        "launch": "eager" if args.eager else "graph",
+        "ms_per_step_eager": ms_eager / args.steps,
         "diag": {"max_divb": diag["max_divb"], "n_c2p_fail": diag["n_c2p_fail"],
                  "rho_min": diag["rho_min"], "t": diag["t"]},
     }

@@ -227,6 +227,18 @@ int grmhd_shell_fluxes(grmhd_grid* h, double* host_out, size_t n_doubles);
  * a negative rho_cut. */
 int grmhd_mri_quality(grmhd_grid* h, double rho_cut, double q_min, double* host_out, size_t n_doubles);
 
+/* nsteps SSP-RK3 steps with the device CFL step (as grmhd_rk_step with
+ * dt <= 0), replayed from a HIP graph of one step: the step's ~25 kernel
+ * launches go to the device as one graph launch, which removes the gaps
+ * between them.  The graph is captured on the grid's stream at the first
+ * call and kept; binding fields, setting the metric, the Newton split or
+ * the network weights drops it (the next call captures again).  The first
+ * step after a state change (curl_potential, prim2cons, cons2prim, a step
+ * with a host dt) runs eagerly, as it also reduces the CFL step.  Results
+ * equal those of grmhd_rk_step bit for bit.  ESTATE while kernel timing is
+ * on or on the null stream (which cannot be captured). */
+int grmhd_rk_steps_graph(grmhd_grid* h, int32_t nsteps);
+
 /* Split inversion (load balance of the Newton iteration; paper, section on
  * the OpenMP optimisation: uneven work per zone left threads idle and the
  * fix was a guided schedule).  On the GPU the cost of a wavefront is its

@@ -21,7 +21,8 @@ EXPORTS = ("grmhd_init_grid", "grmhd_get_layout", "grmhd_bind_fields", "grmhd_se
            "grmhd_last_error", "grmhd_set_profiling", "grmhd_get_profile",
            "grmhd_profile_class_name", "grmhd_mlp_set_weights", "grmhd_mlp_get_weights",
            "grmhd_mlp_datagen", "grmhd_mlp_gradient", "grmhd_mlp_train_step", "grmhd_mlp_forward",
-           "grmhd_cons2prim_points", "grmhd_set_newton_split", "grmhd_mri_quality")
+           "grmhd_cons2prim_points", "grmhd_set_newton_split", "grmhd_mri_quality",
+           "grmhd_rk_steps_graph")
 MLP_NPARAM = 10448
 MLP_NNORM = 32
 PROF_NCLASS = 16
@@ -103,6 +104,7 @@ def lib():
     L.grmhd_last_error.restype = C.c_char_p
     L.grmhd_set_profiling.argtypes = [P, C.c_int]
     L.grmhd_set_newton_split.argtypes = [P, C.c_int32]
+    L.grmhd_rk_steps_graph.argtypes = [P, C.c_int32]
     L.grmhd_mri_quality.argtypes = [P, C.c_double, C.c_double, C.POINTER(C.c_double), C.c_size_t]
     L.grmhd_get_profile.argtypes = [P, C.POINTER(Profile), C.c_int]
     L.grmhd_profile_class_name.argtypes = [C.c_int]

@@ -110,9 +110,20 @@ struct grmhd_grid {
   // field, whose contents are dead while an inversion runs
   double* list_y() const { return scratch + (long)SCR_FLUX * G.field; }
   int split_it = 0;   // Newton iterations of the first pass of a split inversion (0: off)
+  // one captured device-dt step (grmhd_rk_steps_graph); dropped whenever the
+  // launch sequence or a pointer in it changes
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
   MlpState mlp;
   bool mlp_alloc = false;
 };
+
+static void graph_reset(grmhd_grid* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+}
 
 namespace {
 
@@ -270,6 +281,7 @@ int grmhd_bind_fields(grmhd_grid* h, double* prim, double* cons, void* scratch,
     return fail(GRMHD_EINVAL, "field pointers must be 256-byte aligned");
   if ((int64_t)scratch_bytes < h->lay.scratch_bytes)
     return fail(GRMHD_EINVAL, "scratch smaller than layout.scratch_bytes");
+  graph_reset(h);
   h->prim = prim;
   h->cons = cons;
   h->scratch = (double*)scratch;
@@ -280,6 +292,7 @@ int grmhd_bind_fields(grmhd_grid* h, double* prim, double* cons, void* scratch,
 int grmhd_set_metric(grmhd_grid* h, int kind, const double* host_tables, size_t n_doubles) {
   if (!h) return fail(GRMHD_EINVAL, "grid handle is NULL");
   h->next_dt_valid = false;
+  graph_reset(h);
   if (kind == GRMHD_METRIC_MINKOWSKI) {
     if (h->desc.coord != GRMHD_CART) return fail(GRMHD_EINVAL, "Minkowski kind needs Cartesian coordinates");
     if (h->tab) { (void)hipFree(h->tab); h->tab = nullptr; }
@@ -398,20 +411,13 @@ int grmhd_rhs(grmhd_grid* h, double* rhs_out) {
   return hip_check("rhs");
 }
 
-int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used) {
-  int rc = ready(h);
-  if (rc) return rc;
-  rc = mlp_ready(h);
-  if (rc) return rc;
-  if (!std::isfinite(dt)) return fail(GRMHD_EINVAL, "dt not finite");
-  // Device time step: the CFL dt of the current primitives.  When the last
-  // state change was a step taken in this mode, its final inversion already
-  // reduced that value into d_dt[2]; otherwise it is reduced here.
+// The three stages of one SSP-RK3 step (dt <= 0: the device CFL step in
+// d_dt[2], reduced again by the last inversion for the next step).  Kernel
+// launches only, on the grid's stream: a step whose dt is already on the
+// device is captured into a graph as it stands.
+static void step_stages(grmhd_grid* h, double dt) {
   const bool device_dt = dt <= 0.0;
   const double* dt_src = h->d_dt + 2;
-  if (device_dt && !h->next_dt_valid)
-    h->timed(10, [&] { launch_cfl(h->G, h->flat, h->prim, h->tab, h->desc.cfl, h->d_part, h->d_dt + 2, h->stream); });
-  h->next_dt_valid = false;
   // U^n is saved by the first stage's update (a = 0, so U^(1) needs only U^n).
   const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
   // periodic box: the update and the inversion write the ghost images of
@@ -430,6 +436,22 @@ int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used) {
     if (!img) h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
     c2p_with_guess(h, cp, s == 2 && device_dt);
   }
+}
+
+int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used) {
+  int rc = ready(h);
+  if (rc) return rc;
+  rc = mlp_ready(h);
+  if (rc) return rc;
+  if (!std::isfinite(dt)) return fail(GRMHD_EINVAL, "dt not finite");
+  // Device time step: the CFL dt of the current primitives.  When the last
+  // state change was a step taken in this mode, its final inversion already
+  // reduced that value into d_dt[2]; otherwise it is reduced here.
+  const bool device_dt = dt <= 0.0;
+  if (device_dt && !h->next_dt_valid)
+    h->timed(10, [&] { launch_cfl(h->G, h->flat, h->prim, h->tab, h->desc.cfl, h->d_part, h->d_dt + 2, h->stream); });
+  h->next_dt_valid = false;
+  step_stages(h, dt);
   h->step += 1;
   rc = hip_check("rk_step");
   if (rc) return rc;
@@ -440,6 +462,41 @@ int grmhd_rk_step(grmhd_grid* h, double dt, double* dt_used) {
     if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
   }
   return GRMHD_OK;
+}
+
+int grmhd_rk_steps_graph(grmhd_grid* h, int32_t nsteps) {
+  int rc = ready(h);
+  if (rc) return rc;
+  rc = mlp_ready(h);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(GRMHD_EINVAL, "nsteps must be >= 0");
+  if (h->prof_on) return fail(GRMHD_ESTATE, "graph replay needs kernel timing off");
+  if (h->stream == nullptr) return fail(GRMHD_ESTATE, "graph replay needs a stream other than the null stream");
+  int done = 0;
+  // the first step after a state change also reduces the CFL step: eager
+  if (nsteps > 0 && !h->next_dt_valid) {
+    rc = grmhd_rk_step(h, 0.0, nullptr);
+    if (rc) return rc;
+    done = 1;
+  }
+  if (done < nsteps && !h->gexec) {
+    hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+    step_stages(h, 0.0);
+    e = hipStreamEndCapture(h->stream, &h->graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      graph_reset(h);
+      return fail(GRMHD_EHIP, hipGetErrorString(e));
+    }
+  }
+  for (; done < nsteps; ++done) {
+    hipError_t e = hipGraphLaunch(h->gexec, h->stream);
+    if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+    h->step += 1;
+    h->next_dt_valid = true;
+  }
+  return hip_check("rk_steps_graph");
 }
 
 int grmhd_cons2prim(grmhd_grid* h, int64_t* n_fail, int strict) {
@@ -579,6 +636,7 @@ int grmhd_mlp_set_weights(grmhd_grid* h, const float* host_params, size_t n_para
     if (!std::isfinite(host_params[q])) return fail(GRMHD_EINVAL, "non-finite weight");
   for (size_t q = 0; q < n_norm; ++q)
     if (!std::isfinite(host_norm[q])) return fail(GRMHD_EINVAL, "non-finite normalisation");
+  graph_reset(h);
   int rc = mlp_alloc(h);
   if (rc) return rc;
   hipError_t e = hipMemcpy(h->mlp.wf, host_params, NPARAM * sizeof(float), hipMemcpyHostToDevice);
@@ -679,6 +737,7 @@ int grmhd_set_newton_split(grmhd_grid* h, int32_t iters) {
   if (iters > 0 && h->desc.c2p_guess == GRMHD_GUESS_MLP)
     return fail(GRMHD_EINVAL, "the split inversion is not combined with the learned guess");
   if (iters == h->split_it) return GRMHD_OK;
+  graph_reset(h);
   h->split_it = iters;
   // the second pass's counter slots must read zero whenever it does not run
   hipError_t e = hipMemsetAsync(h->d_spart + (long)h->nblk * C2P_NSTAT, 0,
@@ -723,6 +782,7 @@ const char* grmhd_profile_class_name(int cls) {
 void grmhd_destroy(grmhd_grid* h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream); else (void)hipDeviceSynchronize();
+  graph_reset(h);
   for (auto& r : h->pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
   for (auto ev : h->pool) (void)hipEventDestroy(ev);
   if (h->mlp_alloc) {

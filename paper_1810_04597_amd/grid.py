@@ -25,24 +25,38 @@ class Grid:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.desc = L.make_desc(spec, precision, guess, recon, deriv_order)
         h = C.c_void_p()
-        L.check(self.lib.grmhd_init_grid(C.byref(self.desc), C.c_void_p(self.stream.cuda_stream),
-                                         C.byref(h)))
+        self._call(self.lib.grmhd_init_grid, C.byref(self.desc), C.c_void_p(self.stream.cuda_stream),
+                                         C.byref(h))
         self.h = h
         lay = L.Layout()
-        L.check(self.lib.grmhd_get_layout(self.h, C.byref(lay)))
+        self._call(self.lib.grmhd_get_layout, self.h, C.byref(lay))
         self.layout = lay
         f64 = dict(dtype=torch.float64, device=self.device)
         self.prim = torch.zeros(int(lay.prim_doubles), **f64)
         self.cons = torch.zeros(int(lay.cons_doubles), **f64)
         self.scratch = torch.zeros(int(lay.scratch_bytes) // 8, **f64)
-        L.check(self.lib.grmhd_bind_fields(self.h, C.c_void_p(self.prim.data_ptr()),
+        self._call(self.lib.grmhd_bind_fields, self.h, C.c_void_p(self.prim.data_ptr()),
                                            C.c_void_p(self.cons.data_ptr()),
                                            C.c_void_p(self.scratch.data_ptr()),
-                                           C.c_size_t(int(lay.scratch_bytes))))
+                                           C.c_size_t(int(lay.scratch_bytes)))
         if tables is None:
-            L.check(self.lib.grmhd_set_metric(self.h, L.METRIC_MINKOWSKI, None, 0))
+            self._call(self.lib.grmhd_set_metric, self.h, L.METRIC_MINKOWSKI, None, 0)
         else:
             self.set_metric(tables)
+
+    def _call(self, fn, *args):
+        """One library call on the grid's stream.  When that is not torch's
+        current stream, the grid stream first waits for torch's pending work
+        (uploads, allocations) and torch's stream then waits for the call
+        (results read through torch)."""
+        cur = torch.cuda.current_stream(self.device)
+        other = cur != self.stream
+        if other:
+            self.stream.wait_stream(cur)
+        rc = L.check(fn(*args))
+        if other:
+            cur.wait_stream(self.stream)
+        return rc
 
     # ------------------------------------------------------------ layout views
     def field_view(self, flat, f):
@@ -62,8 +76,8 @@ class Grid:
     # ------------------------------------------------------------ API calls
     def set_metric(self, tables):
         t = np.ascontiguousarray(tables, dtype=np.float64)
-        L.check(self.lib.grmhd_set_metric(self.h, L.METRIC_TABLE_AXISYM,
-                                          t.ctypes.data_as(C.POINTER(C.c_double)), t.size))
+        self._call(self.lib.grmhd_set_metric, self.h, L.METRIC_TABLE_AXISYM,
+                                          t.ctypes.data_as(C.POINTER(C.c_double)), t.size)
 
     def set_primitives(self, data):
         """Interior rho, u, p (numpy [k][j][i]) -> prim; then prim2cons."""
@@ -84,42 +98,42 @@ class Grid:
             t = self.new_single()
             self.field_view(t, 0).copy_(torch.from_numpy(np.ascontiguousarray(data["A%d" % (a + 1)], dtype=np.float64)))
             arrs.append(t)
-        L.check(self.lib.grmhd_curl_potential(self.h, *[C.c_void_p(t.data_ptr()) for t in arrs]))
+        self._call(self.lib.grmhd_curl_potential, self.h, *[C.c_void_p(t.data_ptr()) for t in arrs])
         self.synchronize()
 
     def prim2cons(self):
-        L.check(self.lib.grmhd_prim2cons(self.h))
+        self._call(self.lib.grmhd_prim2cons, self.h)
 
     def rhs(self):
         out = torch.zeros_like(self.cons)
-        L.check(self.lib.grmhd_rhs(self.h, C.c_void_p(out.data_ptr())))
+        self._call(self.lib.grmhd_rhs, self.h, C.c_void_p(out.data_ptr()))
         return out
 
     def rk_step(self, dt=0.0, want_dt=False):
         v = C.c_double(0.0)
-        L.check(self.lib.grmhd_rk_step(self.h, C.c_double(dt), C.byref(v) if want_dt else None))
+        self._call(self.lib.grmhd_rk_step, self.h, C.c_double(dt), C.byref(v) if want_dt else None)
         return v.value if want_dt else None
 
     def cons2prim(self, strict=False):
         n = C.c_int64(0)
-        L.check(self.lib.grmhd_cons2prim(self.h, C.byref(n), 1 if strict else 0))
+        self._call(self.lib.grmhd_cons2prim, self.h, C.byref(n), 1 if strict else 0)
         return n.value
 
     def compute_dt(self):
         v = C.c_double(0.0)
-        L.check(self.lib.grmhd_compute_dt(self.h, C.byref(v)))
+        self._call(self.lib.grmhd_compute_dt, self.h, C.byref(v))
         return v.value
 
     def diagnostics(self):
         d = L.Diag()
-        L.check(self.lib.grmhd_diagnostics(self.h, C.byref(d)))
+        self._call(self.lib.grmhd_diagnostics, self.h, C.byref(d))
         return d.as_dict()
 
     def shell_fluxes(self):
         """{F_D, F_tau, Phi, Phi_s}: fluxes through the x^1 = const shells (numpy, n1 each)."""
         n1 = self.spec.n[0]
         buf = (C.c_double * (4 * n1))()
-        L.check(self.lib.grmhd_shell_fluxes(self.h, buf, C.c_size_t(4 * n1)))
+        self._call(self.lib.grmhd_shell_fluxes, self.h, buf, C.c_size_t(4 * n1))
         a = np.frombuffer(buf, dtype=np.float64).copy()
         return {"F_D": a[0:n1], "F_tau": a[n1:2 * n1], "Phi": a[2 * n1:3 * n1], "Phi_s": a[3 * n1:]}
 
@@ -130,7 +144,7 @@ class Grid:
         fractions of body zones with Q >= q_min."""
         n1 = self.spec.n[0]
         buf = (C.c_double * (6 * n1))()
-        L.check(self.lib.grmhd_mri_quality(self.h, float(rho_cut), float(q_min), buf, C.c_size_t(6 * n1)))
+        self._call(self.lib.grmhd_mri_quality, self.h, float(rho_cut), float(q_min), buf, C.c_size_t(6 * n1))
         a = np.frombuffer(buf, dtype=np.float64).copy().reshape(6, n1)
         out = dict(zip(("wQ2", "wQ3", "w", "n_body", "n_Q2_ok", "n_Q3_ok"), a))
         w, nb = a[2].sum(), a[3].sum()
@@ -145,14 +159,14 @@ class Grid:
         flat = np.ascontiguousarray(flat, dtype=np.float32)
         norm = np.ascontiguousarray(norm, dtype=np.float32)
         Fp = C.POINTER(C.c_float)
-        L.check(self.lib.grmhd_mlp_set_weights(self.h, flat.ctypes.data_as(Fp), flat.size,
-                                               norm.ctypes.data_as(Fp), norm.size))
+        self._call(self.lib.grmhd_mlp_set_weights, self.h, flat.ctypes.data_as(Fp), flat.size,
+                                               norm.ctypes.data_as(Fp), norm.size)
 
     def mlp_get_weights(self):
         flat = np.zeros(L.MLP_NPARAM, dtype=np.float32)
         norm = np.zeros(L.MLP_NNORM, dtype=np.float32)
         Fp = C.POINTER(C.c_float)
-        L.check(self.lib.grmhd_mlp_get_weights(self.h, flat.ctypes.data_as(Fp), norm.ctypes.data_as(Fp)))
+        self._call(self.lib.grmhd_mlp_get_weights, self.h, flat.ctypes.data_as(Fp), norm.ctypes.data_as(Fp))
         return flat, norm
 
     def mlp_datagen(self, prims, set_norm=False, want_cons=False):
@@ -164,10 +178,10 @@ class Grid:
         feat = torch.empty((n, 8), dtype=torch.float32, device=self.device)
         targ = torch.empty((n, 8), dtype=torch.float32, device=self.device)
         cons = torch.empty((n, 8), dtype=torch.float64, device=self.device) if want_cons else None
-        L.check(self.lib.grmhd_mlp_datagen(self.h, C.c_void_p(pr.data_ptr()), n,
+        self._call(self.lib.grmhd_mlp_datagen, self.h, C.c_void_p(pr.data_ptr()), n,
                                            C.c_void_p(feat.data_ptr()), C.c_void_p(targ.data_ptr()),
                                            C.c_void_p(cons.data_ptr()) if want_cons else None,
-                                           1 if set_norm else 0))
+                                           1 if set_norm else 0)
         self.synchronize()
         return (feat, targ, cons) if want_cons else (feat, targ)
 
@@ -177,46 +191,51 @@ class Grid:
         n = cons.shape[0]
         prim = torch.empty((n, 8), dtype=torch.float64, device=self.device)
         it = torch.empty((n,), dtype=torch.int32, device=self.device)
-        L.check(self.lib.grmhd_cons2prim_points(self.h, C.c_void_p(cons.data_ptr()), n,
+        self._call(self.lib.grmhd_cons2prim_points, self.h, C.c_void_p(cons.data_ptr()), n,
                                                 C.c_void_p(y0.data_ptr()) if y0 is not None else None,
-                                                C.c_void_p(prim.data_ptr()), C.c_void_p(it.data_ptr())))
+                                                C.c_void_p(prim.data_ptr()), C.c_void_p(it.data_ptr()))
         self.synchronize()
         return prim, it
 
     def mlp_gradient(self, feat, targ):
         g = np.zeros(L.MLP_NPARAM, dtype=np.float32)
         loss = C.c_double(0.0)
-        L.check(self.lib.grmhd_mlp_gradient(self.h, C.c_void_p(feat.data_ptr()), C.c_void_p(targ.data_ptr()),
+        self._call(self.lib.grmhd_mlp_gradient, self.h, C.c_void_p(feat.data_ptr()), C.c_void_p(targ.data_ptr()),
                                             feat.shape[0], g.ctypes.data_as(C.POINTER(C.c_float)),
-                                            C.byref(loss)))
+                                            C.byref(loss))
         return g, loss.value
 
     def mlp_train_step(self, feat, targ, lr, want_loss=False):
         loss = C.c_double(0.0)
-        L.check(self.lib.grmhd_mlp_train_step(self.h, C.c_void_p(feat.data_ptr()), C.c_void_p(targ.data_ptr()),
+        self._call(self.lib.grmhd_mlp_train_step, self.h, C.c_void_p(feat.data_ptr()), C.c_void_p(targ.data_ptr()),
                                               feat.shape[0], C.c_float(lr),
-                                              C.byref(loss) if want_loss else None))
+                                              C.byref(loss) if want_loss else None)
         return loss.value if want_loss else None
 
     def mlp_forward(self, feat):
         out = torch.empty((feat.shape[0], 8), dtype=torch.float32, device=self.device)
-        L.check(self.lib.grmhd_mlp_forward(self.h, C.c_void_p(feat.data_ptr()), feat.shape[0],
-                                           C.c_void_p(out.data_ptr())))
+        self._call(self.lib.grmhd_mlp_forward, self.h, C.c_void_p(feat.data_ptr()), feat.shape[0],
+                                           C.c_void_p(out.data_ptr()))
         self.synchronize()
         return out
+
+    def rk_steps_graph(self, nsteps):
+        """nsteps device-dt RK3 steps replayed from a captured HIP graph of
+        one step (the grid needs its own stream: Grid(..., stream=...))."""
+        self._call(self.lib.grmhd_rk_steps_graph, self.h, int(nsteps))
 
     def set_newton_split(self, iters):
         """Split inversion: at most iters Newton iterations in the first pass,
         the rest of the slow zones in a second, compact pass (0: off)."""
-        L.check(self.lib.grmhd_set_newton_split(self.h, int(iters)))
+        self._call(self.lib.grmhd_set_newton_split, self.h, int(iters))
 
     def set_profiling(self, on=True):
-        L.check(self.lib.grmhd_set_profiling(self.h, 1 if on else 0))
+        self._call(self.lib.grmhd_set_profiling, self.h, 1 if on else 0)
 
     def profile(self, reset=True):
         """{kernel class: (total ms, launches)} since the last reset."""
         p = L.Profile()
-        L.check(self.lib.grmhd_get_profile(self.h, C.byref(p), 1 if reset else 0))
+        self._call(self.lib.grmhd_get_profile, self.h, C.byref(p), 1 if reset else 0)
         out = {}
         for c in range(L.PROF_NCLASS):
             if p.launches[c]:
