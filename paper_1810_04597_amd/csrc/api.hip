@@ -339,17 +339,20 @@ int grmhd_prim2cons(grmhd_grid* h) {
 
 // fill_ghosts: ghost fill of the primitives first (skipped inside rk_step on
 // a periodic box, where the inversion writes the ghost images itself).
-static void rhs_pieces(grmhd_grid* h, bool fill_ghosts = true) {
+// cons_cur: the conserved state the right-hand side reads (its face fields):
+// the bound cons, or the step's scratch stage buffer.
+static void rhs_pieces(grmhd_grid* h, bool fill_ghosts = true, double* cons_cur = nullptr) {
+  double* const U = cons_cur ? cons_cur : h->cons;
   const bool fp32 = h->desc.precision == GRMHD_FP32_FLUX;
   if (fill_ghosts) h->timed(0, [&] { launch_bc_centred(h->G, h->bc, h->prim, NPRIM, h->stream); });
   for (int d = 0; d < 3; ++d)
     h->timed(1 + d, [&] {
-      launch_sweep(d, h->G, h->flat, fp32, h->desc.recon, h->prim, h->cons, h->tab, h->flux(), h->ctd(),
+      launch_sweep(d, h->G, h->flat, fp32, h->desc.recon, h->prim, U, h->tab, h->flux(), h->ctd(),
                    h->stream);
     });
   for (int e = 0; e < 3; ++e)
     h->timed(4 + e, [&] {
-      launch_edge(e, h->G, h->flat, fp32, h->desc.recon, h->cons, h->tab, h->ctd(), h->edges(), h->stream);
+      launch_edge(e, h->G, h->flat, fp32, h->desc.recon, U, h->tab, h->ctd(), h->edges(), h->stream);
     });
 }
 
@@ -357,17 +360,21 @@ static void rhs_pieces(grmhd_grid* h, bool fill_ghosts = true) {
 // Learned guess: the inversion defers zones with a poor warm start to a list,
 // the network pass inverts those; counters and CFL partials of both passes
 // are reduced together.
-static void c2p_with_guess(grmhd_grid* h, const C2PParams& cp, bool with_cfl = false) {
+// cons_cur: the conserved state to invert (the bound cons, or the step's
+// scratch stage buffer); floored zones are written back to it.
+static void c2p_with_guess(grmhd_grid* h, const C2PParams& cp, bool with_cfl = false,
+                           double* cons_cur = nullptr) {
+  double* const U = cons_cur ? cons_cur : h->cons;
   double* cflp = with_cfl ? h->d_part : nullptr;
   const int nb = (int)h->nblk;
   if (cp.guess == GRMHD_GUESS_MLP) {
     h->timed(9, [&] {
       launch_zero_int(h->d_list_n, h->stream);
-      launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, cflp, h->list(), h->d_list_n,
+      launch_c2p(h->G, h->flat, cp, h->prim, U, h->tab, h->d_spart, cflp, h->list(), h->d_list_n,
                  nullptr, h->stream);
     });
     h->timed(14, [&] {
-      mlp_launch_c2p_list(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->mlp, h->list(), h->d_list_n,
+      mlp_launch_c2p_list(h->G, h->flat, cp, h->prim, U, h->tab, h->mlp, h->list(), h->d_list_n,
                           h->d_spart + (long)nb * C2P_NSTAT, cflp ? cflp + nb : nullptr, h->stream);
     });
     if (with_cfl) launch_dt_final(cflp, nb + C2P_LIST_BLOCKS, h->desc.cfl, h->d_dt + 2, h->stream);
@@ -376,17 +383,17 @@ static void c2p_with_guess(grmhd_grid* h, const C2PParams& cp, bool with_cfl = f
     c1.split_it = h->split_it;
     h->timed(9, [&] {
       launch_zero_int(h->d_list_n, h->stream);
-      launch_c2p(h->G, h->flat, c1, h->prim, h->cons, h->tab, h->d_spart, cflp, h->list(), h->d_list_n,
+      launch_c2p(h->G, h->flat, c1, h->prim, U, h->tab, h->d_spart, cflp, h->list(), h->d_list_n,
                  h->list_y(), h->stream);
     });
     h->timed(11, [&] {
-      launch_c2p_split(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->list(), h->d_list_n, h->list_y(),
+      launch_c2p_split(h->G, h->flat, cp, h->prim, U, h->tab, h->list(), h->d_list_n, h->list_y(),
                        h->d_spart + (long)nb * C2P_NSTAT, cflp ? cflp + nb : nullptr, h->stream);
     });
     if (with_cfl) launch_dt_final(cflp, nb + C2P_LIST_BLOCKS, h->desc.cfl, h->d_dt + 2, h->stream);
   } else {
     h->timed(9, [&] {
-      launch_c2p(h->G, h->flat, cp, h->prim, h->cons, h->tab, h->d_spart, cflp, nullptr, nullptr, nullptr,
+      launch_c2p(h->G, h->flat, cp, h->prim, U, h->tab, h->d_spart, cflp, nullptr, nullptr, nullptr,
                  h->stream);
     });
     if (with_cfl) launch_dt_final(cflp, nb, h->desc.cfl, h->d_dt + 2, h->stream);
@@ -406,7 +413,7 @@ int grmhd_rhs(grmhd_grid* h, double* rhs_out) {
   rhs_pieces(h);
   h->timed(13, [&] {
     launch_update(h->G, h->flat, 1, h->prim, h->cons, h->cons_n(), h->flux(), h->edges(), h->tab,
-                  0.0, 0.0, 0.0, h->d_dt, rhs_out, 0, h->stream);
+                  0.0, 0.0, 0.0, h->d_dt, rhs_out, 1, h->stream);
   });
   return hip_check("rhs");
 }
@@ -418,23 +425,29 @@ int grmhd_rhs(grmhd_grid* h, double* rhs_out) {
 static void step_stages(grmhd_grid* h, double dt) {
   const bool device_dt = dt <= 0.0;
   const double* dt_src = h->d_dt + 2;
-  // U^n is saved by the first stage's update (a = 0, so U^(1) needs only U^n).
+  // Shu-Osher weights: U^(s+1) = A[s] U^n + B[s] (U^(s) + dt L(U^(s)))
   const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
   // periodic box: the update and the inversion write the ghost images of
   // what they produce, so the stage needs no separate ghost fills
   C2PParams cp = c2p_params(h->desc);
   const bool img = h->img && h->flat;
   cp.img = img ? 1 : 0;
+  // stage buffers: U^n stays in the bound cons until the last stage writes
+  // U^(3) over it; U^(1) and U^(2) live in the scratch buffer S (no copy of U^n)
+  double* const Un = h->cons;
+  double* const S = h->cons_n();
   for (int s = 0; s < 3; ++s) {
-    rhs_pieces(h, !img);
+    double* const cur = s == 0 ? Un : S;        // state the stage's RHS reads
+    double* const next = s == 2 ? Un : S;       // state the stage produces
+    rhs_pieces(h, !img, cur);
     h->timed(7, [&] {
-      launch_update(h->G, h->flat, 0, h->prim, h->cons, h->cons_n(), h->flux(), h->edges(), h->tab,
-                    A[s], B[s], dt, dt_src, nullptr, s == 0 ? 1 : 0, h->stream, img ? 1 : 0);
+      launch_update(h->G, h->flat, 0, h->prim, s == 0 ? Un : S, s == 0 ? S : Un, h->flux(), h->edges(),
+                    h->tab, A[s], B[s], dt, dt_src, nullptr, s + 1, h->stream, img ? 1 : 0);
     });
     // dt and time are recorded once the last update has consumed d_dt[2]
     if (s == 2) h->timed(12, [&] { launch_advance(h->d_dt, dt_src, dt, h->stream); });
-    if (!img) h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
-    c2p_with_guess(h, cp, s == 2 && device_dt);
+    if (!img) h->timed(8, [&] { launch_bc_faces(h->G, h->bc, next, h->stream); });
+    c2p_with_guess(h, cp, s == 2 && device_dt, next);
   }
 }
 

@@ -36,14 +36,16 @@ void launch_sweep(int d, const Geom& G, bool flat, bool fp32, int recon, const d
                   const double* cons, const double* tab, double* flux, double* ctd, hipStream_t s);
 void launch_edge(int e, const Geom& G, bool flat, bool fp32, int recon, const double* cons,
                  const double* tab, const double* ctd, double* edges, hipStream_t s);
-// mode 0: RK combine into cons (needs cons_n, a, b, dt on device);
-// mode 1: write L into out (cons layout).
+// mode 0: SSP-RK3 stage `stage` (1, 2, 3) over the distinct buffers x, y
+// (stage 1: x = U^n -> y; stage 2: x updated in place, U^n read from y;
+// stage 3: x -> y, overwriting U^n); dt from d_dt when dt_host <= 0.
+// mode 1: write L of the state in x into out (cons layout).
 // img (flat metric, mode 0): all directions periodic with n >= 2 NG; the new
 // face fields are also written to their ghost images (no separate face fill).
-void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* cons,
-                   double* cons_n, const double* flux, const double* edges,
-                   const double* tab, double a, double b, double dt_host, const double* d_dt,
-                   double* out, int save_n, hipStream_t s, int img = 0);
+void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* x, double* y,
+                   const double* flux, const double* edges, const double* tab, double a, double b,
+                   double dt_host, const double* d_dt, double* out, int stage, hipStream_t s,
+                   int img = 0);
 void launch_advance(double* d_dt, const double* src, double dt_host, hipStream_t s);
 // Inversion of all interior zones; per-block counters into partials[0, nblk),
 // CFL partials (nullable) into cfl_partials[0, nblk).  list != nullptr: defer

@@ -74,15 +74,46 @@ __device__ __forceinline__ void sources_of(const PState<double>& s, const MET& m
 }
 
 // ------------------------------------------------------------------ RK update
+// RK stage store over two distinct buffers x and y (SSP-RK3, Shu-Osher form,
+// U^(s+1) = a U^n + b (U^(s) + dt L)), so that U^n is never copied:
+//   stage 1 (a = 0): reads U^n from x, writes U^(1) to y;
+//   stage 2: reads U^(1) from x and U^n from y, writes U^(2) to x;
+//   stage 3: reads U^(2) from x and U^n from y, writes U^(3) to y.
+// The caller's buffer holds U^n and receives U^(3); the other is scratch.
+// Returns the stored value.  ST is a template argument so that a
+// z-iteration of the update below is one basic block: the scheduler can then
+// issue every field's stencil loads ahead of the earlier fields' stores.
+template <int ST>
+__device__ __forceinline__ double rk_store(double* __restrict__ x, double* __restrict__ y, long o,
+                                           double a, double b, double dt, double L) {
+  const double old = x[o];
+  if constexpr (ST == 1) {
+    const double v = b * (old + dt * L);   // a = 0
+    y[o] = v;
+    return v;
+  } else {
+    const double v = a * y[o] + b * (old + dt * L);
+    if constexpr (ST == 2) x[o] = v; else y[o] = v;
+    return v;
+  }
+}
+
+__device__ __forceinline__ double rk_store_rt(double* __restrict__ x, double* __restrict__ y, long o,
+                                              double a, double b, double dt, double L, int stage) {
+  if (stage == 1) return rk_store<1>(x, y, o, a, b, dt, L);
+  if (stage == 2) return rk_store<2>(x, y, o, a, b, dt, L);
+  return rk_store<3>(x, y, o, a, b, dt, L);
+}
+
 template <class MET, int DO>
 __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* __restrict__ prim,
-                                                double* __restrict__ cons,
-                                                double* __restrict__ cons_n,
+                                                double* __restrict__ x,
+                                                double* __restrict__ y,
                                                 const double* __restrict__ flux,
                                                 const double* __restrict__ edges,
                                                 const double* __restrict__ tab, double a, double b,
                                                 double dt_host, const double* __restrict__ d_dt,
-                                                double* __restrict__ out, int save_n) {
+                                                double* __restrict__ out, int stage) {
   const long t = flat_thread();
   if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
   int i, j, k;
@@ -118,12 +149,9 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
     }
     L = L + src[q];
     const long o = (long)q * G.field + c;
-    if (mode == 0) {
-      const double old = cons[o];
-      const double un = save_n ? old : cons_n[o];
-      if (save_n) cons_n[o] = old;
-      cons[o] = a * un + b * (old + dt * L);
-    } else
+    if (mode == 0)
+      rk_store_rt(x, y, o, a, b, dt, L, stage);
+    else
       out[o] = L;
   }
 #pragma unroll
@@ -140,36 +168,13 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
     const double t2 = fd_deriv_o<DO>(f, 1.0 / G.dx[d2]);
     const double L = -t1 + t2;
     const long o = (long)(C_BF1 + nd) * G.field + c;
-    if (mode == 0) {
-      const double old = cons[o];
-      const double un = save_n ? old : cons_n[o];
-      if (save_n) cons_n[o] = old;
-      cons[o] = a * un + b * (old + dt * L);
-    } else
+    if (mode == 0)
+      rk_store_rt(x, y, o, a, b, dt, L, stage);
+    else
       out[o] = L;
   }
 }
 
-// RK stage store; SAVE (first stage, a = 0): U^n is this value, saved.
-// Returns the stored value.
-// SAVE is a template argument so that a z-iteration of the update below is
-// one basic block: the scheduler can then issue every field's stencil loads
-// ahead of the earlier fields' stores instead of waiting field by field.
-template <int SAVE>
-__device__ __forceinline__ double rk_store(double* __restrict__ cons, double* __restrict__ cons_n, long o,
-                                           double a, double b, double dt, double L) {
-  const double old = cons[o];
-  double un;
-  if constexpr (SAVE) {
-    un = old;
-    cons_n[o] = old;
-  } else {
-    un = cons_n[o];
-  }
-  const double v = a * un + b * (old + dt * L);
-  cons[o] = v;
-  return v;
-}
 
 // z-marching variant (flat metric): one thread per (i, j) column segment of
 // KZ zones along x^3.  The x^3 stencils (F of the x^3 sweep, E_1, E_2) are
@@ -177,10 +182,10 @@ __device__ __forceinline__ double rk_store(double* __restrict__ cons, double* __
 // segment instead of six times; x^1 and x^2 stencils are read per plane.
 constexpr int KZ = 16;
 
-template <class MET, int SAVE, int DO>
+template <class MET, int ST, int DO>
 __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restrict__ prim,
-                                                   double* __restrict__ cons,
-                                                   double* __restrict__ cons_n,
+                                                   double* __restrict__ x,
+                                                   double* __restrict__ y,
                                                    const double* __restrict__ flux,
                                                    const double* __restrict__ edges,
                                                    const double* __restrict__ tab, double a,
@@ -231,21 +236,21 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
       for (int s = 0; s < 6; ++s) f[s] = fy[(s - 3) * sy];
       L = L - fd_deriv_o<DO>(f, idx1);
       L = L - fd_deriv_o<DO>(wf[q], idx2);
-      rk_store<SAVE>(cons, cons_n, (long)q * G.field + c, a, b, dt, L);
+      rk_store<ST>(x, y, (long)q * G.field + c, a, b, dt, L);
     }
     // B^1: -D_2 E_3 + D_3 E_2
     {
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sy];
       const double L = -fd_deriv_o<DO>(f, idx1) + fd_deriv_o<DO>(w2, idx2);
-      bf[0] = rk_store<SAVE>(cons, cons_n, (long)C_BF1 * G.field + c, a, b, dt, L);
+      bf[0] = rk_store<ST>(x, y, (long)C_BF1 * G.field + c, a, b, dt, L);
     }
     // B^2: -D_3 E_1 + D_1 E_3
     {
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sx];
       const double L = -fd_deriv_o<DO>(w1, idx2) + fd_deriv_o<DO>(f, idx0);
-      bf[1] = rk_store<SAVE>(cons, cons_n, (long)C_BF2 * G.field + c, a, b, dt, L);
+      bf[1] = rk_store<ST>(x, y, (long)C_BF2 * G.field + c, a, b, dt, L);
     }
     // B^3: -D_1 E_2 + D_2 E_1
     {
@@ -256,11 +261,11 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
         g2[s] = e1[c + (s - 3) * sy];
       }
       const double L = -fd_deriv_o<DO>(f, idx0) + fd_deriv_o<DO>(g2, idx1);
-      bf[2] = rk_store<SAVE>(cons, cons_n, (long)C_BF3 * G.field + c, a, b, dt, L);
+      bf[2] = rk_store<ST>(x, y, (long)C_BF3 * G.field + c, a, b, dt, L);
     }
     if (img) {
       constexpr int ff[3] = {C_BF1, C_BF2, C_BF3};
-      write_images<3>(G, cons, i, j, k, ff, bf);
+      write_images<3>(G, ST == 2 ? x : y, i, j, k, ff, bf);
     }
 #pragma unroll
     for (int s = 0; s < 5; ++s) {
@@ -678,38 +683,38 @@ void launch_bc_faces(const Geom& G, const BCSpec& bc, double* cons, hipStream_t 
 }
 
 template <int DO>
-static void launch_update_o(const Geom& G, bool flat, int mode, const double* prim, double* cons,
-                            double* cons_n, const double* flux, const double* edges,
+static void launch_update_o(const Geom& G, bool flat, int mode, const double* prim, double* x,
+                            double* y, const double* flux, const double* edges,
                             const double* tab, double a, double b, double dt_host,
-                            const double* d_dt, double* out, int save_n, hipStream_t s, int img) {
+                            const double* d_dt, double* out, int stage, hipStream_t s, int img) {
   const unsigned nb = zone_blocks(G);
   if (flat && mode == 0) {
     const long nseg = (G.n[2] + KZ - 1) / KZ;
-    const long total = (long)G.n[0] * G.n[1] * nseg;
-    if (save_n)
-      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 1, DO>), dim3(nblk(total)), dim3(256), 0, s, G,
-                         prim, cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, img);
+    const unsigned ng = nblk((long)G.n[0] * G.n[1] * nseg);
+    if (stage == 1)
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 1, DO>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
+                         flux, edges, tab, a, b, dt_host, d_dt, img);
+    else if (stage == 2)
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 2, DO>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
+                         flux, edges, tab, a, b, dt_host, d_dt, img);
     else
-      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 0, DO>), dim3(nblk(total)), dim3(256), 0, s, G,
-                         prim, cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, img);
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 3, DO>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
+                         flux, edges, tab, a, b, dt_host, d_dt, img);
   } else if (flat)
-    hipLaunchKernelGGL((k_update<FlatMet<double>, DO>), dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
-                       cons_n, flux, edges, tab, a, b, dt_host, d_dt, out, save_n);
+    hipLaunchKernelGGL((k_update<FlatMet<double>, DO>), dim3(nb), dim3(256), 0, s, G, mode, prim, x, y,
+                       flux, edges, tab, a, b, dt_host, d_dt, out, stage);
   else
-    hipLaunchKernelGGL((k_update<TabMet<double>, DO>), dim3(nb), dim3(256), 0, s, G, mode, prim, cons,
-                       cons_n, flux, edges, tab, a, b, dt_host, d_dt, out, save_n);
+    hipLaunchKernelGGL((k_update<TabMet<double>, DO>), dim3(nb), dim3(256), 0, s, G, mode, prim, x, y,
+                       flux, edges, tab, a, b, dt_host, d_dt, out, stage);
 }
 
-void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* cons,
-                   double* cons_n, const double* flux, const double* edges,
-                   const double* tab, double a, double b, double dt_host, const double* d_dt,
-                   double* out, int save_n, hipStream_t s, int img) {
+void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* x, double* y,
+                   const double* flux, const double* edges, const double* tab, double a, double b,
+                   double dt_host, const double* d_dt, double* out, int stage, hipStream_t s, int img) {
   if (G.dorder == 4)
-    launch_update_o<4>(G, flat, mode, prim, cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, out,
-                       save_n, s, img);
+    launch_update_o<4>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img);
   else
-    launch_update_o<6>(G, flat, mode, prim, cons, cons_n, flux, edges, tab, a, b, dt_host, d_dt, out,
-                       save_n, s, img);
+    launch_update_o<6>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img);
 }
 
 // d_dt[0]: dt of the last step, d_dt[1]: time; src: where the device dt was read
