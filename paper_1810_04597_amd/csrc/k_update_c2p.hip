@@ -278,11 +278,42 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
 }
 
 // ------------------------------------------------------------------ inversion
+// Zone order of the inversion.  The centred field of a zone reads the x^2
+// face field over rows j-3 .. j+2 and the x^3 face field over planes
+// k-3 .. k+2.  In the plain order (x^1 fastest, then x^2, then x^3) the x^3
+// neighbours of a row are n_2 rows apart, more than one XCD's L2 holds, so
+// the x^3 face field is fetched from HBM once per stencil point.  Here the
+// (j, k) rows are walked in strips of C2P_STRIP rows of x^2 with k advancing
+// once per strip: x^3 neighbours are C2P_STRIP rows apart, x^2 neighbours
+// inside a strip 1-3 rows apart, and only the strip edges re-read x^2 rows.
+// A bijection on the interior zones (the last strip may be narrower).
+constexpr int C2P_STRIP = 32;
+
+__device__ __forceinline__ long c2p_zone_order(const Geom& G, long t) {
+  const long n0 = G.n[0];
+  const long r = t / n0;                        // logical row
+  const int i = (int)(t - r * n0);
+  const long per = (long)C2P_STRIP * G.n[2];    // rows in a full strip
+  const int st = (int)(r / per);
+  const int w = (int)(r - st * per);
+  const int h = min(C2P_STRIP, G.n[1] - st * C2P_STRIP);
+  const int k = w / h;
+  const int j = st * C2P_STRIP + (w - k * h);
+  return i + n0 * (j + (long)G.n[1] * k);
+}
+
+// Occupancy of the inversion: on the flat metric its registers fit 96 VGPRs
+// without spills, which gives 5 wavefronts per SIMD instead of 4 (the Newton
+// iteration is a dependent chain, so more wavefronts hide more latency); the
+// tabulated metric needs 138 and is left to the compiler.
+template <class MET>
+constexpr int C2P_MIN_WAVES = MET::flat ? 5 : 1;
+
 // With list != nullptr (learned guess) zones whose warm start has a relative
 // residual above cp.defer_tol are left untouched and appended to list (their
 // order is irrelevant: each is inverted on its own in the learned-guess pass).
 template <class MET>
-__global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __restrict__ prim,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C2P_MIN_WAVES<MET>))) void k_c2p(Geom G, C2PParams cp, double* __restrict__ prim,
                                              double* __restrict__ cons,
                                              const double* __restrict__ tab,
                                              long long* __restrict__ partials,
@@ -293,12 +324,13 @@ __global__ __launch_bounds__(256) void k_c2p(Geom G, C2PParams cp, double* __res
   long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double cfl_v = 0.0;
   if (t < (long)G.n[0] * G.n[1] * G.n[2]) {
+    const long z = c2p_zone_order(G, t);
     const double defer = list ? cp.defer_tol : 0.0;
     double yl = -1.0;
-    if (c2p_zone<MET>(G, cp, prim, cons, tab, t, -1.0, defer, cfl_partials != nullptr, st, cfl_v, -1.0,
+    if (c2p_zone<MET>(G, cp, prim, cons, tab, z, -1.0, defer, cfl_partials != nullptr, st, cfl_v, -1.0,
                       &yl)) {
       const int pos = atomicAdd(list_n, 1);
-      list[pos] = (int)t;
+      list[pos] = (int)z;
       if (list_y) list_y[pos] = yl;
     }
   }
