@@ -290,7 +290,7 @@ struct TabMet {
 template <typename T>
 struct PState {
   T rho, p, u[3], B[3];
-  T W, v[3], vl[3], v2, Bl[3], B2, vB, E2, h, y, D, S[3], Su[3], tau;
+  T W, v[3], vl[3], v2, Bl[3], B2, vB, E2, rhoh, y, D, S[3], Su[3], tau;
 };
 
 // Derived quantities of a primitive state (3+1 GRMHD, ideal gas).
@@ -299,16 +299,19 @@ GR_HD void make_state(PState<T>& s, const M& m, T gam) {
   T ul[3];
   m.lower(s.u, ul);
   const T uu = ul[0] * s.u[0] + ul[1] * s.u[1] + ul[2] * s.u[2];
-  s.W = sqrt(T(1) + uu);
-  const T iw = T(1) / s.W;
+  const T w2 = T(1) + uu;   // W^2
+  const T iw = rsqrt(w2);   // 1/W: one reciprocal square root, no division
+  s.W = w2 * iw;
   for (int i = 0; i < 3; ++i) { s.v[i] = s.u[i] * iw; s.vl[i] = ul[i] * iw; }
   s.v2 = uu * (iw * iw);   // u^2 / W^2
   m.lower(s.B, s.Bl);
   s.B2 = s.Bl[0] * s.B[0] + s.Bl[1] * s.B[1] + s.Bl[2] * s.B[2];
   s.vB = s.vl[0] * s.B[0] + s.vl[1] * s.B[1] + s.vl[2] * s.B[2];
   s.E2 = s.B2 * s.v2 - s.vB * s.vB;
-  s.h = T(1) + (gam * s.p) / ((gam - T(1)) * s.rho);
-  s.y = s.rho * s.h * s.W * s.W;
+  // rho h = rho + Gamma p / (Gamma - 1): the ratio Gamma / (Gamma - 1) is the
+  // same for every state of a call, so no per-state division
+  s.rhoh = s.rho + gam / (gam - T(1)) * s.p;
+  s.y = s.rhoh * w2;
   s.D = s.rho * s.W;
   const T yb = s.y + s.B2;
   for (int i = 0; i < 3; ++i) {
@@ -350,17 +353,20 @@ GR_HD void flux_of(const PState<T>& s, const M& m, int d, T f[5]) {
 // Fast magnetosonic speed estimate lambda^+-_d.
 template <typename T, class M>
 GR_HD void speeds_of(const PState<T>& s, const M& m, int d, T gam, T& lp, T& lm) {
-  const T rhoh = s.rho * s.h;
-  const T cs2 = gam * s.p / rhoh;
+  // a^2 = c_s^2 + v_A^2 - c_s^2 v_A^2 with c_s^2 = Gamma p / (rho h) and
+  // v_A^2 = b^2 / (rho h + b^2) is exactly (Gamma p + b^2) / (rho h + b^2),
+  // and 1 - a^2 = (rho h - Gamma p) / (rho h + b^2): one division for both
+  const T gp = gam * s.p;
   const T bb = s.B2 * (T(1) - s.v2) + s.vB * s.vB;   // b^2 = B^2/W^2 + (v.B)^2
-  const T va2 = bb / (rhoh + bb);
-  const T a2 = cs2 + va2 - cs2 * va2;
+  const T ib = T(1) / (s.rhoh + bb);
+  const T a2 = (gp + bb) * ib;
+  const T one_a2 = (s.rhoh - gp) * ib;
   const T vd = s.v[d];
   const T den = T(1) - s.v2 * a2;
-  T rad = a2 * (T(1) - s.v2) * (m.guu(d) * den - vd * vd * (T(1) - a2));
+  T rad = a2 * (T(1) - s.v2) * (m.guu(d) * den - vd * vd * one_a2);
   rad = sqrt(fmax(rad, T(0)));
   const T fac = m.alpha() / den;
-  const T base = vd * (T(1) - a2);
+  const T base = vd * one_a2;
   if (M::flat) {
     lp = fac * (base + rad);
     lm = fac * (base - rad);

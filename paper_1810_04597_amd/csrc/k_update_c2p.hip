@@ -938,7 +938,7 @@ __global__ __launch_bounds__(256) void k_mri(Geom G, const double* __restrict__ 
     const double b2c = st.B[1] / st.W + bt * m.tvel(st.v[1], 1);
     const double b3c = st.B[2] / st.W + bt * m.tvel(st.v[2], 2);
     const double bsq = st.B2 / (st.W * st.W) + st.vB * st.vB;
-    const double den = fabs(m.tvel(st.v[2], 2)) * sqrt(st.rho * st.h + bsq);
+    const double den = fabs(m.tvel(st.v[2], 2)) * sqrt(st.rhoh + bsq);
     const double qq2 = 2.0 * M_PI * fabs(b2c) / (den * G.dx[1]);
     const double qq3 = 2.0 * M_PI * fabs(b3c) / (den * G.dx[2]);
     const double w = st.rho * m.sqrtg();

@@ -37,6 +37,10 @@ inline bool operator<=(Cnt a, Cnt b) { g_ops.cmp++; return a.v <= b.v; }
 inline bool operator>=(Cnt a, Cnt b) { g_ops.cmp++; return a.v >= b.v; }
 inline bool operator==(Cnt a, Cnt b) { g_ops.cmp++; return a.v == b.v; }
 inline Cnt sqrt(Cnt a) { g_ops.sqrt++; return Cnt(std::sqrt(a.v)); }
+// reciprocal square root: one square root and one division in the count
+inline Cnt rsqrt(Cnt a) { g_ops.sqrt++; g_ops.div++; return Cnt(1.0 / std::sqrt(a.v)); }
+// plain double (states built without counting): the host has no rsqrt
+inline double rsqrt(double a) { return 1.0 / std::sqrt(a); }
 inline Cnt fmin(Cnt a, Cnt b) { g_ops.minmax++; return Cnt(std::fmin(a.v, b.v)); }
 inline Cnt fmax(Cnt a, Cnt b) { g_ops.minmax++; return Cnt(std::fmax(a.v, b.v)); }
 inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v)); }
