@@ -73,6 +73,33 @@ __device__ __forceinline__ void sources_of(const PState<double>& s, const MET& m
   src[4] = m.sg * t;
 }
 
+// ------------------------------------------------------------------ zone order
+// Zone order of the one-thread-per-zone kernels that read x^3 stencils (the
+// update on a tabulated metric reads F^3, E_1 and E_2 over planes k-3 .. k+2;
+// the inversion's centred field reads the x^3 face field there).  In the
+// plain order (x^1 fastest, then x^2, then x^3) the x^3 neighbours of a row
+// are n_2 rows apart, more than one XCD's L2 holds, so those fields are
+// fetched from HBM once per stencil point.  Here the (j, k) rows are walked
+// in strips of S rows of x^2 with k advancing once per strip: x^3 neighbours
+// are S rows apart, x^2 neighbours inside a strip 1-3 rows apart, and only
+// the strip edges re-read x^2 rows.  A bijection on the interior zones (the
+// last strip may be narrower).
+template <int S>
+__device__ __forceinline__ long strip_zone_order(const Geom& G, long t) {
+  const long n0 = G.n[0];
+  const long r = t / n0;                        // logical row
+  const int i = (int)(t - r * n0);
+  const long per = (long)S * G.n[2];            // rows in a full strip
+  const int st = (int)(r / per);
+  const int w = (int)(r - st * per);
+  const int h = min(S, G.n[1] - st * S);
+  const int k = w / h;
+  const int j = st * S + (w - k * h);
+  return i + n0 * (j + (long)G.n[1] * k);
+}
+constexpr int UPDATE_STRIP = 16;
+constexpr int C2P_STRIP = 32;
+
 // ------------------------------------------------------------------ RK update
 // RK stage store over two distinct buffers x and y (SSP-RK3, Shu-Osher form,
 // U^(s+1) = a U^n + b (U^(s) + dt L)), so that U^n is never copied:
@@ -117,7 +144,7 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
   const long t = flat_thread();
   if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
   int i, j, k;
-  zone_of(G, t, i, j, k);
+  zone_of(G, strip_zone_order<UPDATE_STRIP>(G, t), i, j, k);
   const long c = G.idx(i, j, k);
   double src[5] = {0, 0, 0, 0, 0};
   if constexpr (!MET::flat) {
@@ -278,30 +305,6 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
 }
 
 // ------------------------------------------------------------------ inversion
-// Zone order of the inversion.  The centred field of a zone reads the x^2
-// face field over rows j-3 .. j+2 and the x^3 face field over planes
-// k-3 .. k+2.  In the plain order (x^1 fastest, then x^2, then x^3) the x^3
-// neighbours of a row are n_2 rows apart, more than one XCD's L2 holds, so
-// the x^3 face field is fetched from HBM once per stencil point.  Here the
-// (j, k) rows are walked in strips of C2P_STRIP rows of x^2 with k advancing
-// once per strip: x^3 neighbours are C2P_STRIP rows apart, x^2 neighbours
-// inside a strip 1-3 rows apart, and only the strip edges re-read x^2 rows.
-// A bijection on the interior zones (the last strip may be narrower).
-constexpr int C2P_STRIP = 32;
-
-__device__ __forceinline__ long c2p_zone_order(const Geom& G, long t) {
-  const long n0 = G.n[0];
-  const long r = t / n0;                        // logical row
-  const int i = (int)(t - r * n0);
-  const long per = (long)C2P_STRIP * G.n[2];    // rows in a full strip
-  const int st = (int)(r / per);
-  const int w = (int)(r - st * per);
-  const int h = min(C2P_STRIP, G.n[1] - st * C2P_STRIP);
-  const int k = w / h;
-  const int j = st * C2P_STRIP + (w - k * h);
-  return i + n0 * (j + (long)G.n[1] * k);
-}
-
 // Occupancy of the inversion: on the flat metric its registers fit 96 VGPRs
 // without spills, which gives 5 wavefronts per SIMD instead of 4 (the Newton
 // iteration is a dependent chain, so more wavefronts hide more latency); the
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C2P_MIN_WAV
   long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double cfl_v = 0.0;
   if (t < (long)G.n[0] * G.n[1] * G.n[2]) {
-    const long z = c2p_zone_order(G, t);
+    const long z = strip_zone_order<C2P_STRIP>(G, t);
     const double defer = list ? cp.defer_tol : 0.0;
     double yl = -1.0;
     if (c2p_zone<MET>(G, cp, prim, cons, tab, z, -1.0, defer, cfl_partials != nullptr, st, cfl_v, -1.0,
