@@ -586,7 +586,8 @@ def main():
         src = torch.ones(CALIB_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        for _ in range(3):
+            dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
     zones = n ** 3
