@@ -388,25 +388,33 @@ GR_HD T hll(T fl, T fr, T ul, T ur, T ap, T am, T inv_s, bool tiny) {
 
 // ------------------------------------------------------------------ per-face body
 constexpr double POS_FRAC = 0.1;
-// q[v][s]: six cells f-2 .. f+3 of the reconstructed variables in the order
-// rho, p, u^1, u^2, u^3, B^{d+1}, B^{d+2}; bn: normal B at the face.
-template <int DIR, int RC = RECON_MP5, typename T, class M>
-GR_HD void face_body(const T q[7][6], T bn, bool axis, const M& m, T gam, T fh[5], T ctd[6]) {
+// qs(v, s): cell f-2+s (s = 0..5) of reconstructed variable v (rho, p, u^1,
+// u^2, u^3, B^{d+1}, B^{d+2}), read when its reconstruction needs it (a
+// caller staging the cells in LDS then holds one variable's six cells in
+// registers at a time instead of all 42).
+template <int DIR, int RC = RECON_MP5, typename T, class M, class QS>
+GR_HD void face_body_q(const QS& qs, T bn, bool axis, const M& m, T gam, T fh[5], T ctd[6]) {
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
   PState<T> sl, sr;
+  auto rec = [&](int v, T& l, T& r) {
+    T c[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) c[s] = qs(v, s);
+    recon_lr<RC>(c, l, r);
+  };
   // rho and p states are kept at or above POS_FRAC times the cell value on
   // their side of the face (a continuous positivity bound)
-  recon_lr<RC>(q[0], sl.rho, sr.rho);
-  sl.rho = fmax(sl.rho, T(POS_FRAC) * q[0][2]);
-  sr.rho = fmax(sr.rho, T(POS_FRAC) * q[0][3]);
-  recon_lr<RC>(q[1], sl.p, sr.p);
-  sl.p = fmax(sl.p, T(POS_FRAC) * q[1][2]);
-  sr.p = fmax(sr.p, T(POS_FRAC) * q[1][3]);
-  recon_lr<RC>(q[2], sl.u[0], sr.u[0]);
-  recon_lr<RC>(q[3], sl.u[1], sr.u[1]);
-  recon_lr<RC>(q[4], sl.u[2], sr.u[2]);
-  recon_lr<RC>(q[5], sl.B[T1], sr.B[T1]);
-  recon_lr<RC>(q[6], sl.B[T2], sr.B[T2]);
+  rec(0, sl.rho, sr.rho);
+  sl.rho = fmax(sl.rho, T(POS_FRAC) * qs(0, 2));
+  sr.rho = fmax(sr.rho, T(POS_FRAC) * qs(0, 3));
+  rec(1, sl.p, sr.p);
+  sl.p = fmax(sl.p, T(POS_FRAC) * qs(1, 2));
+  sr.p = fmax(sr.p, T(POS_FRAC) * qs(1, 3));
+  rec(2, sl.u[0], sr.u[0]);
+  rec(3, sl.u[1], sr.u[1]);
+  rec(4, sl.u[2], sr.u[2]);
+  rec(5, sl.B[T1], sr.B[T1]);
+  rec(6, sl.B[T2], sr.B[T2]);
   sl.B[DIR] = bn;
   sr.B[DIR] = bn;
   make_state(sl, m, gam);
@@ -436,20 +444,35 @@ GR_HD void face_body(const T q[7][6], T bn, bool axis, const M& m, T gam, T fh[5
   ctd[5] = am;
 }
 
+// q[v][s]: six cells f-2 .. f+3 of the reconstructed variables in the order
+// rho, p, u^1, u^2, u^3, B^{d+1}, B^{d+2}; bn: normal B at the face.
+template <int DIR, int RC = RECON_MP5, typename T, class M>
+GR_HD void face_body(const T q[7][6], T bn, bool axis, const M& m, T gam, T fh[5], T ctd[6]) {
+  face_body_q<DIR, RC>([&](int v, int s) { return q[v][s]; }, bn, axis, m, gam, fh, ctd);
+}
+
 // ------------------------------------------------------------------ per-edge body
 // Edge field of family E (d = E+1, c = E+2 mod 3).  qd[v][s]: six d-faces
 // along c of v^d_L, v^d_R, v^c_L, v^c_R, B^d; qc[s]: six c-faces along d of
 // B^c; a*: speeds of the two adjacent faces of each family.
-template <int E, int RC = RECON_MP5, typename T, class M>
-GR_HD T edge_body(const T qd[5][6], const T qc[6], T apd0, T apd1, T amd0, T amd1,
-                  T apc0, T apc1, T amc0, T amc1, const M& m) {
+// qds(v, s) returns qd[v][s], read when its reconstruction needs it (for a
+// caller that stages qd in LDS: one variable's cells in registers at a time).
+template <int E, int RC = RECON_MP5, typename T, class M, class QD>
+GR_HD T edge_body_q(const QD& qds, const T qc[6], T apd0, T apd1, T amd0, T amd1,
+                    T apc0, T apc1, T amc0, T amc1, const M& m) {
   constexpr int D = (E + 1) % 3, C = (E + 2) % 3;
   T vd[2][2], vc[2][2], bd[2], bc[2];   // [a][b]
-  recon_lr<RC>(qd[0], vd[0][0], vd[0][1]);
-  recon_lr<RC>(qd[1], vd[1][0], vd[1][1]);
-  recon_lr<RC>(qd[2], vc[0][0], vc[0][1]);
-  recon_lr<RC>(qd[3], vc[1][0], vc[1][1]);
-  recon_lr<RC>(qd[4], bd[0], bd[1]);
+  auto rec = [&](int v, T& l, T& r) {
+    T c[6];
+#pragma unroll
+    for (int s = 0; s < 6; ++s) c[s] = qds(v, s);
+    recon_lr<RC>(c, l, r);
+  };
+  rec(0, vd[0][0], vd[0][1]);
+  rec(1, vd[1][0], vd[1][1]);
+  rec(2, vc[0][0], vc[0][1]);
+  rec(3, vc[1][0], vc[1][1]);
+  rec(4, bd[0], bd[1]);
   recon_lr<RC>(qc, bc[0], bc[1]);
   const T apd = fmax(apd0, apd1), amd = fmax(amd0, amd1);
   const T apc = fmax(apc0, apc1), amc = fmax(amc0, amc1);
@@ -472,6 +495,13 @@ GR_HD T edge_body(const T qd[5][6], const T qc[6], T apd0, T apd1, T amd0, T amd
   }
   ee = ee + kd * (bc[1] - bc[0]) - kc * (bd[1] - bd[0]);
   return ee;
+}
+
+template <int E, int RC = RECON_MP5, typename T, class M>
+GR_HD T edge_body(const T qd[5][6], const T qc[6], T apd0, T apd1, T amd0, T amd1,
+                  T apc0, T apc1, T amc0, T amc1, const M& m) {
+  return edge_body_q<E, RC>([&](int v, int s) { return qd[v][s]; }, qc, apd0, apd1, amd0, amd1, apc0,
+                            apc1, amc0, amc1, m);
 }
 
 // ------------------------------------------------------------------ inversion

@@ -210,11 +210,6 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
     constexpr int loc = DIR == 1 ? LOC_F2 : LOC_C;
     m.load(tab, G.tab_plane, loc, G.tidx(ii[0], ii[1]));
   }
-  T q[7][6];
-#pragma unroll
-  for (int v = 0; v < 7; ++v)
-#pragma unroll
-    for (int s = 0; s < 6; ++s) q[v][s] = sh[v][cy + s][cx];
   const double bface = cons[(long)(C_BF1 + DIR) * G.field + c];
   T bn;
   bool axis = false;
@@ -225,7 +220,7 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
     bn = axis ? T(0) : T(bface) / m.sg;
   }
   T fh[5], cd[6];
-  face_body<DIR, RC>(q, bn, axis, m, gam, fh, cd);
+  face_body_q<DIR, RC>([&](int v, int s) { return sh[v][cy + s][cx]; }, bn, axis, m, gam, fh, cd);
 #pragma unroll
   for (int q5 = 0; q5 < 5; ++q5) flux[(long)q5 * G.field + c] = double(fh[q5]);
 #pragma unroll
@@ -348,11 +343,7 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   if (mt * SX + cx >= M || cc > G.n[C] + 1) return;
   ii[C] = cc;
   const long b = G.idx(ii[0], ii[1], ii[2]);
-  T qd[5][6], qc[6];
-#pragma unroll
-  for (int v = 0; v < 5; ++v)
-#pragma unroll
-    for (int s2 = 0; s2 < 6; ++s2) qd[v][s2] = sh[v][cy + s2][cx];
+  T qc[6];
   {
     const double* bcs = cons + (long)(C_BF1 + C) * G.field;
 #pragma unroll
@@ -363,7 +354,8 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
     constexpr int loc = E == 2 ? LOC_E3 : LOC_F2;
     m.load(tab, G.tab_plane, loc, G.tidx(ii[0], ii[1]));
   }
-  const T ee = edge_body<E, RC>(qd, qc, T(ctd_d[4 * G.field + b]), T(ctd_d[4 * G.field + b + sc]),
+  const T ee = edge_body_q<E, RC>([&](int v, int s2) { return sh[v][cy + s2][cx]; }, qc,
+                                  T(ctd_d[4 * G.field + b]), T(ctd_d[4 * G.field + b + sc]),
                             T(ctd_d[5 * G.field + b]), T(ctd_d[5 * G.field + b + sc]),
                             T(ctd_c[4 * G.field + b]), T(ctd_c[4 * G.field + b + sd]),
                             T(ctd_c[5 * G.field + b]), T(ctd_c[5 * G.field + b + sd]), m);
