@@ -147,6 +147,35 @@ def test_box256_invariants_device_dt():
     assert torch.equal(runs[0], runs[1])
 
 
+@gpu
+def test_box256_graph_replay_equals_eager():
+    """The benchmark's launch configuration at 256^3: a grid on its own
+    stream replaying the captured device-dt step equals a grid stepped
+    launch by launch, bit for bit (state, primitives including ghosts, time
+    and dt), over two steps; the eager path is the one checked against the
+    oracle above."""
+    torch = _torch()
+    from workloads import box
+    from paper_1810_04597_amd.grid import Grid
+    g, d = box.turbulent_box(256)
+    E = Grid(g)
+    R = Grid(g, stream=torch.cuda.Stream())
+    for G in (E, R):
+        G.curl_potential(d)
+        G.set_primitives(d)
+    for _ in range(2):
+        E.rk_step()
+    R.rk_steps_graph(2)
+    E.synchronize()
+    R.synchronize()
+    assert torch.equal(E.cons, R.cons)
+    assert torch.equal(E.prim, R.prim)
+    de, dr = E.diagnostics(), R.diagnostics()
+    assert de["t"] == dr["t"] and de["dt"] == dr["dt"] and de["step"] == dr["step"] == 2
+    E.close()
+    R.close()
+
+
 def _torus_window_case(n, origins, guess_trained=False):
     from workloads.torus import torus
     from workloads.metric import kerr_schild_tables
