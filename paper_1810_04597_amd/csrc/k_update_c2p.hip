@@ -37,38 +37,44 @@ __device__ __forceinline__ void sources_of(const PState<double>& s, const MET& m
   eu[1] = m.e_up(-(s.vl[2] * s.Bl[0] - s.vl[0] * s.Bl[2]));
   eu[2] = m.e_up(-(s.vl[0] * s.Bl[1] - s.vl[1] * s.Bl[0]));
   const double ptot = s.p + 0.5 * (s.E2 + s.B2);
-  const double gu[3][3] = {{m.u11, m.u12, m.u13}, {m.u12, m.u22, m.u23}, {m.u13, m.u23, m.u33}};
-  double wup[3][3], wmix[3][3];
+  // W^jk and d_i gamma_jk are symmetric: the sum over j, k is the sum over
+  // j <= k with the off-diagonal terms doubled.  Each term is formed and
+  // consumed at once (no 3x3 arrays held), which keeps the register count of
+  // the update low.  a_i = sum_jk W^jk d_i gamma_jk for i = 1, 2.
+  constexpr int JJ[6] = {0, 0, 0, 1, 1, 2}, KK[6] = {0, 1, 2, 1, 2, 2};   // 11,12,13,22,23,33
+  const double gu[6] = {m.u11, m.u12, m.u13, m.u22, m.u23, m.u33};
+  double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-  for (int j = 0; j < 3; ++j)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      wup[j][k] = s.y * s.v[j] * s.v[k] - eu[j] * eu[k] - s.B[j] * s.B[k] + ptot * gu[j][k];
-      wmix[j][k] = s.y * s.v[j] * s.vl[k] - eu[j] * el[k] - s.B[j] * s.Bl[k] + (j == k ? ptot : 0.0);
-    }
-  // derivative of gamma_jk in direction i (0 or 1)
-  auto dg = [&](int i, int j, int k) {
-    const int a = j < k ? j : k, b = j < k ? k : j;
-    const int sym = a == 0 ? b : (a == 1 ? 2 + b : 5);   // 11,12,13,22,23,33 -> 0..5
-    return der((i == 0 ? D1_G11 : D2_G11) + sym);
-  };
+  for (int q = 0; q < 6; ++q) {
+    const int j = JJ[q], k = KK[q];
+    double w = s.y * s.v[j] * s.v[k] - eu[j] * eu[k] - s.B[j] * s.B[k] + ptot * gu[q];
+    if (j != k) w = 2.0 * w;
+    a0 = a0 + w * der(D1_G11 + q);
+    a1 = a1 + w * der(D2_G11 + q);
+  }
   const double utot = s.tau + s.D;
   src[0] = 0.0 * m.sg;
-  for (int i = 0; i < 2; ++i) {
-    double t = 0.0;
-    for (int j = 0; j < 3; ++j)
-      for (int k = 0; k < 3; ++k) t = t + 0.5 * m.al * wup[j][k] * dg(i, j, k);
-    for (int j = 0; j < 3; ++j) t = t + s.S[j] * der((i == 0 ? D1_B1 : D2_B1) + j);
-    t = t - utot * der(i == 0 ? D1_AL : D2_AL);
-    src[1 + i] = m.sg * t;
-  }
   src[3] = 0.0 * m.sg;
-  double t = 0.0;
-  for (int l = 0; l < 2; ++l)
-    for (int j = 0; j < 3; ++j)
-      for (int k = 0; k < 3; ++k) t = t + 0.5 * wup[j][k] * m.b[l] * dg(l, j, k);
+  {
+    double t1 = 0.5 * m.al * a0, t2 = 0.5 * m.al * a1;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      t1 = t1 + s.S[j] * der(D1_B1 + j);
+      t2 = t2 + s.S[j] * der(D2_B1 + j);
+    }
+    src[1] = m.sg * (t1 - utot * der(D1_AL));
+    src[2] = m.sg * (t2 - utot * der(D2_AL));
+  }
+  // energy: W^jk beta^l d_l gamma_jk / 2 + W^j_k d_j beta^k - S^j d_j alpha (l, j over the
+  // two axisymmetric directions)
+  double t = 0.5 * (m.b[0] * a0 + m.b[1] * a1);
+#pragma unroll
   for (int j = 0; j < 2; ++j)
-    for (int k = 0; k < 3; ++k) t = t + wmix[j][k] * der((j == 0 ? D1_B1 : D2_B1) + k);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double wm = s.y * s.v[j] * s.vl[k] - eu[j] * el[k] - s.B[j] * s.Bl[k] + (j == k ? ptot : 0.0);
+      t = t + wm * der((j == 0 ? D1_B1 : D2_B1) + k);
+    }
   for (int j = 0; j < 2; ++j) t = t - s.Su[j] * der(j == 0 ? D1_AL : D2_AL);
   src[4] = m.sg * t;
 }
