@@ -42,7 +42,7 @@ int hip_check(const char* what) {
 long round_up(long v, long m) { return (v + m - 1) / m * m; }
 
 // scratch carve (in fields of the single-field layout)
-constexpr int SCR_CONS_N = 0;    // 8 fields
+constexpr int SCR_STAGE = 0;     // 8 fields: U^(1), U^(2) of the RK stages
 constexpr int SCR_FLUX = 8;      // 3 x 5 fields
 constexpr int SCR_CTD = 23;      // 3 x 6 fields
 constexpr int SCR_EDGE = 41;     // 3 fields
@@ -101,7 +101,7 @@ struct grmhd_grid {
     (void)hipEventRecord(b, stream);
     pending.push_back({cls, a, b});
   }
-  double* cons_n() const { return scratch + (long)SCR_CONS_N * G.field; }
+  double* stage_state() const { return scratch + (long)SCR_STAGE * G.field; }
   double* flux() const { return scratch + (long)SCR_FLUX * G.field; }
   double* ctd() const { return scratch + (long)SCR_CTD * G.field; }
   double* edges() const { return scratch + (long)SCR_EDGE * G.field; }
@@ -412,7 +412,7 @@ int grmhd_rhs(grmhd_grid* h, double* rhs_out) {
   if (!rhs_out) return fail(GRMHD_EINVAL, "rhs_out is NULL");
   rhs_pieces(h);
   h->timed(13, [&] {
-    launch_update(h->G, h->flat, 1, h->prim, h->cons, h->cons_n(), h->flux(), h->edges(), h->tab,
+    launch_update(h->G, h->flat, 1, h->prim, h->cons, h->stage_state(), h->flux(), h->edges(), h->tab,
                   0.0, 0.0, 0.0, h->d_dt, rhs_out, 1, h->stream);
   });
   return hip_check("rhs");
@@ -435,7 +435,7 @@ static void step_stages(grmhd_grid* h, double dt) {
   // stage buffers: U^n stays in the bound cons until the last stage writes
   // U^(3) over it; U^(1) and U^(2) live in the scratch buffer S (no copy of U^n)
   double* const Un = h->cons;
-  double* const S = h->cons_n();
+  double* const S = h->stage_state();
   for (int s = 0; s < 3; ++s) {
     double* const cur = s == 0 ? Un : S;        // state the stage's RHS reads
     double* const next = s == 2 ? Un : S;       // state the stage produces
