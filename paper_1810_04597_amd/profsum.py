@@ -5,7 +5,11 @@
     rocprofv3 --pmc SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 \
         SQ_INSTS_VALU_TRANS_F64 SQ_INSTS_VALU --output-format csv -d <dir_v> -o run -- \
         python -u bench.py --steps 1 --warmup 1 --no-cpu-baseline --eager
-    python -m paper_1810_04597_amd.profsum --ktrace <dir_t> --valu <dir_v> \
+    rocprofv3 --pmc SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY \
+        SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VMEM SQ_LDS_BANK_CONFLICT \
+        --output-format csv -d <dir_s> -o run -- python -u bench.py --steps 1 --warmup 1 \
+        --no-cpu-baseline --eager
+    python -m paper_1810_04597_amd.profsum --ktrace <dir_t> --valu <dir_v> --stall <dir_s> \
         --bench <bench log> --out <file.md> [--n 256]
 
 Per kernel class: calls and average duration (kernel trace), HBM bytes per
@@ -111,6 +115,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--ktrace", required=True)
     ap.add_argument("--valu")
+    ap.add_argument("--stall", help="counter pass with SQ_WAVE_CYCLES, SQ_WAIT_ANY, SQ_WAIT_INST_ANY, "
+                    "SQ_ACTIVE_INST_ANY, SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_LDS, SQ_LDS_BANK_CONFLICT")
     ap.add_argument("--bench", required=True)
     ap.add_argument("--out", required=True)
     ap.add_argument("--n", type=int, default=256)
@@ -195,6 +201,25 @@ def main():
                    "keep the SIMDs %.2f busy over the step" % (
                        f64_step / 1e12, f64_step / (ms * 1e-3) / 1e12,
                        f64_step / (ms * 1e-3) / FP64_PEAK, vt * 4.0 / (SIMDS * CLOCK * ms * 1e-3)))
+    if a.stall:
+        sc = read_counters(a.stall)
+        out.append("\nWave states (SQ counters, fractions of the wave-cycles of each class: "
+                   "SQ_WAIT_ANY, waiting on a dependency or counter; SQ_WAIT_INST_ANY, waiting for "
+                   "an instruction to be issued (arbitration with the other wavefronts of the SIMD, "
+                   "instruction fetch); SQ_ACTIVE_INST_ANY, _VALU, _LDS, issuing; LDS bank "
+                   "conflict cycles):\n")
+        out.append("| kernel | wait (dependency) | wait (issue) | issuing | issuing VALU | issuing LDS "
+                   "| LDS bank conflicts |")
+        out.append("|---|---|---|---|---|---|---|")
+        for c in STAGE_CLASSES:
+            v = sc.get(c, {})
+            w = v.get("SQ_WAVE_CYCLES")
+            if not w:
+                continue
+            out.append("| %s | %.2f | %.2f | %.2f | %.2f | %.3f | %d |" % (
+                c, v["SQ_WAIT_ANY"] / w, v["SQ_WAIT_INST_ANY"] / w, v["SQ_ACTIVE_INST_ANY"] / w,
+                v["SQ_ACTIVE_INST_VALU"] / w, v["SQ_ACTIVE_INST_LDS"] / w,
+                int(v.get("SQ_LDS_BANK_CONFLICT", 0))))
     text = "\n".join(out) + "\n"
     with open(a.out, "w") as f:
         f.write(text)
