@@ -76,10 +76,21 @@ def cpu_baseline(seconds_target=12.0):
             break
     wall = time.perf_counter() - w0
     cpu = time.process_time() - c0
+    cores = max(1, int(round(cpu / wall)))
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": n ** 3 * steps / wall, "unit": "zone-updates/s",
-            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": "FP64 NumPy oracle, 32^3 turbulent SRMHD box (same seeded generator), "
-                      "%d SSP-RK3 steps, %.1f s wall" % (steps, wall)}
+                      "%d SSP-RK3 steps, %.1f s wall; %d core used of %d on %s" % (
+                          steps, wall, cores, os.cpu_count() or 0, model)}
 
 
 def precision_report(args):
