@@ -523,7 +523,7 @@ def main():
                     help="torus-long: density above which a zone counts as torus body")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (a single grid block per device); "
+        print("bench.py: the solver runs one grid block on one GPU (no domain decomposition across GPUs); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     rank = int(os.environ.get("RANK", "0"))

@@ -54,7 +54,7 @@ enum {
   GRMHD_EHIP = -3,         /* HIP runtime error (message says which)        */
   GRMHD_ESTATE = -4,       /* call order: fields or metric not set          */
   GRMHD_ENOCONV = -5,      /* strict inversion requested and a zone failed  */
-  GRMHD_EUNSUPPORTED = -6  /* valid request this build does not provide     */
+  GRMHD_EUNSUPPORTED = -6  /* valid request the library does not provide     */
 };
 
 enum { GRMHD_CART = 0, GRMHD_LOGSPH = 1 };          /* (x,y,z) | (ln r, theta, phi) */
