@@ -92,20 +92,23 @@ __device__ __forceinline__ long flat_thread() {
 GR_HD int sign_word(double a) { return (int)(__builtin_bit_cast(unsigned long long, a) >> 32); }
 GR_HD int sign_word(float a) { return __builtin_bit_cast(int, a); }
 
-// minmod(a, b) = (sgn a + sgn b)/2 min(|a|, |b|): zero unless the sign bits
-// agree, else the argument nearer zero.
+// minmod(a, b) = (sgn a + sgn b)/2 min(|a|, |b|): zero unless a and b have
+// the same sign, else the argument nearer zero.  Written as
+// max(min(a, b), 0) + min(max(a, b), 0): one of the two terms is always zero,
+// so the sum is exact, and it takes four min/max and an add instead of
+// compares, sign-bit logic and selects (the result can differ only in the
+// sign of a zero).
 template <typename T>
 GR_HD T minmod(T a, T b) {
-  const T m = fabs(a) < fabs(b) ? a : b;
-  return (sign_word(a) ^ sign_word(b)) >= 0 ? m : T(0);
+  return fmax(fmin(a, b), T(0)) + fmin(fmax(a, b), T(0));
 }
 
-// Four-argument minmod: min |.| with the common sign, zero without one.
+// Four-argument minmod: min |.| with the common sign, zero without one; the
+// same construction on the smallest and largest argument.
 template <typename T>
 GR_HD T minmod4(T w, T x, T y, T z) {
-  const int sw = sign_word(w), sx = sign_word(x), sy = sign_word(y), sz = sign_word(z);
-  const T m = fmin(fmin(fabs(w), fabs(x)), fmin(fabs(y), fabs(z)));
-  return (sw | sx | sy | sz) >= 0 ? m : ((sw & sx & sy & sz) < 0 ? -m : T(0));
+  const T lo = fmin(fmin(w, x), fmin(y, z)), hi = fmax(fmax(w, x), fmax(y, z));
+  return fmax(lo, T(0)) + fmin(hi, T(0));
 }
 
 // Limited left state at the face between q0 and qp1 from q_{j-2..j+2}.
