@@ -111,7 +111,7 @@ def copy_rate(dir_t):
     return best
 
 
-def main():
+def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--ktrace", required=True)
     ap.add_argument("--valu")
@@ -121,10 +121,12 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
+    ap.add_argument("--traffic", default=os.path.join(HERE, "traffic.json"),
+                    help="per-launch HBM bytes written by paper_1810_04597_amd.traffic")
     ap.add_argument("--title", default="FP64 SSP-RK3 step, turbulent SRMHD box 256^3 (MI355X)")
     ap.add_argument("--commands", default="", help="text block: the commands that made the inputs")
-    a = ap.parse_args()
-    traffic = json.load(open(os.path.join(HERE, "traffic.json")))
+    a = ap.parse_args(argv)
+    traffic = json.load(open(a.traffic))
     ops = json.load(open(os.path.join(HERE, "opcounts.json")))
     bench = [json.loads(l) for l in open(a.bench) if l.startswith("{")][-1]
     valu = read_counters(a.valu) if a.valu else {}

@@ -55,7 +55,9 @@ def _read(d, counter):
     return out
 
 
-def main(dir_f, dir_w, copy_bytes=1 << 30):
+def compute(dir_f, dir_w, copy_bytes=1 << 30):
+    """Per-class HBM bytes per launch (the largest-grid launches of each
+    class), scaled by the calibration copy's counter readings."""
     fetch = _read(dir_f, "FETCH_SIZE")
     write = _read(dir_w, "WRITE_SIZE")
     known_kib = copy_bytes / 1024.0
@@ -71,7 +73,12 @@ def main(dir_f, dir_w, copy_bytes=1 << 30):
         fb = sum(fv) / len(fv) * cf * 1024
         wb = sum(wv) / len(wv) * cw * 1024
         res["kernels"][cls] = {"fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb}
-    with open(os.path.join(HERE, "traffic.json"), "w") as f:
+    return res
+
+
+def main(dir_f, dir_w, copy_bytes=1 << 30, out=None):
+    res = compute(dir_f, dir_w, copy_bytes)
+    with open(out or os.path.join(HERE, "traffic.json"), "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
 
