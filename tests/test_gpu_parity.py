@@ -125,6 +125,28 @@ def test_ten_steps_config0_parity():
 
 
 @gpu
+def test_ten_steps_64_parity():
+    """The 256^3 benchmark's generator at 64^3 (several tiles of every kernel
+    in every direction, four x^3 segments of the update), 10 SSP-RK3 steps with
+    the device CFL step: every zone and field within 1e-10 relative of the
+    oracle, div B at round-off, no failed inversion."""
+    _torch()
+    g, d, s, G = _pair_box(64)
+    for _ in range(10):
+        dt_o = s.cfl_dt()
+        dt_g = G.rk_step(0.0, want_dt=True)
+        assert abs(dt_g / dt_o - 1) < 1e-11
+        s.rk_step(dt_o)
+    P, U = _oracle_fields(s)
+    e = max_rel(G.to_numpy("prim", interior=True), P, PRIM)
+    e.update(max_rel(G.to_numpy("cons", interior=True), U, CONS))
+    assert max(e.values()) < 1e-10, e
+    dg = G.diagnostics()
+    assert dg["max_divb"] <= 1e-12 and dg["n_c2p_fail"] == 0
+    G.close()
+
+
+@gpu
 @pytest.mark.parametrize("shape", [(37, 21, 27), (70, 10, 18)])
 def test_ten_steps_ragged_box_parity(shape):
     """Non-cubic periodic boxes whose sizes are not multiples of the kernels'
