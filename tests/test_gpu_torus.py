@@ -121,6 +121,10 @@ def test_torus_ten_steps_within_oracle_envelope(n, fixed_dt):
         report[k] = (q / scale, env / scale, float(np.max(diff[body]) / scale))
         assert q <= 10.0 * env + 1e-10 * scale, (k, report[k])
         assert np.max(diff[body]) < 1e-2 * scale, (k, report[k])
+        if fixed_dt is None:
+            # at the CFL step this grid stays well conditioned: the FP64 bar
+            # holds at every zone
+            assert np.max(diff) < 1e-10 * scale, (k, float(np.max(diff) / scale))
     print("torus envelope report (gpu q99, oracle q99, body max):", report)
     assert G.diagnostics()["n_nonfinite"] == 0
 
