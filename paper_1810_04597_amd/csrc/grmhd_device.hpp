@@ -576,15 +576,17 @@ GR_HD NewtonOut<T> newton(T dd, const T S[3], T tau, const T B[3], const MET& m,
         return o;
       }
       ++it;
-      // three reciprocals per iteration (1/y, 1/(y + B^2), 1/sqrt(1 - v^2));
+      // two reciprocals and a reciprocal square root per iteration (1/y,
+      // 1/(y + B^2), 1/sqrt(1 - v^2), with sqrt(1 - v^2) = (1 - v^2) / sqrt(1 - v^2));
       // the expressions are those of the residual and its derivative
       const T iy = 1.0 / y, iy2 = iy * iy;
       const T yb = y + b2, iyb = 1.0 / yb, iyb2 = iyb * iyb;
       const T num = s2 + sb2 * (2.0 * y + b2) * iy2;
       const T v2 = num * iyb2;
       const bool bad = v2 >= 1.0;
-      const T sq = sqrt(1.0 - v2);
-      const T isq = 1.0 / sq;
+      const T omv = 1.0 - v2;
+      const T isq = rsqrt(omv);
+      const T sq = omv * isq;
       const T p = gf * (y * (1.0 - v2) - dd * sq);
       const T f = y - p + 0.5 * b2 * (1.0 + v2) - 0.5 * sb2 * iy2 - utot;
       const T dv2 = -2.0 * iyb * (sb2 * iy2 * iy + num * iyb2);
@@ -607,12 +609,19 @@ GR_HD NewtonOut<T> newton(T dd, const T S[3], T tau, const T B[3], const MET& m,
       if (fabs(dy) <= tol * y) { conv = true; break; }
     }
   }
-  const T v2 = (s2 + sb2 * (2.0 * y + b2) / (y * y)) / ((y + b2) * (y + b2));
-  const T w = 1.0 / sqrt(1.0 - v2);
-  o.p = gf * (y * (1.0 - v2) - dd * sqrt(1.0 - v2));
-  o.rho = dd / w;
+  // primitives at the root: W = 1/sqrt(1 - v^2), rho = D/W, p from the
+  // equation of state, v_i = (S_i + (S.B) B_i / y) / (y + B^2); two
+  // reciprocals and a reciprocal square root
+  const T iy = 1.0 / y, iyb = 1.0 / (y + b2);
+  const T v2 = (s2 + sb2 * (2.0 * y + b2) * (iy * iy)) * (iyb * iyb);
+  const T omv = 1.0 - v2;
+  const T w = rsqrt(omv);
+  const T sq = omv * w;                         // sqrt(1 - v^2) = 1/W
+  o.p = gf * (y * omv - dd * sq);
+  o.rho = dd * sq;
   T vl[3], vu[3];
-  for (int q = 0; q < 3; ++q) vl[q] = (S[q] + (sb / y) * bl[q]) / (y + b2);
+  const T sby = sb * iy;
+  for (int q = 0; q < 3; ++q) vl[q] = (S[q] + sby * bl[q]) * iyb;
   m.raise(vl, vu);
   for (int q = 0; q < 3; ++q) o.u[q] = w * vu[q];
   o.ok = conv && valid && (v2 < 1.0) && isfinite(o.rho) && isfinite(o.p) && isfinite(o.u[0]) &&
