@@ -20,7 +20,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 
 def algorithmic_units():
-    """Per-unit algorithmic figures of each kernel class:
+    """Per-unit algorithmic figures of each kernel class (opcounts.json):
     FP64 flops per face/edge/zone counted from the kernel arithmetic, and the
     compulsory HBM bytes per element."""
     path = os.path.join(ROOT, "paper_1810_04597_amd", "opcounts.json")
