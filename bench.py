@@ -33,6 +33,14 @@ def algorithmic_units():
 def measured_traffic(kernel):
     """HBM bytes per launch from the counter passes, or None when the kernel
     sources changed since they were taken."""
+    t = _traffic_table()
+    if t is None:
+        return None
+    k = t["kernels"].get(kernel)
+    return None if k is None else k["bytes"]
+
+
+def _traffic_table():
     path = os.path.join(ROOT, "paper_1810_04597_amd", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -41,8 +49,15 @@ def measured_traffic(kernel):
         t = json.load(f)
     if t.get("source_hash") != source_hash():
         return None
-    k = t["kernels"].get(kernel)
-    return None if k is None else k["bytes"]
+    return t
+
+
+# Compulsory HBM bytes per interior zone of one SSP-RK3 stage when a stage
+# reads and writes the state once: stage 1 reads P^n and U^n and writes U^(1)
+# and P^(1) (4 x 8 FP64 fields); stages 2 and 3 also read U^n beside the
+# current stage state (5 x 8 fields).  896 bytes per zone per step.
+STAGE_BYTES = (256.0, 320.0, 320.0)
+STEP_BYTES = sum(STAGE_BYTES)
 
 
 def launch_units(kernel, n):
@@ -54,6 +69,65 @@ def launch_units(kernel, n):
     if kernel.startswith("edge"):
         return (n + 5) * (n + 5) * n
     return n ** 3
+
+
+def rooflines(prof, n, steps, ms_step, precision):
+    """(roofline of the dominant kernel, roofline of the whole step, per-kernel
+    figures) from the HIP-event profile {class: (total ms, launches)} of
+    `steps` steps.
+
+    Dominant kernel (largest total time): when it is the stage update, its
+    algorithmic bytes are the stage's compulsory bytes (the mean of
+    STAGE_BYTES per zone, n^3 zones per launch), which credits it with the
+    state traffic of the whole stage; another dominant kernel is priced at its
+    own compulsory bytes per face, edge or zone (opcounts.json).  `traffic` is
+    the counter-measured HBM bytes per launch of that kernel (None when the
+    kernel sources changed since the counters were taken) and
+    traffic_over_algorithmic their ratio.
+    Step: STEP_BYTES per zone over the step time, and the counter-measured
+    bytes of every launch of a step (sum over classes of bytes per launch x
+    launches per step) over the same time."""
+    if not prof:
+        return None, None, {}
+    units = algorithmic_units()
+    tot_ms = sum(v[0] for v in prof.values())
+    kernels = {}
+    for k, (tot, cnt) in prof.items():
+        kernels[k] = {"avg_ms": tot / cnt, "launches": cnt, "share": tot / tot_ms}
+        u = units.get(k, {})
+        if "bytes" in u and k != "update":
+            kb = u["bytes"] * launch_units(k, n)
+            kernels[k]["own_bytes_per_launch"] = kb
+            kernels[k]["own_GBs"] = kb / (tot / cnt / 1e3) / 1e9
+    zones = n ** 3
+    dom = max(prof, key=lambda k: prof[k][0])
+    avg_s = prof[dom][0] / prof[dom][1] / 1e3
+    traffic = measured_traffic(dom) if n == 256 and precision == "fp64" else None
+    if dom == "update":
+        alg = sum(STAGE_BYTES) / len(STAGE_BYTES) * zones
+        basis = "stage compulsory bytes, mean of %s B/zone x %d zones" % (list(STAGE_BYTES), zones)
+    else:
+        alg = units.get(dom, {}).get("bytes", float("nan")) * launch_units(dom, n)
+        basis = "kernel's own compulsory bytes per unit x units per launch"
+    achieved = alg / avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                "avg_ms": avg_s * 1e3, "algorithmic_bytes_per_launch": alg, "basis": basis,
+                "traffic_over_algorithmic": (traffic / alg) if traffic else None}
+    step_alg = STEP_BYTES * zones
+    step = {"algorithmic_bytes": step_alg, "ms": ms_step,
+            "achieved": step_alg / (ms_step / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    step["frac"] = step["achieved"] / HBM_PEAK_GBS
+    t = _traffic_table() if n == 256 and precision == "fp64" else None
+    if t is not None and all(k in t["kernels"] for k in prof if k != "advance"):
+        meas = sum(t["kernels"][k]["bytes"] * prof[k][1] / steps for k in prof if k != "advance")
+        step.update(measured_bytes=meas, measured_achieved=meas / (ms_step / 1e3) / 1e9,
+                    measured_frac=meas / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+                    traffic_over_algorithmic=meas / step_alg)
+    else:
+        step.update(measured_bytes=None, measured_achieved=None, measured_frac=None,
+                    traffic_over_algorithmic=None)
+    return roofline, step, kernels
 
 
 def cpu_baseline(seconds_target=12.0):
@@ -603,33 +677,7 @@ def main():
         del src, dst
     zones = n ** 3
     value = zones * args.steps / (ms / 1e3)
-    # dominant kernel class
-    units = algorithmic_units()
-    roofline = None
-    kernels = {}
-    if prof:
-        for k, (tot, cnt) in prof.items():
-            kernels[k] = {"avg_ms": tot / cnt, "launches": cnt, "share": tot / sum(v[0] for v in prof.values())}
-        dom = max(prof, key=lambda k: prof[k][0])
-        avg_s = prof[dom][0] / prof[dom][1] / 1e3
-        u = units.get(dom, {})
-        nunits = launch_units(dom, n)
-        traffic = measured_traffic(dom) if n == 256 else None
-        if "flops" in u:
-            peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
-            achieved = u["flops"] * nunits / avg_s / 1e12
-            roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                        "frac": achieved / peak, "traffic": traffic,
-                        "kernel": dom, "avg_ms": avg_s * 1e3}
-        elif "bytes" in u:
-            achieved = u["bytes"] * nunits / avg_s / 1e9
-            roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                        "kernel": dom, "avg_ms": avg_s * 1e3}
-        else:
-            roofline = {"bound": "alu", "achieved": None, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": None, "traffic": None, "kernel": dom,
-                        "avg_ms": avg_s * 1e3}
+    roofline, step_roofline, kernels = rooflines(prof, n, args.steps, ms / args.steps, args.precision)
     cpu = None
     if rank == 0 and not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
@@ -652,8 +700,9 @@ def main():
                    "zones": zones, "precision": args.precision},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "step_roofline": step_roofline,
         "kernels": kernels,
-        "algorithmic_hbm_GBs": 896.0 * value / 1e9,
+        "algorithmic_hbm_GBs": STEP_BYTES * value / 1e9,
         "wall_s": wall,
         "launch": "eager" if args.eager else "graph",
         "ms_per_step_eager": ms_eager / args.steps,

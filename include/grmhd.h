@@ -129,6 +129,10 @@ typedef struct {
   int64_t newton_iters_sum, newton_iters_max;/* last inversion                     */
   int64_t n_nonfinite;     /* interior primitives that are not finite            */
   int64_t n_mlp_chosen;    /* last inversion: zones that started from the learned guess */
+  /* Accumulated over every inversion (each RK stage, cons2prim, the learned
+   * and split passes) since grmhd_init_grid or grmhd_reset_run_counters: */
+  int64_t run_c2p_fail;    /* zones whose Newton inversion failed                */
+  int64_t run_floor_rho, run_floor_p, run_wcap;  /* floor and W-cap activations  */
 } grmhd_diag;
 
 /* Create a grid.  desc is copied.  hip_stream: hipStream_t or NULL.
@@ -195,6 +199,10 @@ int grmhd_compute_dt(grmhd_grid* h, double* dt);
 /* Diagnostics of the bound state (synchronises).  Sums are taken in a fixed
  * order (deterministic). */
 int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out);
+
+/* Zero the accumulated inversion counters (grmhd_diag.run_*); enqueued on
+ * the grid's stream.  EINVAL on a NULL handle. */
+int grmhd_reset_run_counters(grmhd_grid* h);
 
 /* Fluxes through the surfaces x^1 = const of the bound state, for each
  * interior x^1 index i (synchronises; deterministic order).  A diagnostic of

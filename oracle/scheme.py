@@ -453,14 +453,33 @@ class Solver:
         return tot
 
     def diagnostics(self):
+        """Monitoring values of the current state (interior cells; owned faces
+        for the face fields): plain sums of the 8 conserved fields; the
+        largest |div_D B| and that value times min(dx) over the largest field
+        strength; extrema of rho and p; the largest Lorentz factor
+        W = sqrt(1 + u_i u^i) and field strength |B| = sqrt(B_i B^i) with the
+        centre metric; the number of non-finite interior primitives.  Extrema
+        skip NaN values."""
+        from .physics import lower
         out = {}
         for k in HYDRO + FACE:
             out["sum_" + k] = float(np.sum(self.interior(self.U[k])))
         dv = self.div_b()
         out["max_divb"] = float(np.max(np.abs(dv)))
         P = {k: self.interior(v) for k, v in self.P.items()}
-        out["rho_min"], out["rho_max"] = float(P["rho"].min()), float(P["rho"].max())
-        out["p_min"], out["p_max"] = float(P["p"].min()), float(P["p"].max())
+        out["rho_min"], out["rho_max"] = float(np.nanmin(P["rho"])), float(np.nanmax(P["rho"]))
+        out["p_min"], out["p_max"] = float(np.nanmin(P["p"])), float(np.nanmax(P["p"]))
+        m = self.centre_metric()
+        u = (P["u1"], P["u2"], P["u3"])
+        b = (P["B1"], P["B2"], P["B3"])
+        ul, bl = lower(m, u), lower(m, b)
+        w = np.sqrt(1.0 + ul[0] * u[0] + ul[1] * u[1] + ul[2] * u[2])
+        bmag = np.sqrt(np.maximum(bl[0] * b[0] + bl[1] * b[1] + bl[2] * b[2], 0.0))
+        out["w_max"] = float(np.nanmax(w))
+        out["b_max"] = float(np.nanmax(bmag))
+        out["max_divb_norm"] = (out["max_divb"] * min(self.grid.dx) / out["b_max"]
+                                if out["b_max"] > 0.0 else 0.0)
+        out["n_nonfinite"] = int(sum(int((~np.isfinite(v)).sum()) for v in P.values()))
         return out
 
 

@@ -22,7 +22,7 @@ EXPORTS = ("grmhd_init_grid", "grmhd_get_layout", "grmhd_bind_fields", "grmhd_se
            "grmhd_profile_class_name", "grmhd_mlp_set_weights", "grmhd_mlp_get_weights",
            "grmhd_mlp_datagen", "grmhd_mlp_gradient", "grmhd_mlp_train_step", "grmhd_mlp_forward",
            "grmhd_cons2prim_points", "grmhd_set_newton_split", "grmhd_mri_quality",
-           "grmhd_rk_steps_graph")
+           "grmhd_rk_steps_graph", "grmhd_reset_run_counters")
 MLP_NPARAM = 10448
 MLP_NNORM = 32
 PROF_NCLASS = 16
@@ -53,7 +53,9 @@ class Diag(C.Structure):
                 ("n_floor_rho", C.c_int64), ("n_floor_p", C.c_int64), ("n_wcap", C.c_int64),
                 ("n_c2p_fail", C.c_int64), ("n_mlp_fallback", C.c_int64),
                 ("newton_iters_sum", C.c_int64), ("newton_iters_max", C.c_int64),
-                ("n_nonfinite", C.c_int64), ("n_mlp_chosen", C.c_int64)]
+                ("n_nonfinite", C.c_int64), ("n_mlp_chosen", C.c_int64),
+                ("run_c2p_fail", C.c_int64), ("run_floor_rho", C.c_int64),
+                ("run_floor_p", C.c_int64), ("run_wcap", C.c_int64)]
 
     def as_dict(self):
         out = {}
@@ -98,6 +100,7 @@ def lib():
     L.grmhd_cons2prim.argtypes = [P, C.POINTER(C.c_int64), C.c_int]
     L.grmhd_compute_dt.argtypes = [P, D]
     L.grmhd_diagnostics.argtypes = [P, C.POINTER(Diag)]
+    L.grmhd_reset_run_counters.argtypes = [P]
     L.grmhd_shell_fluxes.argtypes = [P, C.POINTER(C.c_double), C.c_size_t]
     L.grmhd_destroy.argtypes = [P]
     L.grmhd_destroy.restype = None

@@ -18,6 +18,8 @@ static_assert(sizeof(grmhd_grid_desc) == 184 && offsetof(grmhd_grid_desc, recon)
                   offsetof(grmhd_grid_desc, newton_tol) == 168 &&
                   offsetof(grmhd_grid_desc, deriv_order) == 176,
               "grmhd_grid_desc layout");
+static_assert(sizeof(grmhd_diag) == 248 && offsetof(grmhd_diag, run_c2p_fail) == 216,
+              "grmhd_diag layout, which the Python binding mirrors");
 static_assert(GRMHD_RECON_MP5 == grmhd::RECON_MP5 && GRMHD_RECON_WENO5 == grmhd::RECON_WENO5 &&
                   GRMHD_RECON_PLM == grmhd::RECON_PLM,
               "reconstruction codes of the ABI and the kernels agree");
@@ -76,6 +78,7 @@ struct grmhd_grid {
   double* d_part = nullptr;      // per-block partials (cfl, diagnostics)
   long long* d_spart = nullptr;  // per-block inversion statistics
   long long* d_stats = nullptr;  // reduced inversion statistics (8)
+  unsigned long long* d_run = nullptr;  // accumulated inversion counters (RUN_SLOTS x RUN_STRIDE)
   double* d_diag = nullptr;      // reduced diagnostics (16)
   unsigned nblk = 0;
   int64_t step = 0;
@@ -193,8 +196,9 @@ void make_layout(const grmhd_grid_desc& d, grmhd_layout& L, Geom& G) {
   G.tab_plane = L.dims[0] * L.dims[1];
 }
 
-C2PParams c2p_params(const grmhd_grid_desc& d) {
+C2PParams c2p_params(const grmhd_grid_desc& d, unsigned long long* run_acc) {
   C2PParams cp;
+  cp.run_acc = run_acc;
   cp.tol = d.newton_tol;
   cp.maxit = d.newton_maxit;
   cp.guess = d.c2p_guess;
@@ -257,6 +261,8 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** 
   if (e == hipSuccess) e = hipMemsetAsync(h->d_spart, 0, spart, h->stream);
   if (e == hipSuccess) e = hipMalloc(&h->d_stats, C2P_NSTAT * sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&h->d_diag, (DIAG_NSUM + DIAG_NMAX) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&h->d_run, (size_t)RUN_SLOTS * RUN_STRIDE * sizeof(unsigned long long));
+  if (e == hipSuccess) launch_zero_u64(h->d_run, RUN_SLOTS * RUN_STRIDE, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->d_dt, 0, 3 * sizeof(double), h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->d_stats, 0, C2P_NSTAT * sizeof(long long), h->stream);
   if (e != hipSuccess) {
@@ -429,7 +435,7 @@ static void step_stages(grmhd_grid* h, double dt) {
   const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
   // periodic box: the update and the inversion write the ghost images of
   // what they produce, so the stage needs no separate ghost fills
-  C2PParams cp = c2p_params(h->desc);
+  C2PParams cp = c2p_params(h->desc, h->d_run);
   const bool img = h->img && h->flat;
   cp.img = img ? 1 : 0;
   // stage buffers: U^n stays in the bound cons until the last stage writes
@@ -519,7 +525,7 @@ int grmhd_cons2prim(grmhd_grid* h, int64_t* n_fail, int strict) {
   if (rc) return rc;
   if (strict && !n_fail) return fail(GRMHD_EINVAL, "strict mode needs n_fail");
   h->next_dt_valid = false;
-  C2PParams cp = c2p_params(h->desc);
+  C2PParams cp = c2p_params(h->desc, h->d_run);
   cp.img = h->img && h->flat ? 1 : 0;   // leaves the primitive ghosts filled, as rk_step expects
   h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
   c2p_with_guess(h, cp);
@@ -590,6 +596,10 @@ int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out) {
   hipError_t e = hipMemcpyAsync(dg, h->d_diag, sizeof(dg), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(st, h->d_stats, sizeof(st), hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(dtt, h->d_dt, sizeof(dtt), hipMemcpyDeviceToHost, h->stream);
+  std::vector<unsigned long long> run((size_t)RUN_SLOTS * RUN_STRIDE, 0ull);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(run.data(), h->d_run, run.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                       h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
   rc = hip_check("diagnostics");
@@ -618,7 +628,20 @@ int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out) {
   out->n_wcap = st[5];
   out->n_mlp_fallback = st[6];
   out->n_mlp_chosen = st[7];
+  int64_t acc[RUN_NCOUNT] = {0, 0, 0, 0};
+  for (int sl = 0; sl < RUN_SLOTS; ++sl)
+    for (int q = 0; q < RUN_NCOUNT; ++q) acc[q] += (int64_t)run[(size_t)sl * RUN_STRIDE + q];
+  out->run_c2p_fail = acc[0];
+  out->run_floor_rho = acc[1];
+  out->run_floor_p = acc[2];
+  out->run_wcap = acc[3];
   return GRMHD_OK;
+}
+
+int grmhd_reset_run_counters(grmhd_grid* h) {
+  if (!h) return fail(GRMHD_EINVAL, "grid handle is NULL");
+  launch_zero_u64(h->d_run, RUN_SLOTS * RUN_STRIDE, h->stream);
+  return hip_check("reset_run_counters");
 }
 
 static int mlp_alloc(grmhd_grid* h) {
@@ -810,6 +833,7 @@ void grmhd_destroy(grmhd_grid* h) {
   (void)hipFree(h->d_spart);
   (void)hipFree(h->d_stats);
   (void)hipFree(h->d_diag);
+  (void)hipFree(h->d_run);
   delete h;
 }
 

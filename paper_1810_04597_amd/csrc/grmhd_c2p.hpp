@@ -231,10 +231,13 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+// run_acc (nullable): the block's failed, rho-floored, p-floored and W-capped
+// zones are also added to the accumulated counters (only when non-zero).
 template <bool PACKED>
 __device__ __forceinline__ void c2p_block_partials(const long long st[8], double cfl_v,
                                                    long long* __restrict__ partials,
-                                                   double* __restrict__ cfl_partials, int slot) {
+                                                   double* __restrict__ cfl_partials, int slot,
+                                                   unsigned long long* __restrict__ run_acc) {
   if (cfl_partials) {
     __shared__ double shc[4];
     const double w = wave_max(cfl_v);
@@ -264,6 +267,12 @@ __device__ __forceinline__ void c2p_block_partials(const long long st[8], double
       for (int q = 0; q < 8; ++q) o[q] = q == 2 ? (sh[w][q] > o[q] ? sh[w][q] : o[q]) : o[q] + sh[w][q];
     long long* dst = partials + (long)slot * C2P_NSTAT;
     for (int q = 0; q < 8; ++q) dst[q] = o[q];
+    if (run_acc) {
+      constexpr int src[RUN_NCOUNT] = {0, 3, 4, 5};   // fail, floor_rho, floor_p, W cap
+      unsigned long long* a = run_acc + (long)(blockIdx.x % RUN_SLOTS) * RUN_STRIDE;
+      for (int q = 0; q < RUN_NCOUNT; ++q)
+        if (o[src[q]] != 0) atomicAdd(a + q, (unsigned long long)o[src[q]]);
+    }
   }
 }
 

@@ -15,7 +15,17 @@ struct C2PParams {
   double defer_tol;     // learned guess: relative warm residual above which a zone is deferred
   int img;              // all directions periodic, n >= 2 NG: also write the ghost images
   int split_it;         // > 0: defer zones not converged after this many iterations to a second pass
+  // nullable: counters accumulated over every inversion (RUN_SLOTS slots of
+  // RUN_STRIDE words: failed zones, rho floors, p floors, W caps)
+  unsigned long long* run_acc;
 };
+
+// Accumulated inversion counters: a block adds its non-zero counts to slot
+// (block mod RUN_SLOTS) so that concurrent blocks rarely hit one address;
+// each slot sits on its own 128-byte line.  The host sums the slots.
+constexpr int RUN_NCOUNT = 4;
+constexpr int RUN_SLOTS = 64;
+constexpr int RUN_STRIDE = 16;
 
 // Per-block partial results of the inversion (reduced on the device).
 constexpr int C2P_NSTAT = 8;   // fail, iters_sum, iters_max, floor_rho, floor_p, wcap, learned fallback, learned chosen
@@ -61,6 +71,7 @@ void launch_c2p_split(const Geom& G, bool flat, const C2PParams& cp, double* pri
                       const double* tab, const int* list, const int* list_n, const double* list_y,
                       long long* partials, double* cfl_partials, hipStream_t s);
 void launch_zero_int(int* p, hipStream_t s);
+void launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 // Shell fluxes through x^1 = const: out[4 n1] = F_D, F_tau, Phi (|B|/2), Phi
 // signed; part: shell_part_doubles(G) doubles of chunk partials.
 void launch_shell(const Geom& G, bool flat, const double* prim, const double* cons, const double* tab,

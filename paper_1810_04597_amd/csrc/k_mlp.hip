@@ -653,7 +653,7 @@ __global__ __launch_bounds__(256) void k_c2p_list(Geom G, C2PParams cp, double* 
       cfl_v = fmax(cfl_v, cv);
     }
   }
-  c2p_block_partials<false>(st, cfl_v, partials, cfl_partials, blockIdx.x);
+  c2p_block_partials<false>(st, cfl_v, partials, cfl_partials, blockIdx.x, cp.run_acc);
 }
 
 }  // namespace mlp

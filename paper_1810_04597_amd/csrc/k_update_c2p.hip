@@ -343,7 +343,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C2P_MIN_WAV
       if (list_y) list_y[pos] = yl;
     }
   }
-  c2p_block_partials<true>(st, cfl_v, partials, cfl_partials, blockIdx.x);
+  c2p_block_partials<true>(st, cfl_v, partials, cfl_partials, blockIdx.x, cp.run_acc);
 }
 
 // Second pass of the split inversion: the zones the first pass deferred after
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_c2p_split(Geom G, C2PParams cp, double*
     c2p_zone<MET>(G, cp, prim, cons, tab, list[idx], -1.0, 0.0, cfl_partials != nullptr, st, cv, list_y[idx]);
     cfl_v = fmax(cfl_v, cv);
   }
-  c2p_block_partials<false>(st, cfl_v, partials, cfl_partials, blockIdx.x);
+  c2p_block_partials<false>(st, cfl_v, partials, cfl_partials, blockIdx.x, cp.run_acc);
 }
 
 __global__ __launch_bounds__(256) void k_reduce_stats(const long long* __restrict__ partials, int nb,
@@ -802,6 +802,14 @@ __global__ void k_zero_int(int* __restrict__ p) {
 }
 
 void launch_zero_int(int* p, hipStream_t s) { hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, p); }
+
+__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* __restrict__ p, int n) {
+  for (int q = threadIdx.x; q < n; q += blockDim.x) p[q] = 0ull;
+}
+
+void launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, p, n);
+}
 
 void launch_dt_final(const double* cfl_partials, int nb, double cfl, double* d_dt, hipStream_t s) {
   hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, cfl_partials, nb, cfl, d_dt);

@@ -129,6 +129,10 @@ class Grid:
         self._call(self.lib.grmhd_diagnostics, self.h, C.byref(d))
         return d.as_dict()
 
+    def reset_run_counters(self):
+        """Zero the inversion counters accumulated over every inversion (diag run_*)."""
+        self._call(self.lib.grmhd_reset_run_counters, self.h)
+
     def shell_fluxes(self):
         """{F_D, F_tau, Phi, Phi_s}: fluxes through the x^1 = const shells (numpy, n1 each)."""
         n1 = self.spec.n[0]
