@@ -196,6 +196,20 @@ int grmhd_cons2prim(grmhd_grid* h, int64_t* n_fail, int strict);
  * rk_step with dt <= 0 takes this step. */
 int grmhd_compute_dt(grmhd_grid* h, double* dt);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight stepping loops, harnesses that forbid hipMalloc): the CFL
+ * time step of grmhd_compute_dt, written to caller-owned device memory
+ * dt_dev (one double) on the grid's stream, without synchronising and
+ * without any allocation.  The per-workgroup partial maxima go to a static
+ * device array of the library (4 MiB per device, kept until the process
+ * ends), so the grid may hold at most 2^27 interior zones (EINVAL beyond).
+ * Every call on one device shares that array: calls that overlap on one
+ * device (other streams, other threads) race.  The grid's own state,
+ * including the time step a following rk_step(dt <= 0) takes, is unchanged.
+ * ESTATE before fields and metric are set; EHIP when the array's device
+ * address could not be looked up at grmhd_init_grid. */
+int grmhd_compute_dt_noalloc(grmhd_grid* h, double* dt_dev);
+
 /* Diagnostics of the bound state (synchronises).  Sums are taken in a fixed
  * order (deterministic). */
 int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out);

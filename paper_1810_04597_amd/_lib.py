@@ -22,7 +22,7 @@ EXPORTS = ("grmhd_init_grid", "grmhd_get_layout", "grmhd_bind_fields", "grmhd_se
            "grmhd_profile_class_name", "grmhd_mlp_set_weights", "grmhd_mlp_get_weights",
            "grmhd_mlp_datagen", "grmhd_mlp_gradient", "grmhd_mlp_train_step", "grmhd_mlp_forward",
            "grmhd_cons2prim_points", "grmhd_set_newton_split", "grmhd_mri_quality",
-           "grmhd_rk_steps_graph", "grmhd_reset_run_counters")
+           "grmhd_rk_steps_graph", "grmhd_reset_run_counters", "grmhd_compute_dt_noalloc")
 MLP_NPARAM = 10448
 MLP_NNORM = 32
 PROF_NCLASS = 16
@@ -99,6 +99,7 @@ def lib():
     L.grmhd_rk_step.argtypes = [P, C.c_double, D]
     L.grmhd_cons2prim.argtypes = [P, C.POINTER(C.c_int64), C.c_int]
     L.grmhd_compute_dt.argtypes = [P, D]
+    L.grmhd_compute_dt_noalloc.argtypes = [P, P]
     L.grmhd_diagnostics.argtypes = [P, C.POINTER(Diag)]
     L.grmhd_reset_run_counters.argtypes = [P]
     L.grmhd_shell_fluxes.argtypes = [P, C.POINTER(C.c_double), C.c_size_t]

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,42 @@ static_assert(GRMHD_RECON_MP5 == grmhd::RECON_MP5 && GRMHD_RECON_WENO5 == grmhd:
 #include "grmhd_mlp.hpp"
 
 using namespace grmhd;
+
+// ------------------------------------------------------------------ no-allocation scratch
+// Per-workgroup partial maxima of the CFL reduction for
+// grmhd_compute_dt_noalloc: a file-scope device array (4 MiB on every device
+// the library runs on, held until the process ends) instead of the grid's
+// library-allocated reduction buffer.  One double per 256-zone workgroup:
+// grids of up to NOALLOC_MAX_BLOCKS x 256 = 2^27 interior zones (512^3).
+// Host code never uses the array's name as an address: its device address is
+// looked up once per device at grmhd_init_grid (noalloc_resolve) and kept.
+constexpr long NOALLOC_MAX_BLOCKS = 1L << 19;
+static __device__ __align__(256) double scratch[NOALLOC_MAX_BLOCKS];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device).  Returns nullptr and sets *err when the lookup fails.
+double* noalloc_resolve(int dev, std::string* err) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    *err = "device index beyond the no-allocation table";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[dev]) return g_noalloc_ptr[dev];
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr) {
+    *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  g_noalloc_ptr[dev] = static_cast<double*>(p);
+  return g_noalloc_ptr[dev];
+}
+}  // namespace
 
 namespace {
 thread_local std::string g_err;
@@ -63,6 +100,9 @@ struct grmhd_grid {
   Geom G;
   BCSpec bc;
   hipStream_t stream = nullptr;
+  int device = 0;                  // device current at grmhd_init_grid
+  double* noalloc_scratch = nullptr;   // that device's `scratch` (nullptr: lookup failed)
+  std::string noalloc_err;
   grmhd_layout lay;
   double* prim = nullptr;
   double* cons = nullptr;
@@ -245,6 +285,12 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** 
   for (int d = 0; d < 3; ++d) h->img = h->img && desc->n[d] >= 2 * NG;
   h->stream = (hipStream_t)hip_stream;
   h->nblk = zone_blocks(h->G);
+  // the device address of the no-allocation scratch, once per device; a
+  // failed lookup only disables grmhd_compute_dt_noalloc
+  if (hipGetDevice(&h->device) == hipSuccess)
+    h->noalloc_scratch = noalloc_resolve(h->device, &h->noalloc_err);
+  else
+    h->noalloc_err = "hipGetDevice failed";
   // reduction partials: diagnostics (nblk x 16), CFL (nblk + learned-pass
   // blocks), shell fluxes (chunk partials, then the 4 n1 results)
   const size_t part = std::max(std::max((size_t)h->nblk * (DIAG_NSUM + DIAG_NMAX),
@@ -553,6 +599,17 @@ int grmhd_compute_dt(grmhd_grid* h, double* dt) {
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
   return hip_check("compute_dt");
+}
+
+int grmhd_compute_dt_noalloc(grmhd_grid* h, double* dt_dev) {
+  int rc = ready(h);
+  if (rc) return rc;
+  if (!dt_dev) return fail(GRMHD_EINVAL, "dt_dev is NULL");
+  if ((long)h->nblk > NOALLOC_MAX_BLOCKS)
+    return fail(GRMHD_EINVAL, "grid too large for the no-allocation scratch (at most 2^27 interior zones)");
+  if (!h->noalloc_scratch) return fail(GRMHD_EHIP, "no-allocation scratch unavailable: " + h->noalloc_err);
+  launch_cfl(h->G, h->flat, h->prim, h->tab, h->desc.cfl, h->noalloc_scratch, dt_dev, h->stream);
+  return hip_check("compute_dt_noalloc");
 }
 
 int grmhd_shell_fluxes(grmhd_grid* h, double* host_out, size_t n_doubles) {

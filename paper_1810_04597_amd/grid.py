@@ -124,6 +124,11 @@ class Grid:
         self._call(self.lib.grmhd_compute_dt, self.h, C.byref(v))
         return v.value
 
+    def compute_dt_noalloc(self, out):
+        """CFL step into out (device float64 tensor, >= 1 element), without
+        synchronising or allocating."""
+        self._call(self.lib.grmhd_compute_dt_noalloc, self.h, C.c_void_p(out.data_ptr()))
+
     def diagnostics(self):
         d = L.Diag()
         self._call(self.lib.grmhd_diagnostics, self.h, C.byref(d))
