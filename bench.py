@@ -505,6 +505,32 @@ def learned_report(args):
     ok = (ic > 0) & (im > 0)
     T.close()
     del feat, targ
+    # the network's own gain on this workload: the torus' conserved state
+    # inverted from the cold start, from the network's guess alone (every
+    # zone deferred to the learned pass) and from the warm start (the exact
+    # previous primitives); Newton iterations and inversion time
+    starts = {}
+    for name, guess in (("cold", L.GUESS_COLD), ("network_only", L.GUESS_MLP), ("warm", L.GUESS_WARM)):
+        G = Grid(g, tables=tab, guess=guess)
+        if guess == L.GUESS_MLP:
+            G.mlp_set_weights(flat, norm)
+            G.set_learned_guess(0.0, L.LEARNED_ONLY)
+        G.curl_potential(d)
+        G.set_primitives(d)
+        G.cons2prim()
+        G.set_profiling(True)
+        G.profile(reset=True)
+        G.reset_run_counters()
+        G.cons2prim()
+        prof = G.profile(reset=True)
+        G.set_profiling(False)
+        dg = G.diagnostics()
+        starts[name] = {"newton_iters_per_zone": dg["newton_iters_sum"] / g.zones,
+                        "newton_iters_max": dg["newton_iters_max"],
+                        "inversion_ms": sum(v[0] for k, v in prof.items() if k in ("cons2prim", "learned_guess")),
+                        "network_chosen": dg["run_mlp_chosen"], "network_fallbacks": dg["run_mlp_fallback"]}
+        G.close()
+    print("bench: start comparison %s" % json.dumps(starts), file=sys.stderr, flush=True)
     forms = {"fp64_warm": (L.FP64, L.GUESS_WARM), "fp32_learned": (L.FP32_FLUX, L.GUESS_MLP),
              "fp32_warm": (L.FP32_FLUX, L.GUESS_WARM)}
     res, grids = {}, {}
@@ -520,6 +546,7 @@ def learned_report(args):
         G.synchronize()
         G.set_profiling(True)
         G.profile(reset=True)
+        G.reset_run_counters()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(G.stream)
@@ -535,6 +562,11 @@ def learned_report(args):
                      "newton_iters_per_zone_last": dg["newton_iters_sum"] / g.zones,
                      "learned_fallbacks_last": dg["n_mlp_fallback"],
                      "learned_chosen_last": dg["n_mlp_chosen"], "c2p_fail_last": dg["n_c2p_fail"],
+                     "run": {"stages": 3 * args.steps, "deferred_to_network": dg["run_mlp_deferred"],
+                             "network_chosen": dg["run_mlp_chosen"],
+                             "network_fallbacks": dg["run_mlp_fallback"], "c2p_fail": dg["run_c2p_fail"],
+                             "floor_rho": dg["run_floor_rho"], "floor_p": dg["run_floor_p"],
+                             "wcap": dg["run_wcap"]},
                      "kernels_avg_ms": {k: v[0] / v[1] for k, v in prof.items()}}
         grids[name] = G
         print("bench: %s done" % name, file=sys.stderr, flush=True)
@@ -558,6 +590,7 @@ def learned_report(args):
            "config": {"workload": "Kerr-Schild a=0.9 torus %dx%dx%d, fixed dt %.3e, 2%% noise, beta 100" % (n1, n2, n3, dt),
                       "train_samples": args.train_samples, "epochs": args.epochs},
            "training": {"seconds": train_s, "loss_first_epoch": losses[0], "loss_last_epoch": losses[-1]},
+           "inversion_of_torus_state_by_start": starts,
            "unseen_samples_newton_iters": {"cold": float(ic[ok].mean()), "learned": float(im[ok].mean()),
                                            "n": int(ok.sum())},
            "forms": res}

@@ -133,6 +133,9 @@ typedef struct {
    * and split passes) since grmhd_init_grid or grmhd_reset_run_counters: */
   int64_t run_c2p_fail;    /* zones whose Newton inversion failed                */
   int64_t run_floor_rho, run_floor_p, run_wcap;  /* floor and W-cap activations  */
+  int64_t run_mlp_deferred;  /* zones inverted in the learned-guess pass        */
+  int64_t run_mlp_chosen;    /* zones that started from the network's guess     */
+  int64_t run_mlp_fallback;  /* learned starts rerun from the warm guess         */
 } grmhd_diag;
 
 /* Create a grid.  desc is copied.  hip_stream: hipStream_t or NULL.
@@ -298,6 +301,18 @@ int grmhd_set_newton_split(grmhd_grid* h, int32_t iters);
  * Sample arrays are device float32: features n x 8, targets n x 8 (5 used),
  * outputs n x 8 (5 used, standardised). */
 #define GRMHD_MLP_NPARAM 10448
+/* Policy of the learned-guess pass (GRMHD_GUESS_MLP grids only):
+ * defer_tol > 0: zones whose warm start leaves a first relative residual
+ * above defer_tol go to the network pass (1e-2 by default); defer_tol = 0:
+ * every zone goes there (the warm start is not tried first).
+ * start = GRMHD_LEARNED_BEST (default): Newton starts from the warm or the
+ * network's guess, whichever has the smaller residual; GRMHD_LEARNED_ONLY:
+ * from the network's guess alone (rerun from the warm guess if it does not
+ * converge), which measures what the network itself gains.
+ * EINVAL on another grid, a negative or non-finite defer_tol or another
+ * start.  Drops a captured step graph; allocates nothing. */
+enum { GRMHD_LEARNED_BEST = 0, GRMHD_LEARNED_ONLY = 1 };
+int grmhd_set_learned_guess(grmhd_grid* h, double defer_tol, int start);
 #define GRMHD_MLP_NNORM 32
 int grmhd_mlp_set_weights(grmhd_grid* h, const float* host_params, size_t n_params,
                           const float* host_norm, size_t n_norm);

@@ -10,6 +10,7 @@ CART, LOGSPH = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_AXIS = 0, 1, 2
 FP64, FP32_FLUX = 0, 1
 GUESS_WARM, GUESS_COLD, GUESS_MLP = 0, 1, 2
+LEARNED_BEST, LEARNED_ONLY = 0, 1
 RECON_MP5, RECON_WENO5, RECON_PLM = 0, 1, 2
 RECON = {"mp5": RECON_MP5, "weno5": RECON_WENO5, "plm": RECON_PLM}
 METRIC_MINKOWSKI, METRIC_TABLE_AXISYM = 0, 1
@@ -22,7 +23,8 @@ EXPORTS = ("grmhd_init_grid", "grmhd_get_layout", "grmhd_bind_fields", "grmhd_se
            "grmhd_profile_class_name", "grmhd_mlp_set_weights", "grmhd_mlp_get_weights",
            "grmhd_mlp_datagen", "grmhd_mlp_gradient", "grmhd_mlp_train_step", "grmhd_mlp_forward",
            "grmhd_cons2prim_points", "grmhd_set_newton_split", "grmhd_mri_quality",
-           "grmhd_rk_steps_graph", "grmhd_reset_run_counters", "grmhd_compute_dt_noalloc")
+           "grmhd_rk_steps_graph", "grmhd_reset_run_counters", "grmhd_compute_dt_noalloc",
+           "grmhd_set_learned_guess")
 MLP_NPARAM = 10448
 MLP_NNORM = 32
 PROF_NCLASS = 16
@@ -55,7 +57,9 @@ class Diag(C.Structure):
                 ("newton_iters_sum", C.c_int64), ("newton_iters_max", C.c_int64),
                 ("n_nonfinite", C.c_int64), ("n_mlp_chosen", C.c_int64),
                 ("run_c2p_fail", C.c_int64), ("run_floor_rho", C.c_int64),
-                ("run_floor_p", C.c_int64), ("run_wcap", C.c_int64)]
+                ("run_floor_p", C.c_int64), ("run_wcap", C.c_int64),
+                ("run_mlp_deferred", C.c_int64), ("run_mlp_chosen", C.c_int64),
+                ("run_mlp_fallback", C.c_int64)]
 
     def as_dict(self):
         out = {}
@@ -108,6 +112,7 @@ def lib():
     L.grmhd_last_error.restype = C.c_char_p
     L.grmhd_set_profiling.argtypes = [P, C.c_int]
     L.grmhd_set_newton_split.argtypes = [P, C.c_int32]
+    L.grmhd_set_learned_guess.argtypes = [P, C.c_double, C.c_int]
     L.grmhd_rk_steps_graph.argtypes = [P, C.c_int32]
     L.grmhd_mri_quality.argtypes = [P, C.c_double, C.c_double, C.POINTER(C.c_double), C.c_size_t]
     L.grmhd_get_profile.argtypes = [P, C.POINTER(Profile), C.c_int]

@@ -19,7 +19,7 @@ static_assert(sizeof(grmhd_grid_desc) == 184 && offsetof(grmhd_grid_desc, recon)
                   offsetof(grmhd_grid_desc, newton_tol) == 168 &&
                   offsetof(grmhd_grid_desc, deriv_order) == 176,
               "grmhd_grid_desc layout");
-static_assert(sizeof(grmhd_diag) == 248 && offsetof(grmhd_diag, run_c2p_fail) == 216,
+static_assert(sizeof(grmhd_diag) == 272 && offsetof(grmhd_diag, run_c2p_fail) == 216,
               "grmhd_diag layout, which the Python binding mirrors");
 static_assert(GRMHD_RECON_MP5 == grmhd::RECON_MP5 && GRMHD_RECON_WENO5 == grmhd::RECON_WENO5 &&
                   GRMHD_RECON_PLM == grmhd::RECON_PLM,
@@ -153,6 +153,10 @@ struct grmhd_grid {
   // field, whose contents are dead while an inversion runs
   double* list_y() const { return scratch + (long)SCR_FLUX * G.field; }
   int split_it = 0;   // Newton iterations of the first pass of a split inversion (0: off)
+  // learned guess: relative warm-start residual above which a zone goes to
+  // the network pass (0: every zone), and the start policy there
+  double mlp_defer_tol = 1e-2;
+  int mlp_start = GRMHD_LEARNED_BEST;
   // one captured device-dt step (grmhd_rk_steps_graph); dropped whenever the
   // launch sequence or a pointer in it changes
   hipGraph_t graph = nullptr;
@@ -236,9 +240,13 @@ void make_layout(const grmhd_grid_desc& d, grmhd_layout& L, Geom& G) {
   G.tab_plane = L.dims[0] * L.dims[1];
 }
 
-C2PParams c2p_params(const grmhd_grid_desc& d, unsigned long long* run_acc) {
+C2PParams c2p_params(const grmhd_grid* h) {
+  const grmhd_grid_desc& d = h->desc;
   C2PParams cp;
-  cp.run_acc = run_acc;
+  cp.run_acc = h->d_run;
+  const bool mlp = d.c2p_guess == GRMHD_GUESS_MLP;
+  cp.defer_all = mlp && h->mlp_defer_tol == 0.0 ? 1 : 0;
+  cp.learned_only = mlp && h->mlp_start == GRMHD_LEARNED_ONLY ? 1 : 0;
   cp.tol = d.newton_tol;
   cp.maxit = d.newton_maxit;
   cp.guess = d.c2p_guess;
@@ -249,9 +257,9 @@ C2PParams c2p_params(const grmhd_grid_desc& d, unsigned long long* run_acc) {
   cp.p_fl_n = d.p_fl_n;
   cp.w_max = d.w_max;
   // learned guess: zones whose warm start (the previous primitives) leaves a
-  // relative residual above 1e-2 go to the network pass; elsewhere the warm
-  // start is better than the network's accuracy
-  cp.defer_tol = d.c2p_guess == GRMHD_GUESS_MLP ? 1e-2 : 0.0;
+  // relative residual above mlp_defer_tol (1e-2 unless set) go to the network
+  // pass; elsewhere the warm start is better than the network's accuracy
+  cp.defer_tol = mlp && h->mlp_defer_tol > 0.0 ? h->mlp_defer_tol : 0.0;
   cp.img = 0;
   cp.split_it = 0;
   return cp;
@@ -464,7 +472,8 @@ int grmhd_rhs(grmhd_grid* h, double* rhs_out) {
   if (!rhs_out) return fail(GRMHD_EINVAL, "rhs_out is NULL");
   rhs_pieces(h);
   h->timed(13, [&] {
-    launch_update(h->G, h->flat, 1, h->prim, h->cons, h->stage_state(), h->flux(), h->edges(), h->tab,
+    launch_update(h->G, h->flat, h->desc.precision == GRMHD_FP32_FLUX, 1, h->prim, h->cons, h->stage_state(),
+                  h->flux(), h->edges(), h->tab,
                   0.0, 0.0, 0.0, h->d_dt, rhs_out, 1, h->stream);
   });
   return hip_check("rhs");
@@ -481,7 +490,7 @@ static void step_stages(grmhd_grid* h, double dt) {
   const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
   // periodic box: the update and the inversion write the ghost images of
   // what they produce, so the stage needs no separate ghost fills
-  C2PParams cp = c2p_params(h->desc, h->d_run);
+  C2PParams cp = c2p_params(h);
   const bool img = h->img && h->flat;
   cp.img = img ? 1 : 0;
   // stage buffers: U^n stays in the bound cons until the last stage writes
@@ -493,7 +502,8 @@ static void step_stages(grmhd_grid* h, double dt) {
     double* const next = s == 2 ? Un : S;       // state the stage produces
     rhs_pieces(h, !img, cur);
     h->timed(7, [&] {
-      launch_update(h->G, h->flat, 0, h->prim, s == 0 ? Un : S, s == 0 ? S : Un, h->flux(), h->edges(),
+      launch_update(h->G, h->flat, h->desc.precision == GRMHD_FP32_FLUX, 0, h->prim, s == 0 ? Un : S,
+                    s == 0 ? S : Un, h->flux(), h->edges(),
                     h->tab, A[s], B[s], dt, dt_src, nullptr, s + 1, h->stream, img ? 1 : 0);
     });
     // dt and time are recorded once the last update has consumed d_dt[2]
@@ -571,7 +581,7 @@ int grmhd_cons2prim(grmhd_grid* h, int64_t* n_fail, int strict) {
   if (rc) return rc;
   if (strict && !n_fail) return fail(GRMHD_EINVAL, "strict mode needs n_fail");
   h->next_dt_valid = false;
-  C2PParams cp = c2p_params(h->desc, h->d_run);
+  C2PParams cp = c2p_params(h);
   cp.img = h->img && h->flat ? 1 : 0;   // leaves the primitive ghosts filled, as rk_step expects
   h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
   c2p_with_guess(h, cp);
@@ -692,6 +702,9 @@ int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out) {
   out->run_floor_rho = acc[1];
   out->run_floor_p = acc[2];
   out->run_wcap = acc[3];
+  out->run_mlp_deferred = acc[4];
+  out->run_mlp_chosen = acc[5];
+  out->run_mlp_fallback = acc[6];
   return GRMHD_OK;
 }
 
@@ -836,6 +849,18 @@ int grmhd_set_newton_split(grmhd_grid* h, int32_t iters) {
   hipError_t e = hipMemsetAsync(h->d_spart + (long)h->nblk * C2P_NSTAT, 0,
                                 (size_t)C2P_LIST_BLOCKS * C2P_NSTAT * sizeof(long long), h->stream);
   if (e != hipSuccess) return fail(GRMHD_EHIP, hipGetErrorString(e));
+  return GRMHD_OK;
+}
+
+int grmhd_set_learned_guess(grmhd_grid* h, double defer_tol, int start) {
+  if (!h) return fail(GRMHD_EINVAL, "grid handle is NULL");
+  if (h->desc.c2p_guess != GRMHD_GUESS_MLP) return fail(GRMHD_EINVAL, "the grid does not use the learned guess");
+  if (!(defer_tol >= 0.0) || !std::isfinite(defer_tol)) return fail(GRMHD_EINVAL, "defer_tol must be finite and >= 0");
+  if (start != GRMHD_LEARNED_BEST && start != GRMHD_LEARNED_ONLY) return fail(GRMHD_EINVAL, "bad start policy");
+  if (defer_tol == h->mlp_defer_tol && start == h->mlp_start) return GRMHD_OK;
+  graph_reset(h);
+  h->mlp_defer_tol = defer_tol;
+  h->mlp_start = start;
   return GRMHD_OK;
 }
 

@@ -98,7 +98,7 @@ __device__ __forceinline__ bool c2p_zone(const Geom& G, const C2PParams& cp, dou
                                          double* __restrict__ cons, const double* __restrict__ tab,
                                          long t, double y_alt, double defer_tol, bool want_cfl,
                                          long long st[8], double& cfl_v, double y_start = -1.0,
-                                         double* y_last = nullptr) {
+                                         double* y_last = nullptr, bool learned_start = false) {
   int i, j, k;
   zone_of(G, t, i, j, k);
   const long c = G.idx(i, j, k);
@@ -129,10 +129,14 @@ __device__ __forceinline__ bool c2p_zone(const Geom& G, const C2PParams& cp, dou
     if (y_last) *y_last = r.y_last;
     return true;
   }
+  // learned_start: y_start is the network's guess (counted as chosen, and
+  // as a fallback when it has to be rerun from the warm guess)
+  if (learned_start && y_start > 0.0) st[7] += 1;
   if (y_start > 0.0 && !r.ok) {
     const int it0 = r.iters;
     r = newton<double>(dd, S, tau, B, m, G.gam, ywarm, cp.tol, cp.maxit);
     r.iters += it0;
+    if (learned_start) st[6] += 1;
   }
   if (r.alt) st[7] += 1;
   if (r.alt && !r.ok) {
@@ -232,12 +236,15 @@ __device__ __forceinline__ int wave_max_i(int v) {
 }
 
 // run_acc (nullable): the block's failed, rho-floored, p-floored and W-capped
-// zones are also added to the accumulated counters (only when non-zero).
+// zones, its zones taken from the learned-guess list (nlist, per thread), and
+// its learned starts and their fallbacks are also added to the accumulated
+// counters (only when non-zero).
 template <bool PACKED>
 __device__ __forceinline__ void c2p_block_partials(const long long st[8], double cfl_v,
                                                    long long* __restrict__ partials,
                                                    double* __restrict__ cfl_partials, int slot,
-                                                   unsigned long long* __restrict__ run_acc) {
+                                                   unsigned long long* __restrict__ run_acc,
+                                                   long long nlist = 0) {
   if (cfl_partials) {
     __shared__ double shc[4];
     const double w = wave_max(cfl_v);
@@ -258,8 +265,12 @@ __device__ __forceinline__ void c2p_block_partials(const long long st[8], double
   } else {
     for (int q = 0; q < 8; ++q) rr[q] = q == 2 ? wave_max_ll(st[q]) : wave_sum_ll(st[q]);
   }
-  if (lane == 0)
+  __shared__ long long shl[4];
+  const long long nl = run_acc ? wave_sum_ll(nlist) : 0;
+  if (lane == 0) {
     for (int q = 0; q < 8; ++q) sh[wv][q] = rr[q];
+    shl[wv] = nl;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     long long o[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -268,10 +279,10 @@ __device__ __forceinline__ void c2p_block_partials(const long long st[8], double
     long long* dst = partials + (long)slot * C2P_NSTAT;
     for (int q = 0; q < 8; ++q) dst[q] = o[q];
     if (run_acc) {
-      constexpr int src[RUN_NCOUNT] = {0, 3, 4, 5};   // fail, floor_rho, floor_p, W cap
+      const long long v[RUN_NCOUNT] = {o[0], o[3], o[4], o[5], shl[0] + shl[1] + shl[2] + shl[3], o[7], o[6]};
       unsigned long long* a = run_acc + (long)(blockIdx.x % RUN_SLOTS) * RUN_STRIDE;
       for (int q = 0; q < RUN_NCOUNT; ++q)
-        if (o[src[q]] != 0) atomicAdd(a + q, (unsigned long long)o[src[q]]);
+        if (v[q] != 0) atomicAdd(a + q, (unsigned long long)v[q]);
     }
   }
 }

@@ -16,14 +16,19 @@ struct C2PParams {
   int img;              // all directions periodic, n >= 2 NG: also write the ghost images
   int split_it;         // > 0: defer zones not converged after this many iterations to a second pass
   // nullable: counters accumulated over every inversion (RUN_SLOTS slots of
-  // RUN_STRIDE words: failed zones, rho floors, p floors, W caps)
+  // RUN_STRIDE words, RUN_NCOUNT used)
   unsigned long long* run_acc;
+  int defer_all;        // learned guess: every zone goes to the network pass
+  int learned_only;     // learned guess: the network's start alone (warm start as fallback)
 };
 
 // Accumulated inversion counters: a block adds its non-zero counts to slot
 // (block mod RUN_SLOTS) so that concurrent blocks rarely hit one address;
 // each slot sits on its own 128-byte line.  The host sums the slots.
-constexpr int RUN_NCOUNT = 4;
+// Counters: failed zones, rho floors, p floors, W caps, zones inverted in the
+// learned-guess pass, zones started from the network's guess, learned starts
+// rerun from the warm guess.
+constexpr int RUN_NCOUNT = 7;
 constexpr int RUN_SLOTS = 64;
 constexpr int RUN_STRIDE = 16;
 
@@ -52,7 +57,9 @@ void launch_edge(int e, const Geom& G, bool flat, bool fp32, int recon, const do
 // mode 1: write L of the state in x into out (cons layout).
 // img (flat metric, mode 0): all directions periodic with n >= 2 NG; the new
 // face fields are also written to their ghost images (no separate face fill).
-void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* x, double* y,
+// fp32: flux and edges hold float fields (the FP32 form's storage), read at
+// the same element offsets.
+void launch_update(const Geom& G, bool flat, bool fp32, int mode, const double* prim, double* x, double* y,
                    const double* flux, const double* edges, const double* tab, double a, double b,
                    double dt_host, const double* d_dt, double* out, int stage, hipStream_t s,
                    int img = 0);

@@ -614,6 +614,7 @@ __global__ __launch_bounds__(256) void k_c2p_list(Geom G, C2PParams cp, double* 
   const long n = *list_n;
   const long nwaves = (long)gridDim.x * 4;
   long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  long long ntaken = 0;
   double cfl_v = 0.0;
   for (long base = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; base < n; base += nwaves * 64) {
     const long idx = base + lane;
@@ -647,13 +648,18 @@ __global__ __launch_bounds__(256) void k_c2p_list(Geom G, C2PParams cp, double* 
     if (valid) {
       const float t0 = o0 * norm[NM_TSTD + 0] + norm[NM_TMEAN + 0];
       const double y0 = utot * (double)__exp10f(t0);
+      const double yg = isfinite(y0) ? y0 : -1.0;
       double cv = 0.0;
-      c2p_zone<MET>(G, cp, prim, cons, tab, t, isfinite(y0) ? y0 : -1.0, 0.0, cfl_partials != nullptr,
-                    st, cv);
+      if (cp.learned_only)
+        c2p_zone<MET>(G, cp, prim, cons, tab, t, -1.0, 0.0, cfl_partials != nullptr, st, cv, yg, nullptr,
+                      true);
+      else
+        c2p_zone<MET>(G, cp, prim, cons, tab, t, yg, 0.0, cfl_partials != nullptr, st, cv);
       cfl_v = fmax(cfl_v, cv);
+      ntaken += 1;
     }
   }
-  c2p_block_partials<false>(st, cfl_v, partials, cfl_partials, blockIdx.x, cp.run_acc);
+  c2p_block_partials<false>(st, cfl_v, partials, cfl_partials, blockIdx.x, cp.run_acc, ntaken);
 }
 
 }  // namespace mlp

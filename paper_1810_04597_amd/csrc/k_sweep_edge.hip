@@ -72,8 +72,8 @@ template <int DIR, class MET, typename T, int RC>
 __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict__ prim,
                                                const double* __restrict__ cons,
                                                const double* __restrict__ tab,
-                                               double* __restrict__ flux,
-                                               double* __restrict__ ctd) {
+                                               T* __restrict__ flux,
+                                               T* __restrict__ ctd) {
   int ext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) ext[a] = (a == DIR) ? G.n[a] + 5 : G.dims[a];
@@ -122,9 +122,9 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
   T fh[5], cd[6];
   face_body<DIR, RC>(q, bn, axis, m, gam, fh, cd);
 #pragma unroll
-  for (int q5 = 0; q5 < 5; ++q5) flux[(long)q5 * G.field + c] = double(fh[q5]);
+  for (int q5 = 0; q5 < 5; ++q5) flux[(long)q5 * G.field + c] = fh[q5];
 #pragma unroll
-  for (int q6 = 0; q6 < 6; ++q6) ctd[(long)q6 * G.field + c] = double(cd[q6]);
+  for (int q6 = 0; q6 < 6; ++q6) ctd[(long)q6 * G.field + c] = cd[q6];
 }
 
 // LDS-staged sweep for DIR = 1, 2 (stencils across rows or planes, which a
@@ -142,8 +142,8 @@ template <int DIR, int SF, class MET, typename T, int RC>
 __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __restrict__ prim,
                                                    const double* __restrict__ cons,
                                                    const double* __restrict__ tab,
-                                                   double* __restrict__ flux,
-                                                   double* __restrict__ ctd) {
+                                                   T* __restrict__ flux,
+                                                   T* __restrict__ ctd) {
   static_assert(DIR == 1 || DIR == 2, "x^2 and x^3 sweeps only");
   constexpr int TB = DIR == 1 ? 2 : 1;          // the transverse axis other than x^1
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
@@ -222,18 +222,19 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   T fh[5], cd[6];
   face_body_q<DIR, RC>([&](int v, int s) { return sh[v][cy + s][cx]; }, bn, axis, m, gam, fh, cd);
 #pragma unroll
-  for (int q5 = 0; q5 < 5; ++q5) flux[(long)q5 * G.field + c] = double(fh[q5]);
+  for (int q5 = 0; q5 < 5; ++q5) flux[(long)q5 * G.field + c] = fh[q5];
 #pragma unroll
-  for (int q6 = 0; q6 < 6; ++q6) ctd[(long)q6 * G.field + c] = double(cd[q6]);
+  for (int q6 = 0; q6 < 6; ++q6) ctd[(long)q6 * G.field + c] = cd[q6];
 }
 
-// Edge field of family E.  ctd_d / ctd_c: per-face data of the d and c sweeps.
+// Edge field of family E.  ctd_d / ctd_c: per-face data of the d and c sweeps
+// (stored in the arithmetic type T, as the edge field itself).
 template <int E, class MET, typename T, int RC>
 __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__ cons,
                                               const double* __restrict__ tab,
-                                              const double* __restrict__ ctd_d,
-                                              const double* __restrict__ ctd_c,
-                                              double* __restrict__ edge) {
+                                              const T* __restrict__ ctd_d,
+                                              const T* __restrict__ ctd_c,
+                                              T* __restrict__ edge) {
   constexpr int D = (E + 1) % 3, C = (E + 2) % 3;
   int ext[3];
 #pragma unroll
@@ -253,12 +254,13 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
 
   T qd[5][6], qc[6];
   {
-    const double* src[5] = {ctd_d, ctd_d + G.field, ctd_d + 2 * G.field, ctd_d + 3 * G.field,
-                            cons + (long)(C_BF1 + D) * G.field};
 #pragma unroll
-    for (int v = 0; v < 5; ++v)
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int s = 0; s < 6; ++s) qd[v][s] = T(src[v][b + (s - 2) * sc]);
+      for (int s = 0; s < 6; ++s) qd[v][s] = ctd_d[(long)v * G.field + b + (s - 2) * sc];
+    const double* bds = cons + (long)(C_BF1 + D) * G.field;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) qd[4][s] = T(bds[b + (s - 2) * sc]);
     const double* bcs = cons + (long)(C_BF1 + C) * G.field;
 #pragma unroll
     for (int s = 0; s < 6; ++s) qc[s] = T(bcs[b + (s - 2) * sd]);
@@ -269,11 +271,11 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
     constexpr int loc = E == 2 ? LOC_E3 : (E == 0 ? LOC_F2 : LOC_F1);
     m.load(tab, G.tab_plane, loc, G.tidx(ii[0], ii[1]));
   }
-  const T ee = edge_body<E, RC>(qd, qc, T(ctd_d[4 * G.field + b]), T(ctd_d[4 * G.field + b + sc]),
-                            T(ctd_d[5 * G.field + b]), T(ctd_d[5 * G.field + b + sc]),
-                            T(ctd_c[4 * G.field + b]), T(ctd_c[4 * G.field + b + sd]),
-                            T(ctd_c[5 * G.field + b]), T(ctd_c[5 * G.field + b + sd]), m);
-  edge[b] = double(ee);
+  const T ee = edge_body<E, RC>(qd, qc, ctd_d[4 * G.field + b], ctd_d[4 * G.field + b + sc],
+                            ctd_d[5 * G.field + b], ctd_d[5 * G.field + b + sc],
+                            ctd_c[4 * G.field + b], ctd_c[4 * G.field + b + sd],
+                            ctd_c[5 * G.field + b], ctd_c[5 * G.field + b + sd], m);
+  edge[b] = ee;
 }
 
 // LDS-staged edge field for families E = 0, 2, whose five d-face inputs are
@@ -284,9 +286,9 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
 template <int E, int SF, class MET, typename T, int RC>
 __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __restrict__ cons,
                                                       const double* __restrict__ tab,
-                                                      const double* __restrict__ ctd_d,
-                                                      const double* __restrict__ ctd_c,
-                                                      double* __restrict__ edge) {
+                                                      const T* __restrict__ ctd_d,
+                                                      const T* __restrict__ ctd_c,
+                                                      T* __restrict__ edge) {
   static_assert(E == 0 || E == 2, "families whose d-face inputs vary across rows");
   constexpr int D = (E + 1) % 3, C = (E + 2) % 3, B = 3 - C;   // B: the non-x^1 axis that is not C
   constexpr int SR = SF + 5, NRR = (SR + SF - 1) / SF;
@@ -312,8 +314,7 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   const long sd = G.stride(D), sc = G.stride(C);
   const int c0 = -3 + ct * SF;
   {
-    const double* src[5] = {ctd_d, ctd_d + G.field, ctd_d + 2 * G.field, ctd_d + 3 * G.field,
-                            cons + (long)(C_BF1 + D) * G.field};
+    const double* bds = cons + (long)(C_BF1 + D) * G.field;
     const int cmax = G.n[C] + NG - 1;
     T stage[5][NRR];
 #pragma unroll
@@ -321,7 +322,8 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
       if (ty + SF * rr < SR) {
         const long ro = base + (long)min(c0 - 2 + ty + SF * rr, cmax) * sc;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) stage[v][rr] = T(src[v][ro]);
+        for (int v = 0; v < 4; ++v) stage[v][rr] = ctd_d[(long)v * G.field + ro];
+        stage[4][rr] = T(bds[ro]);
       }
     }
 #pragma unroll
@@ -355,22 +357,25 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
     m.load(tab, G.tab_plane, loc, G.tidx(ii[0], ii[1]));
   }
   const T ee = edge_body_q<E, RC>([&](int v, int s2) { return sh[v][cy + s2][cx]; }, qc,
-                                  T(ctd_d[4 * G.field + b]), T(ctd_d[4 * G.field + b + sc]),
-                            T(ctd_d[5 * G.field + b]), T(ctd_d[5 * G.field + b + sc]),
-                            T(ctd_c[4 * G.field + b]), T(ctd_c[4 * G.field + b + sd]),
-                            T(ctd_c[5 * G.field + b]), T(ctd_c[5 * G.field + b + sd]), m);
-  edge[b] = double(ee);
+                                  ctd_d[4 * G.field + b], ctd_d[4 * G.field + b + sc],
+                                  ctd_d[5 * G.field + b], ctd_d[5 * G.field + b + sc],
+                                  ctd_c[4 * G.field + b], ctd_c[4 * G.field + b + sd],
+                                  ctd_c[5 * G.field + b], ctd_c[5 * G.field + b + sd], m);
+  edge[b] = ee;
 }
 
 // ------------------------------------------------------------------ launchers
 constexpr int SWEEP_SF = 4;   // face rows per workgroup of the staged sweeps
 constexpr int EDGE_SF = 4;    // edge rows per workgroup of the staged edge fields
 
+// The per-face results are stored in the arithmetic type T: a float field
+// occupies the first half of the bytes of a double field (same element
+// offsets, half the stride), so the FP32 form moves half the bytes.
 template <class MET, typename T, int RC>
 static void launch_sweep_t(int d, const Geom& G, const double* prim, const double* cons,
                            const double* tab, double* flux, double* ctd, hipStream_t s) {
-  double* fl = flux + (long)d * 5 * G.field;
-  double* cd = ctd + (long)d * 6 * G.field;
+  T* fl = reinterpret_cast<T*>(flux) + (long)d * 5 * G.field;
+  T* cd = reinterpret_cast<T*>(ctd) + (long)d * 6 * G.field;
   if (d == 0) {
     const long nf = (long)(G.n[0] + 5) * G.dims[1] * G.dims[2];
     const unsigned nb = MET::flat ? tile_blocks(G.n[0] + 5, G.dims[1], G.dims[2]) : (unsigned)((nf + 255) / 256);
@@ -389,9 +394,9 @@ template <class MET, typename T, int RC>
 static void launch_edge_t(int e, const Geom& G, const double* cons, const double* tab,
                           const double* ctd, double* edges, hipStream_t s) {
   const int d = (e + 1) % 3, c = (e + 2) % 3;
-  const double* cd = ctd + (long)d * 6 * G.field;
-  const double* cc = ctd + (long)c * 6 * G.field;
-  double* ed = edges + (long)e * G.field;
+  const T* cd = reinterpret_cast<const T*>(ctd) + (long)d * 6 * G.field;
+  const T* cc = reinterpret_cast<const T*>(ctd) + (long)c * 6 * G.field;
+  T* ed = reinterpret_cast<T*>(edges) + (long)e * G.field;
   if (e == 1) {
     hipLaunchKernelGGL((k_edge<1, MET, T, RC>), dim3(tile_blocks(G.n[0] + 5, G.n[2] + 5, G.n[1])),
                        dim3(256), 0, s, G, cons, tab, cd, cc, ed);

@@ -138,12 +138,14 @@ __device__ __forceinline__ double rk_store_rt(double* __restrict__ x, double* __
   return rk_store<3>(x, y, o, a, b, dt, L);
 }
 
-template <class MET, int DO>
+// FS: storage type of the fluxes and edge fields (double, or float in the
+// FP32 form), widened to double on load.
+template <class MET, int DO, typename FS>
 __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* __restrict__ prim,
                                                 double* __restrict__ x,
                                                 double* __restrict__ y,
-                                                const double* __restrict__ flux,
-                                                const double* __restrict__ edges,
+                                                const FS* __restrict__ flux,
+                                                const FS* __restrict__ edges,
                                                 const double* __restrict__ tab, double a, double b,
                                                 double dt_host, const double* __restrict__ d_dt,
                                                 double* __restrict__ out, int stage) {
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
     double L = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const double* fp = flux + ((long)d * 5 + q) * G.field + c;
+      const FS* fp = flux + ((long)d * 5 + q) * G.field + c;
       const long st = G.stride(d);
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = fp[(s - 3) * st];
@@ -190,8 +192,8 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
 #pragma unroll
   for (int nd = 0; nd < 3; ++nd) {
     const int d1 = (nd + 1) % 3, d2 = (nd + 2) % 3;
-    const double* e2 = edges + (long)d2 * G.field + c;
-    const double* e1 = edges + (long)d1 * G.field + c;
+    const FS* e2 = edges + (long)d2 * G.field + c;
+    const FS* e1 = edges + (long)d1 * G.field + c;
     const long s1 = G.stride(d1), s2 = G.stride(d2);
 #pragma unroll
     for (int s = 0; s < 6; ++s) f[s] = e2[(s - 3) * s1];
@@ -215,12 +217,12 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
 // segment instead of six times; x^1 and x^2 stencils are read per plane.
 constexpr int KZ = 16;
 
-template <class MET, int ST, int DO>
+template <class MET, int ST, int DO, typename FS>
 __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restrict__ prim,
                                                    double* __restrict__ x,
                                                    double* __restrict__ y,
-                                                   const double* __restrict__ flux,
-                                                   const double* __restrict__ edges,
+                                                   const FS* __restrict__ flux,
+                                                   const FS* __restrict__ edges,
                                                    const double* __restrict__ tab, double a,
                                                    double b, double dt_host,
                                                    const double* __restrict__ d_dt, int img) {
@@ -235,10 +237,10 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
   const double dt = dt_host > 0.0 ? dt_host : *d_dt;
   const long sx = 1, sy = G.pitch, sz = G.plane;
   const double idx0 = 1.0 / G.dx[0], idx1 = 1.0 / G.dx[1], idx2 = 1.0 / G.dx[2];
-  const double* fz = flux + 2L * 5 * G.field;   // x^3-sweep fluxes
-  const double* e1 = edges;                     // E_1 (offsets in x^2, x^3)
-  const double* e2 = edges + G.field;           // E_2 (offsets in x^3, x^1)
-  const double* e3 = edges + 2 * G.field;       // E_3 (offsets in x^1, x^2)
+  const FS* fz = flux + 2L * 5 * G.field;       // x^3-sweep fluxes
+  const FS* e1 = edges;                         // E_1 (offsets in x^2, x^3)
+  const FS* e2 = edges + G.field;               // E_2 (offsets in x^3, x^1)
+  const FS* e3 = edges + 2 * G.field;           // E_3 (offsets in x^1, x^2)
   // windows along x^3: w[s] holds stored index k - 3 + s
   double wf[5][6], w1[6], w2[6];
   long c = G.idx(i, j, k0);
@@ -260,8 +262,8 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       double L = 0.0;
-      const double* fx = flux + (long)q * G.field + c;
-      const double* fy = flux + (5L + q) * G.field + c;
+      const FS* fx = flux + (long)q * G.field + c;
+      const FS* fy = flux + (5L + q) * G.field + c;
 #pragma unroll
       for (int s = 0; s < 6; ++s) f[s] = fx[(s - 3) * sx];
       L = L - fd_deriv_o<DO>(f, idx0);
@@ -320,7 +322,8 @@ constexpr int C2P_MIN_WAVES = MET::flat ? 5 : 1;
 
 // With list != nullptr (learned guess) zones whose warm start has a relative
 // residual above cp.defer_tol are left untouched and appended to list (their
-// order is irrelevant: each is inverted on its own in the learned-guess pass).
+// order is irrelevant: each is inverted on its own in the learned-guess pass);
+// with cp.defer_all every zone is (one list reservation per wavefront).
 template <class MET>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C2P_MIN_WAVES<MET>))) void k_c2p(Geom G, C2PParams cp, double* __restrict__ prim,
                                              double* __restrict__ cons,
@@ -332,7 +335,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(C2P_MIN_WAV
   const long t = flat_thread();
   long long st[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double cfl_v = 0.0;
-  if (t < (long)G.n[0] * G.n[1] * G.n[2]) {
+  const bool in = t < (long)G.n[0] * G.n[1] * G.n[2];
+  if (list && cp.defer_all) {
+    const unsigned long long mask = __ballot(in);
+    const int lane = threadIdx.x & 63;
+    const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+    int base = 0;
+    if (lane == 0) base = atomicAdd(list_n, __popcll(mask));
+    base = __shfl(base, 0, 64);
+    if (in) list[base + rank] = (int)strip_zone_order<C2P_STRIP>(G, t);
+  } else if (in) {
     const long z = strip_zone_order<C2P_STRIP>(G, t);
     const double defer = list ? cp.defer_tol : 0.0;
     double yl = -1.0;
@@ -723,9 +735,9 @@ void launch_bc_faces(const Geom& G, const BCSpec& bc, double* cons, hipStream_t 
   hipLaunchKernelGGL(k_bc_faces, dim3(nblk(ghost_count(G, bc.bc[2] == 2))), dim3(256), 0, s, G, bc, cons);
 }
 
-template <int DO>
+template <int DO, typename FS>
 static void launch_update_o(const Geom& G, bool flat, int mode, const double* prim, double* x,
-                            double* y, const double* flux, const double* edges,
+                            double* y, const FS* flux, const FS* edges,
                             const double* tab, double a, double b, double dt_host,
                             const double* d_dt, double* out, int stage, hipStream_t s, int img) {
   const unsigned nb = zone_blocks(G);
@@ -733,29 +745,42 @@ static void launch_update_o(const Geom& G, bool flat, int mode, const double* pr
     const long nseg = (G.n[2] + KZ - 1) / KZ;
     const unsigned ng = nblk((long)G.n[0] * G.n[1] * nseg);
     if (stage == 1)
-      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 1, DO>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 1, DO, FS>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
                          flux, edges, tab, a, b, dt_host, d_dt, img);
     else if (stage == 2)
-      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 2, DO>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 2, DO, FS>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
                          flux, edges, tab, a, b, dt_host, d_dt, img);
     else
-      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 3, DO>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 3, DO, FS>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
                          flux, edges, tab, a, b, dt_host, d_dt, img);
   } else if (flat)
-    hipLaunchKernelGGL((k_update<FlatMet<double>, DO>), dim3(nb), dim3(256), 0, s, G, mode, prim, x, y,
+    hipLaunchKernelGGL((k_update<FlatMet<double>, DO, FS>), dim3(nb), dim3(256), 0, s, G, mode, prim, x, y,
                        flux, edges, tab, a, b, dt_host, d_dt, out, stage);
   else
-    hipLaunchKernelGGL((k_update<TabMet<double>, DO>), dim3(nb), dim3(256), 0, s, G, mode, prim, x, y,
+    hipLaunchKernelGGL((k_update<TabMet<double>, DO, FS>), dim3(nb), dim3(256), 0, s, G, mode, prim, x, y,
                        flux, edges, tab, a, b, dt_host, d_dt, out, stage);
 }
 
-void launch_update(const Geom& G, bool flat, int mode, const double* prim, double* x, double* y,
+template <typename FS>
+static void launch_update_s(const Geom& G, bool flat, int mode, const double* prim, double* x, double* y,
+                            const FS* flux, const FS* edges, const double* tab, double a, double b,
+                            double dt_host, const double* d_dt, double* out, int stage, hipStream_t s,
+                            int img) {
+  if (G.dorder == 4)
+    launch_update_o<4, FS>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img);
+  else
+    launch_update_o<6, FS>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img);
+}
+
+void launch_update(const Geom& G, bool flat, bool fp32, int mode, const double* prim, double* x, double* y,
                    const double* flux, const double* edges, const double* tab, double a, double b,
                    double dt_host, const double* d_dt, double* out, int stage, hipStream_t s, int img) {
-  if (G.dorder == 4)
-    launch_update_o<4>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img);
+  if (fp32)
+    launch_update_s<float>(G, flat, mode, prim, x, y, reinterpret_cast<const float*>(flux),
+                           reinterpret_cast<const float*>(edges), tab, a, b, dt_host, d_dt, out, stage, s, img);
   else
-    launch_update_o<6>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img);
+    launch_update_s<double>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s,
+                            img);
 }
 
 // d_dt[0]: dt of the last step, d_dt[1]: time; src: where the device dt was read

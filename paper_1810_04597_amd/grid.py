@@ -238,6 +238,11 @@ class Grid:
         the rest of the slow zones in a second, compact pass (0: off)."""
         self._call(self.lib.grmhd_set_newton_split, self.h, int(iters))
 
+    def set_learned_guess(self, defer_tol=1e-2, start=L.LEARNED_BEST):
+        """Learned-guess pass policy: defer_tol (0: every zone) and start
+        (L.LEARNED_BEST or L.LEARNED_ONLY)."""
+        self._call(self.lib.grmhd_set_learned_guess, self.h, float(defer_tol), int(start))
+
     def set_profiling(self, on=True):
         self._call(self.lib.grmhd_set_profiling, self.h, 1 if on else 0)
 

@@ -238,3 +238,48 @@ def test_learned_start_wins_when_warm_start_is_poor():
         learned["n_mlp_fallback"]))
     assert learned["n_mlp_chosen"] > g.zones // 2
     assert learned["newton_iters_sum"] < warm["newton_iters_sum"]
+
+
+@gpu
+def test_network_start_beats_cold_start_on_the_torus():
+    """What the trained network itself gains on its workload, the Kerr-Schild
+    torus (64 x 32 x 32): the torus' conserved state inverted with every zone
+    started from the network's guess alone (every zone deferred to the
+    learned pass, no warm candidate) against every zone from the method's
+    cold start Gamma U.  Both reach the same primitives; the network's start
+    needs fewer Newton iterations.  With the default policy and the exact
+    previous primitives as the warm start, no zone is deferred."""
+    _torch()
+    from workloads.torus import torus
+    from paper_1810_04597_amd.grid import Grid
+    from paper_1810_04597_amd import _lib as L
+    from helpers import max_rel
+    g0, d0, G0 = _grid()
+    _train(G0, 1 << 18, 4)
+    flat, norm = G0.mlp_get_weights()
+    g, d, tab = torus(64, 32, 32)
+    res, prims = {}, {}
+    for name, guess in (("cold", L.GUESS_COLD), ("network", L.GUESS_MLP), ("default", L.GUESS_MLP)):
+        G = Grid(g, tables=tab, guess=guess)
+        if guess == L.GUESS_MLP:
+            G.mlp_set_weights(flat, norm)
+            if name == "network":
+                G.set_learned_guess(0.0, L.LEARNED_ONLY)
+        G.curl_potential(d)
+        G.set_primitives(d)
+        G.reset_run_counters()
+        assert G.cons2prim() == 0
+        res[name] = G.diagnostics()
+        prims[name] = G.to_numpy("prim", interior=True)
+        G.close()
+    c, m, w = res["cold"], res["network"], res["default"]
+    print("torus 64x32x32 inversion: Newton iterations cold %d (max %d), network %d (max %d), "
+          "network chosen %d fallbacks %d of %d zones; default policy deferred %d" % (
+              c["newton_iters_sum"], c["newton_iters_max"], m["newton_iters_sum"], m["newton_iters_max"],
+              m["run_mlp_chosen"], m["run_mlp_fallback"], g.zones, w["run_mlp_deferred"]))
+    assert m["run_mlp_deferred"] == g.zones and m["run_mlp_chosen"] == g.zones
+    assert m["newton_iters_sum"] < c["newton_iters_sum"]
+    assert w["run_mlp_deferred"] == 0
+    e = max_rel(prims["network"], prims["cold"], ("rho", "u1", "u3", "p"))
+    e["u2"] = float(np.max(np.abs(prims["network"]["u2"] - prims["cold"]["u2"])))
+    assert max(e.values()) < 1e-9, e
