@@ -23,10 +23,13 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
 
 
 # The sweep/edge kernels run on finite states only (the inversion, built
-# without these flags, keeps non-finite values out of the primitives), so
-# their min/max need no signalling-NaN quieting: IEEE mode off removes
-# one canonicalising instruction per loaded min/max operand.
-FILE_FLAGS = {"k_sweep_edge.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
+# without this flag, keeps non-finite values out of the primitives), so
+# their min/max need no signalling-NaN quieting: assuming no NaNs removes the
+# canonicalising instruction per loaded min/max operand.  (Turning the
+# hardware IEEE mode off as well did the same but kept the device library's
+# functions -- reciprocal square root, work-item and group ids -- from being
+# inlined into these kernels: a function call for each.)
+FILE_FLAGS = {"k_sweep_edge.hip": ["-fno-honor-nans"]}
 
 
 def sources():
