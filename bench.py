@@ -223,16 +223,17 @@ def precision_report(args):
 
 
 def recon_report(args):
-    """The three reconstructions on the turbulent box: each grid starts from
-    the same seeded data, runs args.warmup steps, then args.steps timed RK3
-    steps with the device CFL step; per-kernel HIP-event averages."""
+    """The reconstructions on the turbulent box: each grid starts from the
+    same seeded data (MP7 on a grid with six ghost layers, the others on
+    five), runs args.warmup steps, then args.steps timed RK3 steps with the
+    device CFL step; per-kernel HIP-event averages."""
     import torch
     from workloads import box
     from paper_1810_04597_amd.grid import Grid
     n = args.n
-    g, d = box.turbulent_box(n)
     res = {}
-    for name in ("mp5", "weno5", "plm"):
+    for name in ("mp5", "weno5", "plm", "mp7"):
+        g, d = box.turbulent_box(n, ng=6 if name == "mp7" else 5)
         G = Grid(g, recon=name)
         G.curl_potential(d)
         G.set_primitives(d)

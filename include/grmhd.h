@@ -66,8 +66,10 @@ enum { GRMHD_GUESS_WARM = 0, GRMHD_GUESS_COLD = 1, GRMHD_GUESS_MLP = 2 };
  * f-2 .. f+3 around face f+1/2: MP5 (Suresh & Huynh 1997, point-value
  * interpolant, zero limiter tolerance; the default), WENO5 (Jiang & Shu 1996
  * indicators, point-value form, eps = 1e-6), PLM with the monotonized-central
- * limiter (second order, the lower-order member). */
-enum { GRMHD_RECON_MP5 = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_PLM = 2 };
+ * limiter (second order, the lower-order member); MP7 (the same limiter on
+ * the degree-6 interpolant of the seven cells f-3 .. f+3, seventh order;
+ * eight-cell stencils f-3 .. f+4, so it needs ng = 6). */
+enum { GRMHD_RECON_MP5 = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_PLM = 2, GRMHD_RECON_MP7 = 3 };
 enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_TABLE_AXISYM = 1 };
 
 /* Number of float64 components of an axisymmetric metric table per (j, i):
@@ -81,14 +83,15 @@ enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_TABLE_AXISYM = 1 };
 
 typedef struct {
   int32_t n[3];            /* interior zones n1, n2, n3 (each >= 1)              */
-  int32_t ng;              /* ghost layers, must be 5 (MP5 + 6th-order D)        */
+  int32_t ng;              /* ghost layers: 5 (MP5/WENO5/PLM + 6th-order D), or 6
+                              (required by MP7; allowed for the others)        */
   int32_t coord;           /* GRMHD_CART | GRMHD_LOGSPH (floors use r = e^{x^1}) */
   int32_t bc[6];           /* -x1,+x1,-x2,+x2,-x3,+x3; periodic in pairs; axis
-                              only on x^2 (n2 >= 6) with periodic x^3, n3 even */
+                              only on x^2 (n2 >= ng+1) with periodic x^3, n3 even */
   int32_t precision;       /* GRMHD_FP64 | GRMHD_FP32_FLUX                       */
   int32_t c2p_guess;       /* GRMHD_GUESS_WARM | _COLD | _MLP                     */
   int32_t newton_maxit;    /* e.g. 50                                             */
-  int32_t recon;           /* GRMHD_RECON_MP5 (0) | _WENO5 | _PLM                 */
+  int32_t recon;           /* GRMHD_RECON_MP5 (0) | _WENO5 | _PLM | _MP7          */
   double x0[3];            /* lower interior edge in code coordinates            */
   double dx[3];            /* uniform spacing (> 0)                              */
   double gamma_ad;         /* ideal-gas index (> 1)                              */

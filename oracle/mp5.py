@@ -44,7 +44,13 @@ def unlimited(qm2, qm1, q0, qp1, qp2):
 
 def mp5(qm2, qm1, q0, qp1, qp2):
     """Limited left state at the face between q0 and qp1."""
-    ql = unlimited(qm2, qm1, q0, qp1, qp2)
+    return mp_limit(unlimited(qm2, qm1, q0, qp1, qp2), qm2, qm1, q0, qp1, qp2)
+
+
+def mp_limit(ql, qm2, qm1, q0, qp1, qp2):
+    """Steps 2-8 above: the monotonicity-preserving limit of an unlimited
+    face value ql from q_{j-2..j+2} (the same limiter serves every order of
+    the unlimited value)."""
     qmp = q0 + minmod(qp1 - q0, 4.0 * (q0 - qm1))
     accept = (ql - q0) * (ql - qmp) <= 0.0
     dm1 = qm2 - 2.0 * qm1 + q0

@@ -22,6 +22,15 @@ at face j+1/2 from q_{j-2}..q_{j+2}:
   * alpha_k = d_k / (eps + b_k)^2, w_k = alpha_k / sum alpha, with
     eps = 1e-6 (the published value), and qL = sum w_k p_k.
 
+MP7 -- the seventh-order member of the monotonicity-preserving family
+(Suresh & Huynh 1997): the unlimited value is the degree-6 Lagrange
+interpolant of the point values q_{j-3..j+3} at x_{j+1/2},
+  qL7 = (-5 q_{j-3} + 42 q_{j-2} - 175 q_{j-1} + 700 q_j + 525 q_{j+1}
+         - 70 q_{j+2} + 7 q_{j+3}) / 1024,
+limited by the MP limiter of MP5 (its bounds from q_{j-2..j+2}).  Its
+stencil reaches three cells past the face on each side, so a grid using it
+carries six ghost layers.
+
 PLM-MC -- piecewise linear reconstruction with the monotonized-central
 slope limiter (van Leer 1977), the lower-order member:
   qL(j+1/2) = q_j + 1/2 MC(q_j - q_{j-1}, q_{j+1} - q_j),
@@ -36,7 +45,22 @@ from . import mp5 as _mp5
 
 WENO_EPS = 1e-6
 WENO_D = (1.0 / 16.0, 10.0 / 16.0, 5.0 / 16.0)
-METHODS = ("mp5", "weno5", "plm")
+METHODS = ("mp5", "weno5", "plm", "mp7")
+# ghost layers each method needs: its stencil's reach past the face (3 for
+# the five- and six-cell stencils, 4 for MP7's eight) plus the two further
+# faces of the sixth-order flux derivative
+NG_OF = {"mp5": 5, "weno5": 5, "plm": 5, "mp7": 6}
+
+
+def mp7_unlimited(qm3, qm2, qm1, q0, qp1, qp2, qp3):
+    """Degree-6 interpolant of q_{j-3..j+3} at the face between q0 and qp1."""
+    return (-5.0 * qm3 + 42.0 * qm2 - 175.0 * qm1 + 700.0 * q0 + 525.0 * qp1
+            - 70.0 * qp2 + 7.0 * qp3) / 1024.0
+
+
+def mp7(qm3, qm2, qm1, q0, qp1, qp2, qp3):
+    """MP7 left state at the face between q0 and qp1."""
+    return _mp5.mp_limit(mp7_unlimited(qm3, qm2, qm1, q0, qp1, qp2, qp3), qm2, qm1, q0, qp1, qp2)
 
 
 def weno5_candidates(qm2, qm1, q0, qp1, qp2):
@@ -86,4 +110,7 @@ def face_states(q, d, lo, hi, g, take, method="mp5"):
                 weno5(c(3), c(2), c(1), c(0), c(-1)))
     if method == "plm":
         return plm(c(-1), c(0), c(1)), plm(c(2), c(1), c(0))
+    if method == "mp7":
+        return (mp7(c(-3), c(-2), c(-1), c(0), c(1), c(2), c(3)),
+                mp7(c(4), c(3), c(2), c(1), c(0), c(-1), c(-2)))
     raise ValueError("unknown reconstruction %r" % (method,))

@@ -33,7 +33,7 @@ import numpy as np
 
 from . import fd
 from .fd import take, deriv, interp
-from .recon import face_states, METHODS as RECON_METHODS
+from .recon import face_states, METHODS as RECON_METHODS, NG_OF
 from .physics import state, flux, cons, speeds, prim2cons
 from .hll import hll_speeds, hll_flux
 from .c2p import newton, warm_guess
@@ -107,7 +107,8 @@ class Solver:
     reconstruction, face physics, HLL flux and edge field are evaluated in
     float32 from float32-rounded inputs and widened to float64 afterwards
     (derivatives, sources, RK combine and inversion stay float64).
-    recon: interface reconstruction, "mp5" (default), "weno5" or "plm".
+    recon: interface reconstruction, "mp5" (default), "weno5", "plm" or
+    "mp7" (the last on grids with six ghost layers).
     deriv_order: order of the staggered derivative and interpolation, 6
     (default) or 4; one order serves the flux derivative, the induction
     equation, the curl of the vector potential, the centred field and div B,
@@ -118,6 +119,8 @@ class Solver:
             raise ValueError("unknown reconstruction %r" % (recon,))
         if deriv_order not in (4, 6):
             raise ValueError("deriv_order must be 4 or 6")
+        if grid.ng < NG_OF[recon]:
+            raise ValueError("%s needs %d ghost layers" % (recon, NG_OF[recon]))
         self.recon = recon
         self.order = deriv_order
         self.grid = grid

@@ -11,8 +11,8 @@ BC_PERIODIC, BC_OUTFLOW, BC_AXIS = 0, 1, 2
 FP64, FP32_FLUX = 0, 1
 GUESS_WARM, GUESS_COLD, GUESS_MLP = 0, 1, 2
 LEARNED_BEST, LEARNED_ONLY = 0, 1
-RECON_MP5, RECON_WENO5, RECON_PLM = 0, 1, 2
-RECON = {"mp5": RECON_MP5, "weno5": RECON_WENO5, "plm": RECON_PLM}
+RECON_MP5, RECON_WENO5, RECON_PLM, RECON_MP7 = 0, 1, 2, 3
+RECON = {"mp5": RECON_MP5, "weno5": RECON_WENO5, "plm": RECON_PLM, "mp7": RECON_MP7}
 METRIC_MINKOWSKI, METRIC_TABLE_AXISYM = 0, 1
 METRIC_NCOMP = 88
 

@@ -22,7 +22,7 @@ static_assert(sizeof(grmhd_grid_desc) == 184 && offsetof(grmhd_grid_desc, recon)
 static_assert(sizeof(grmhd_diag) == 272 && offsetof(grmhd_diag, run_c2p_fail) == 216,
               "grmhd_diag layout, which the Python binding mirrors");
 static_assert(GRMHD_RECON_MP5 == grmhd::RECON_MP5 && GRMHD_RECON_WENO5 == grmhd::RECON_WENO5 &&
-                  GRMHD_RECON_PLM == grmhd::RECON_PLM,
+                  GRMHD_RECON_PLM == grmhd::RECON_PLM && GRMHD_RECON_MP7 == grmhd::RECON_MP7,
               "reconstruction codes of the ABI and the kernels agree");
 #include "grmhd_mlp.hpp"
 
@@ -114,7 +114,7 @@ struct grmhd_grid {
   double* d_dt = nullptr;        // [0] dt of the current step, [1] time, [2] CFL dt of the state
   bool next_dt_valid = false;    // d_dt[2] holds the CFL dt of the current primitives
   int* d_list_n = nullptr;       // number of zones deferred to the learned-guess pass
-  bool img = false;              // periodic box with n >= 2 NG: ghosts written as images
+  bool img = false;              // periodic box with n >= 2 ng: ghosts written as images
   double* d_part = nullptr;      // per-block partials (cfl, diagnostics)
   long long* d_spart = nullptr;  // per-block inversion statistics
   long long* d_stats = nullptr;  // reduced inversion statistics (8)
@@ -181,7 +181,8 @@ int validate(const grmhd_grid_desc* d) {
     if (!(d->dx[a] > 0.0) || !std::isfinite(d->dx[a])) return fail(GRMHD_EINVAL, "dx must be > 0");
     if (!std::isfinite(d->x0[a])) return fail(GRMHD_EINVAL, "x0 not finite");
   }
-  if (d->ng != NG) return fail(GRMHD_EINVAL, "ng must be 5 (MP5 stencil + sixth-order derivative)");
+  if (d->ng != 5 && d->ng != 6)
+    return fail(GRMHD_EINVAL, "ng must be 5 (five- and six-cell stencils + sixth-order derivative) or 6");
   if (d->coord != GRMHD_CART && d->coord != GRMHD_LOGSPH) return fail(GRMHD_EINVAL, "bad coord");
   for (int s = 0; s < 6; ++s)
     if (d->bc[s] < 0 || d->bc[s] > 2) return fail(GRMHD_EINVAL, "bad boundary code");
@@ -195,7 +196,7 @@ int validate(const grmhd_grid_desc* d) {
   if (d->bc[2] == GRMHD_BC_AXIS) {
     if (d->bc[4] != GRMHD_BC_PERIODIC) return fail(GRMHD_EINVAL, "axis needs periodic x^3");
     if (d->n[2] % 2 != 0) return fail(GRMHD_EINVAL, "axis needs an even n3");
-    if (d->n[1] < NG + 1) return fail(GRMHD_EINVAL, "axis needs n2 >= 6");
+    if (d->n[1] < d->ng + 1) return fail(GRMHD_EINVAL, "axis needs n2 >= ng + 1");
   }
   if (!(d->gamma_ad > 1.0)) return fail(GRMHD_EINVAL, "gamma_ad must be > 1");
   if (!(d->cfl > 0.0)) return fail(GRMHD_EINVAL, "cfl must be > 0");
@@ -206,8 +207,10 @@ int validate(const grmhd_grid_desc* d) {
   if (!(d->newton_tol > 0.0)) return fail(GRMHD_EINVAL, "newton_tol must be > 0");
   if (d->rho_fl_a < 0.0 || d->p_fl_a < 0.0) return fail(GRMHD_EINVAL, "negative floor");
   if (d->w_max != 0.0 && !(d->w_max > 1.0)) return fail(GRMHD_EINVAL, "w_max must be 0 or > 1");
-  if (d->recon != GRMHD_RECON_MP5 && d->recon != GRMHD_RECON_WENO5 && d->recon != GRMHD_RECON_PLM)
+  if (d->recon != GRMHD_RECON_MP5 && d->recon != GRMHD_RECON_WENO5 && d->recon != GRMHD_RECON_PLM &&
+      d->recon != GRMHD_RECON_MP7)
     return fail(GRMHD_EINVAL, "bad recon");
+  if (d->recon == GRMHD_RECON_MP7 && d->ng != 6) return fail(GRMHD_EINVAL, "MP7 needs ng = 6");
   if (d->deriv_order != 0 && d->deriv_order != 4 && d->deriv_order != 6)
     return fail(GRMHD_EINVAL, "deriv_order must be 0, 4 or 6");
   if (d->reserved != 0) return fail(GRMHD_EINVAL, "reserved must be 0");
@@ -215,11 +218,11 @@ int validate(const grmhd_grid_desc* d) {
 }
 
 void make_layout(const grmhd_grid_desc& d, grmhd_layout& L, Geom& G) {
-  for (int a = 0; a < 3; ++a) L.dims[a] = d.n[a] + 2 * NG;
+  for (int a = 0; a < 3; ++a) L.dims[a] = d.n[a] + 2 * d.ng;
   L.pitch = round_up(L.dims[0], 16);               // 128-byte rows
   L.plane = L.pitch * L.dims[1];
   L.field = round_up(L.plane * L.dims[2], 32);     // 256-byte field starts
-  L.offset = (long)NG * L.plane + (long)NG * L.pitch + NG;
+  L.offset = (long)d.ng * L.plane + (long)d.ng * L.pitch + d.ng;
   L.prim_doubles = NPRIM * L.field;
   L.cons_doubles = NCONS * L.field;
   L.edge_doubles = L.field;
@@ -236,6 +239,7 @@ void make_layout(const grmhd_grid_desc& d, grmhd_layout& L, Geom& G) {
   G.off = L.offset;
   G.gam = d.gamma_ad;
   G.dorder = d.deriv_order == 4 ? 4 : 6;
+  G.ng = d.ng;
   G.tab_n1 = (int)L.dims[0];
   G.tab_plane = L.dims[0] * L.dims[1];
 }
@@ -290,7 +294,7 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** 
   for (int s = 0; s < 6; ++s) h->bc.bc[s] = desc->bc[s];
   h->img = true;
   for (int s = 0; s < 6; ++s) h->img = h->img && desc->bc[s] == GRMHD_BC_PERIODIC;
-  for (int d = 0; d < 3; ++d) h->img = h->img && desc->n[d] >= 2 * NG;
+  for (int d = 0; d < 3; ++d) h->img = h->img && desc->n[d] >= 2 * desc->ng;
   h->stream = (hipStream_t)hip_stream;
   h->nblk = zone_blocks(h->G);
   // the device address of the no-allocation scratch, once per device; a

@@ -40,7 +40,7 @@ __device__ __forceinline__ void zone_of(const Geom& G, long t, int& i, int& j, i
 }
 
 // Periodic ghost images of interior element (i, j, k) when every direction is
-// periodic and every n >= 2 NG: per direction the offset 0 and, within NG of
+// periodic and every n >= 2 ng: per direction the offset 0 and, within ng of
 // a boundary, +-n.  Writes v[f] to field fields[f] of each image other than
 // the element itself (at most seven).
 template <int NF>
@@ -52,8 +52,8 @@ __device__ __forceinline__ void write_images(const Geom& G, double* __restrict__
   for (int d = 0; d < 3; ++d) {
     off[d][0] = 0;
     cnt[d] = 1;
-    if (x[d] < NG) { off[d][1] = G.n[d]; cnt[d] = 2; }
-    else if (x[d] >= G.n[d] - NG) { off[d][1] = -G.n[d]; cnt[d] = 2; }
+    if (x[d] < G.ng) { off[d][1] = G.n[d]; cnt[d] = 2; }
+    else if (x[d] >= G.n[d] - G.ng) { off[d][1] = -G.n[d]; cnt[d] = 2; }
   }
   for (int a = 0; a < cnt[0]; ++a)
     for (int b = 0; b < cnt[1]; ++b)

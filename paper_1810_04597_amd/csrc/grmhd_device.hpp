@@ -27,7 +27,7 @@ using std::fmin;
 using std::fmax;
 using std::fabs;
 
-constexpr int NG = 5;
+constexpr int NG = 5;      // default ghost width (MP5 stencil + sixth-order derivative)
 constexpr int NPRIM = 8;   // rho, u1, u2, u3, p, B1, B2, B3
 constexpr int NCONS = 8;   // D, S1, S2, S3, tau, Bf1, Bf2, Bf3
 enum { P_RHO = 0, P_U1 = 1, P_U2 = 2, P_U3 = 3, P_P = 4, P_B1 = 5, P_B2 = 6, P_B3 = 7 };
@@ -47,21 +47,22 @@ constexpr int NCOMP_TAB = DER_BASE + 20;
 // Grid geometry as kernels see it (passed by value).
 struct Geom {
   int n[3];            // interior zones
-  int dims[3];         // n + 2 NG
+  int dims[3];         // n + 2 ng
   long pitch, plane;   // element strides of x^2 and x^3
   long field;          // elements between fields of a group
   long off;            // offset of interior (0,0,0)
   double dx[3], x0[3];
   double gam;          // ideal-gas index
   int dorder;          // order of the staggered derivative and interpolation (6 or 4)
-  int tab_n1;          // metric table row length (n1 + 2 NG)
+  int ng;              // ghost layers (5, or 6 for the eight-cell MP7 stencil)
+  int tab_n1;          // metric table row length (n1 + 2 ng)
   long tab_plane;      // metric table component stride
   __host__ __device__ long idx(int i, int j, int k) const {
     return off + (long)k * plane + (long)j * pitch + i;
   }
   __host__ __device__ long stride(int d) const { return d == 0 ? 1L : (d == 1 ? pitch : plane); }
   __host__ __device__ long tidx(int i, int j) const {
-    return (long)(j + NG) * tab_n1 + (i + NG);
+    return (long)(j + ng) * tab_n1 + (i + ng);
   }
 };
 
@@ -111,13 +112,11 @@ GR_HD T minmod4(T w, T x, T y, T z) {
   return fmax(lo, T(0)) + fmin(hi, T(0));
 }
 
-// Limited left state at the face between q0 and qp1 from q_{j-2..j+2}.
+// Monotonicity-preserving limit (Suresh & Huynh 1997) of an unlimited value
+// ql at the face between q0 and qp1, from q_{j-2..j+2}; the same limiter
+// serves the fifth- and the seventh-order interpolant.
 template <typename T>
-GR_HD T mp5(T qm2, T qm1, T q0, T qp1, T qp2) {
-  // interpolant (3, -20, 90, 60, -5)/128 with the power-of-two scale folded
-  // into the weights (the same value: scaling by 2^-7 commutes with rounding)
-  const T ql = T(3.0 / 128) * qm2 - T(20.0 / 128) * qm1 + T(90.0 / 128) * q0 +
-               T(60.0 / 128) * qp1 - T(5.0 / 128) * qp2;
+GR_HD T mp_limit(T ql, T qm2, T qm1, T q0, T qp1, T qp2) {
   const T qmp = q0 + minmod(qp1 - q0, T(4) * (q0 - qm1));
   if ((ql - q0) * (ql - qmp) <= T(0)) return ql;
   const T dm1 = qm2 - T(2) * qm1 + q0;
@@ -136,6 +135,27 @@ GR_HD T mp5(T qm2, T qm1, T q0, T qp1, T qp2) {
   // qmax - ql); both bounding intervals contain q0, so qmin <= qmax and the
   // median is the clamp (equal up to the rounding of ql + (qmin - ql)).
   return fmin(fmax(ql, qmin), qmax);
+}
+
+// Limited left state at the face between q0 and qp1 from q_{j-2..j+2}.
+template <typename T>
+GR_HD T mp5(T qm2, T qm1, T q0, T qp1, T qp2) {
+  // interpolant (3, -20, 90, 60, -5)/128 with the power-of-two scale folded
+  // into the weights (the same value: scaling by 2^-7 commutes with rounding)
+  const T ql = T(3.0 / 128) * qm2 - T(20.0 / 128) * qm1 + T(90.0 / 128) * q0 +
+               T(60.0 / 128) * qp1 - T(5.0 / 128) * qp2;
+  return mp_limit(ql, qm2, qm1, q0, qp1, qp2);
+}
+
+// MP7: the degree-6 interpolant of q_{j-3..j+3} at the face,
+// (-5, 42, -175, 700, 525, -70, 7)/1024 (power-of-two scale folded into the
+// weights), limited as MP5.
+template <typename T>
+GR_HD T mp7(T qm3, T qm2, T qm1, T q0, T qp1, T qp2, T qp3) {
+  const T ql = T(-5.0 / 1024) * qm3 + T(42.0 / 1024) * qm2 - T(175.0 / 1024) * qm1 +
+               T(700.0 / 1024) * q0 + T(525.0 / 1024) * qp1 - T(70.0 / 1024) * qp2 +
+               T(7.0 / 1024) * qp3;
+  return mp_limit(ql, qm2, qm1, q0, qp1, qp2);
 }
 
 // Left and right states at face f+1/2 from the six cells f-2 .. f+3 (c[0..5]).
@@ -179,12 +199,21 @@ GR_HD T plm_mc(T qm1, T q0, T qp1) {
   return q0 + T(0.5) * slope;
 }
 
-// Interface reconstructions: RECON_MP5 (default), RECON_WENO5, RECON_PLM.
-constexpr int RECON_MP5 = 0, RECON_WENO5 = 1, RECON_PLM = 2;
+// Interface reconstructions: RECON_MP5 (default), RECON_WENO5, RECON_PLM,
+// RECON_MP7.
+constexpr int RECON_MP5 = 0, RECON_WENO5 = 1, RECON_PLM = 2, RECON_MP7 = 3;
+
+// Cells a reconstruction reads for face f+1/2: W cells f-LO .. f-LO+W-1
+// (both states); cell f is c[LO], cell f+1 is c[LO+1].
+template <int RC> struct Stencil { static constexpr int W = 6, LO = 2; };
+template <> struct Stencil<RECON_MP7> { static constexpr int W = 8, LO = 3; };
 
 template <int RC, typename T>
-GR_HD void recon_lr(const T c[6], T& l, T& r) {
-  if constexpr (RC == RECON_WENO5) {
+GR_HD void recon_lr(const T c[Stencil<RC>::W], T& l, T& r) {
+  if constexpr (RC == RECON_MP7) {
+    l = mp7(c[0], c[1], c[2], c[3], c[4], c[5], c[6]);
+    r = mp7(c[7], c[6], c[5], c[4], c[3], c[2], c[1]);
+  } else if constexpr (RC == RECON_WENO5) {
     l = weno5(c[0], c[1], c[2], c[3], c[4]);
     r = weno5(c[5], c[4], c[3], c[2], c[1]);
   } else if constexpr (RC == RECON_PLM) {
@@ -391,28 +420,29 @@ GR_HD T hll(T fl, T fr, T ul, T ur, T ap, T am, T inv_s, bool tiny) {
 
 // ------------------------------------------------------------------ per-face body
 constexpr double POS_FRAC = 0.1;
-// qs(v, s): cell f-2+s (s = 0..5) of reconstructed variable v (rho, p, u^1,
-// u^2, u^3, B^{d+1}, B^{d+2}), read when its reconstruction needs it (a
-// caller staging the cells in LDS then holds one variable's six cells in
-// registers at a time instead of all 42).
+// qs(v, s): cell f-LO+s (s = 0 .. W-1, Stencil<RC>) of reconstructed
+// variable v (rho, p, u^1, u^2, u^3, B^{d+1}, B^{d+2}), read when its
+// reconstruction needs it (a caller staging the cells in LDS then holds one
+// variable's cells in registers at a time instead of all 7 W).
 template <int DIR, int RC = RECON_MP5, typename T, class M, class QS>
 GR_HD void face_body_q(const QS& qs, T bn, bool axis, const M& m, T gam, T fh[5], T ctd[6]) {
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+  constexpr int W = Stencil<RC>::W, LO = Stencil<RC>::LO;
   PState<T> sl, sr;
   auto rec = [&](int v, T& l, T& r) {
-    T c[6];
+    T c[W];
 #pragma unroll
-    for (int s = 0; s < 6; ++s) c[s] = qs(v, s);
+    for (int s = 0; s < W; ++s) c[s] = qs(v, s);
     recon_lr<RC>(c, l, r);
   };
   // rho and p states are kept at or above POS_FRAC times the cell value on
   // their side of the face (a continuous positivity bound)
   rec(0, sl.rho, sr.rho);
-  sl.rho = fmax(sl.rho, T(POS_FRAC) * qs(0, 2));
-  sr.rho = fmax(sr.rho, T(POS_FRAC) * qs(0, 3));
+  sl.rho = fmax(sl.rho, T(POS_FRAC) * qs(0, LO));
+  sr.rho = fmax(sr.rho, T(POS_FRAC) * qs(0, LO + 1));
   rec(1, sl.p, sr.p);
-  sl.p = fmax(sl.p, T(POS_FRAC) * qs(1, 2));
-  sr.p = fmax(sr.p, T(POS_FRAC) * qs(1, 3));
+  sl.p = fmax(sl.p, T(POS_FRAC) * qs(1, LO));
+  sr.p = fmax(sr.p, T(POS_FRAC) * qs(1, LO + 1));
   rec(2, sl.u[0], sr.u[0]);
   rec(3, sl.u[1], sr.u[1]);
   rec(4, sl.u[2], sr.u[2]);
@@ -447,28 +477,31 @@ GR_HD void face_body_q(const QS& qs, T bn, bool axis, const M& m, T gam, T fh[5]
   ctd[5] = am;
 }
 
-// q[v][s]: six cells f-2 .. f+3 of the reconstructed variables in the order
-// rho, p, u^1, u^2, u^3, B^{d+1}, B^{d+2}; bn: normal B at the face.
+// q[v][s]: the cells f-LO .. f-LO+W-1 of the reconstructed variables in the
+// order rho, p, u^1, u^2, u^3, B^{d+1}, B^{d+2}; bn: normal B at the face.
 template <int DIR, int RC = RECON_MP5, typename T, class M>
-GR_HD void face_body(const T q[7][6], T bn, bool axis, const M& m, T gam, T fh[5], T ctd[6]) {
+GR_HD void face_body(const T q[7][Stencil<RC>::W], T bn, bool axis, const M& m, T gam, T fh[5],
+                     T ctd[6]) {
   face_body_q<DIR, RC>([&](int v, int s) { return q[v][s]; }, bn, axis, m, gam, fh, ctd);
 }
 
 // ------------------------------------------------------------------ per-edge body
-// Edge field of family E (d = E+1, c = E+2 mod 3).  qd[v][s]: six d-faces
-// along c of v^d_L, v^d_R, v^c_L, v^c_R, B^d; qc[s]: six c-faces along d of
-// B^c; a*: speeds of the two adjacent faces of each family.
-// qds(v, s) returns qd[v][s], read when its reconstruction needs it (for a
-// caller that stages qd in LDS: one variable's cells in registers at a time).
+// Edge field of family E (d = E+1, c = E+2 mod 3).  qd[v][s]: W d-faces
+// along c (Stencil<RC>) of v^d_L, v^d_R, v^c_L, v^c_R, B^d; qc[s]: W
+// c-faces along d of B^c; a*: speeds of the two adjacent faces of each
+// family.  qds(v, s) returns qd[v][s], read when its reconstruction needs it
+// (for a caller that stages qd in LDS: one variable's cells in registers at
+// a time).
 template <int E, int RC = RECON_MP5, typename T, class M, class QD>
-GR_HD T edge_body_q(const QD& qds, const T qc[6], T apd0, T apd1, T amd0, T amd1,
+GR_HD T edge_body_q(const QD& qds, const T qc[Stencil<RC>::W], T apd0, T apd1, T amd0, T amd1,
                     T apc0, T apc1, T amc0, T amc1, const M& m) {
   constexpr int D = (E + 1) % 3, C = (E + 2) % 3;
+  constexpr int W = Stencil<RC>::W;
   T vd[2][2], vc[2][2], bd[2], bc[2];   // [a][b]
   auto rec = [&](int v, T& l, T& r) {
-    T c[6];
+    T c[W];
 #pragma unroll
-    for (int s = 0; s < 6; ++s) c[s] = qds(v, s);
+    for (int s = 0; s < W; ++s) c[s] = qds(v, s);
     recon_lr<RC>(c, l, r);
   };
   rec(0, vd[0][0], vd[0][1]);
@@ -501,8 +534,8 @@ GR_HD T edge_body_q(const QD& qds, const T qc[6], T apd0, T apd1, T amd0, T amd1
 }
 
 template <int E, int RC = RECON_MP5, typename T, class M>
-GR_HD T edge_body(const T qd[5][6], const T qc[6], T apd0, T apd1, T amd0, T amd1,
-                  T apc0, T apc1, T amc0, T amc1, const M& m) {
+GR_HD T edge_body(const T qd[5][Stencil<RC>::W], const T qc[Stencil<RC>::W], T apd0, T apd1,
+                  T amd0, T amd1, T apc0, T apc1, T amc0, T amc1, const M& m) {
   return edge_body_q<E, RC>([&](int v, int s) { return qd[v][s]; }, qc, apd0, apd1, amd0, amd1, apc0,
                             apc1, amc0, amc1, m);
 }

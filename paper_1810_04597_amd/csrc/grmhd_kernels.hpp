@@ -13,7 +13,7 @@ struct C2PParams {
   int coord;            // 0 Cartesian, 1 log-spherical (r = exp(x^1))
   double rho_fl_a, rho_fl_n, p_fl_a, p_fl_n, w_max;
   double defer_tol;     // learned guess: relative warm residual above which a zone is deferred
-  int img;              // all directions periodic, n >= 2 NG: also write the ghost images
+  int img;              // all directions periodic, n >= 2 ng: also write the ghost images
   int split_it;         // > 0: defer zones not converged after this many iterations to a second pass
   // nullable: counters accumulated over every inversion (RUN_SLOTS slots of
   // RUN_STRIDE words, RUN_NCOUNT used)
@@ -46,7 +46,7 @@ struct BCSpec {
 
 void launch_bc_centred(const Geom& G, const BCSpec& bc, double* prim, int nfields, hipStream_t s);
 void launch_bc_faces(const Geom& G, const BCSpec& bc, double* cons, hipStream_t s);
-// recon: RECON_MP5 | RECON_WENO5 | RECON_PLM (grmhd_device.hpp)
+// recon: RECON_MP5 | RECON_WENO5 | RECON_PLM | RECON_MP7 (grmhd_device.hpp)
 void launch_sweep(int d, const Geom& G, bool flat, bool fp32, int recon, const double* prim,
                   const double* cons, const double* tab, double* flux, double* ctd, hipStream_t s);
 void launch_edge(int e, const Geom& G, bool flat, bool fp32, int recon, const double* cons,
@@ -55,7 +55,7 @@ void launch_edge(int e, const Geom& G, bool flat, bool fp32, int recon, const do
 // (stage 1: x = U^n -> y; stage 2: x updated in place, U^n read from y;
 // stage 3: x -> y, overwriting U^n); dt from d_dt when dt_host <= 0.
 // mode 1: write L of the state in x into out (cons layout).
-// img (flat metric, mode 0): all directions periodic with n >= 2 NG; the new
+// img (flat metric, mode 0): all directions periodic with n >= 2 ng; the new
 // face fields are also written to their ghost images (no separate face fill).
 // fp32: flux and edges hold float fields (the FP32 form's storage), read at
 // the same element offsets.

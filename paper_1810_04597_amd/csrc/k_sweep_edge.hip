@@ -87,11 +87,12 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
   ii[MID] = tp.m;
   ii[SLOW] = tp.s;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) ii[a] += (a == DIR) ? -3 : -NG;
+  for (int a = 0; a < 3; ++a) ii[a] += (a == DIR) ? -3 : -G.ng;
   const long c = G.idx(ii[0], ii[1], ii[2]);
   const long st = G.stride(DIR);
   const T gam = T(G.gam);
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
+  constexpr int W = Stencil<RC>::W, LO = Stencil<RC>::LO;
 
   // face metric: x^1 faces -> F1, x^2 faces -> F2, x^3 faces -> centre tables
   MET m;
@@ -100,14 +101,14 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
     m.load(tab, G.tab_plane, loc, G.tidx(ii[0], ii[1]));
   }
 
-  T q[7][6];
+  T q[7][W];
   {
     const int fields[7] = {P_RHO, P_P, P_U1, P_U2, P_U3, P_B1 + T1, P_B1 + T2};
 #pragma unroll
     for (int v = 0; v < 7; ++v) {
       const double* p = prim + (long)fields[v] * G.field + c;
 #pragma unroll
-      for (int s = 0; s < 6; ++s) q[v][s] = T(p[(s - 2) * st]);
+      for (int s = 0; s < W; ++s) q[v][s] = T(p[(s - LO) * st]);
     }
   }
   const double bface = cons[(long)(C_BF1 + DIR) * G.field + c];
@@ -147,7 +148,8 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   static_assert(DIR == 1 || DIR == 2, "x^2 and x^3 sweeps only");
   constexpr int TB = DIR == 1 ? 2 : 1;          // the transverse axis other than x^1
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
-  constexpr int SR = SF + 5, NRR = (SR + SF - 1) / SF;
+  constexpr int W = Stencil<RC>::W, LO = Stencil<RC>::LO;
+  constexpr int SR = SF + W - 1, NRR = (SR + SF - 1) / SF;
   __shared__ T sh[7][SR][SX + LPAD];
   const int nA = G.dims[0];
   const long M = (long)nA * G.dims[TB];
@@ -162,25 +164,25 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   const bool m_ok = mm < M;
   const unsigned mc = (unsigned)(m_ok ? mm : M - 1);   // clamped: every staging load is in bounds
   int ii[3];
-  ii[0] = (int)(mc % (unsigned)nA) - NG;
-  ii[TB] = (int)(mc / (unsigned)nA) - NG;
+  ii[0] = (int)(mc % (unsigned)nA) - G.ng;
+  ii[TB] = (int)(mc / (unsigned)nA) - G.ng;
   ii[DIR] = 0;
   const long base = G.idx(ii[0], ii[1], ii[2]);
   const long st = G.stride(DIR);
   const int f0 = -3 + ft * SF;
-  // stage cells f0 - 2 .. f0 + SF + 2; wavefront ty loads rows ty + SF rr
+  // stage cells f0 - LO .. f0 + SF - LO + W - 2; wavefront ty loads rows ty + SF rr
   // (a wave-uniform condition).  Rows past the last ghost cell are clamped to
   // it: no face of the tile that exists reads them.  All loads are issued
   // before the first LDS write.
   {
     constexpr int fields[7] = {P_RHO, P_P, P_U1, P_U2, P_U3, P_B1 + T1, P_B1 + T2};
-    const int cmax = G.n[DIR] + NG - 1;
+    const int cmax = G.n[DIR] + G.ng - 1;
     const double* pb = prim + base;             // per lane; the offsets below are uniform
     T stage[7][NRR];
 #pragma unroll
     for (int rr = 0; rr < NRR; ++rr) {
       if (ty + SF * rr < SR) {
-        const long ro = (long)min(f0 - 2 + ty + SF * rr, cmax) * st;
+        const long ro = (long)min(f0 - LO + ty + SF * rr, cmax) * st;
 #pragma unroll
         for (int v = 0; v < 7; ++v) stage[v][rr] = T(pb[(long)fields[v] * G.field + ro]);
       }
@@ -236,6 +238,7 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
                                               const T* __restrict__ ctd_c,
                                               T* __restrict__ edge) {
   constexpr int D = (E + 1) % 3, C = (E + 2) % 3;
+  constexpr int W = Stencil<RC>::W, LO = Stencil<RC>::LO;
   int ext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) ext[a] = (a == E) ? G.n[a] : G.n[a] + 5;
@@ -252,18 +255,18 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
   const long b = G.idx(ii[0], ii[1], ii[2]);
   const long sd = G.stride(D), sc = G.stride(C);
 
-  T qd[5][6], qc[6];
+  T qd[5][W], qc[W];
   {
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int s = 0; s < 6; ++s) qd[v][s] = ctd_d[(long)v * G.field + b + (s - 2) * sc];
+      for (int s = 0; s < W; ++s) qd[v][s] = ctd_d[(long)v * G.field + b + (s - LO) * sc];
     const double* bds = cons + (long)(C_BF1 + D) * G.field;
 #pragma unroll
-    for (int s = 0; s < 6; ++s) qd[4][s] = T(bds[b + (s - 2) * sc]);
+    for (int s = 0; s < W; ++s) qd[4][s] = T(bds[b + (s - LO) * sc]);
     const double* bcs = cons + (long)(C_BF1 + C) * G.field;
 #pragma unroll
-    for (int s = 0; s < 6; ++s) qc[s] = T(bcs[b + (s - 2) * sd]);
+    for (int s = 0; s < W; ++s) qc[s] = T(bcs[b + (s - LO) * sd]);
   }
   MET m;
   if constexpr (!MET::flat) {
@@ -291,7 +294,8 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
                                                       T* __restrict__ edge) {
   static_assert(E == 0 || E == 2, "families whose d-face inputs vary across rows");
   constexpr int D = (E + 1) % 3, C = (E + 2) % 3, B = 3 - C;   // B: the non-x^1 axis that is not C
-  constexpr int SR = SF + 5, NRR = (SR + SF - 1) / SF;
+  constexpr int W = Stencil<RC>::W, LO = Stencil<RC>::LO;
+  constexpr int SR = SF + W - 1, NRR = (SR + SF - 1) / SF;
   __shared__ T sh[5][SR][SX + LPAD];
   const int extA = (E == 0) ? G.n[0] : G.n[0] + 5, offA = (E == 0) ? 0 : -3;
   const int extB = (B == E) ? G.n[B] : G.n[B] + 5, offB = (B == E) ? 0 : -3;
@@ -315,12 +319,12 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   const int c0 = -3 + ct * SF;
   {
     const double* bds = cons + (long)(C_BF1 + D) * G.field;
-    const int cmax = G.n[C] + NG - 1;
+    const int cmax = G.n[C] + G.ng - 1;
     T stage[5][NRR];
 #pragma unroll
     for (int rr = 0; rr < NRR; ++rr) {
       if (ty + SF * rr < SR) {
-        const long ro = base + (long)min(c0 - 2 + ty + SF * rr, cmax) * sc;
+        const long ro = base + (long)min(c0 - LO + ty + SF * rr, cmax) * sc;
 #pragma unroll
         for (int v = 0; v < 4; ++v) stage[v][rr] = ctd_d[(long)v * G.field + ro];
         stage[4][rr] = T(bds[ro]);
@@ -345,11 +349,11 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   if (mt * SX + cx >= M || cc > G.n[C] + 1) return;
   ii[C] = cc;
   const long b = G.idx(ii[0], ii[1], ii[2]);
-  T qc[6];
+  T qc[W];
   {
     const double* bcs = cons + (long)(C_BF1 + C) * G.field;
 #pragma unroll
-    for (int s2 = 0; s2 < 6; ++s2) qc[s2] = T(bcs[b + (s2 - 2) * sd]);
+    for (int s2 = 0; s2 < W; ++s2) qc[s2] = T(bcs[b + (s2 - LO) * sd]);
   }
   MET m;
   if constexpr (!MET::flat) {
@@ -432,14 +436,16 @@ static void launch_edge_r(int e, const Geom& G, bool flat, bool fp32, const doub
 
 void launch_sweep(int d, const Geom& G, bool flat, bool fp32, int recon, const double* prim,
                   const double* cons, const double* tab, double* flux, double* ctd, hipStream_t s) {
-  if (recon == RECON_WENO5) launch_sweep_r<RECON_WENO5>(d, G, flat, fp32, prim, cons, tab, flux, ctd, s);
+  if (recon == RECON_MP7) launch_sweep_r<RECON_MP7>(d, G, flat, fp32, prim, cons, tab, flux, ctd, s);
+  else if (recon == RECON_WENO5) launch_sweep_r<RECON_WENO5>(d, G, flat, fp32, prim, cons, tab, flux, ctd, s);
   else if (recon == RECON_PLM) launch_sweep_r<RECON_PLM>(d, G, flat, fp32, prim, cons, tab, flux, ctd, s);
   else launch_sweep_r<RECON_MP5>(d, G, flat, fp32, prim, cons, tab, flux, ctd, s);
 }
 
 void launch_edge(int e, const Geom& G, bool flat, bool fp32, int recon, const double* cons,
                  const double* tab, const double* ctd, double* edges, hipStream_t s) {
-  if (recon == RECON_WENO5) launch_edge_r<RECON_WENO5>(e, G, flat, fp32, cons, tab, ctd, edges, s);
+  if (recon == RECON_MP7) launch_edge_r<RECON_MP7>(e, G, flat, fp32, cons, tab, ctd, edges, s);
+  else if (recon == RECON_WENO5) launch_edge_r<RECON_WENO5>(e, G, flat, fp32, cons, tab, ctd, edges, s);
   else if (recon == RECON_PLM) launch_edge_r<RECON_PLM>(e, G, flat, fp32, cons, tab, ctd, edges, s);
   else launch_edge_r<RECON_MP5>(e, G, flat, fp32, cons, tab, ctd, edges, s);
 }

@@ -553,34 +553,34 @@ __device__ __forceinline__ GhostSrc ghost_src(const Geom& G, const BCSpec& bc, i
 __device__ __forceinline__ bool ghost_index(const Geom& G, long t, bool axis_row, int& i, int& j,
                                             int& k) {
   const long d0 = G.dims[0], d1 = G.dims[1];
-  const long NA = 2L * NG * d1 * d0;
-  const long NB = (long)G.n[2] * 2 * NG * d0;
-  const long NC = (long)G.n[2] * G.n[1] * 2 * NG;
+  const long NA = 2L * G.ng * d1 * d0;
+  const long NB = (long)G.n[2] * 2 * G.ng * d0;
+  const long NC = (long)G.n[2] * G.n[1] * 2 * G.ng;
   const long ND = axis_row ? (long)G.n[2] * G.n[0] : 0;
   if (t < NA) {
     const int kl = (int)(t / (d1 * d0));
     const long r = t % (d1 * d0);
-    k = kl < NG ? kl - NG : G.n[2] + kl - NG;
-    j = (int)(r / d0) - NG;
-    i = (int)(r % d0) - NG;
+    k = kl < G.ng ? kl - G.ng : G.n[2] + kl - G.ng;
+    j = (int)(r / d0) - G.ng;
+    i = (int)(r % d0) - G.ng;
     return true;
   }
   t -= NA;
   if (t < NB) {
-    k = (int)(t / (2 * NG * d0));
-    const long r = t % (2 * NG * d0);
+    k = (int)(t / (2 * G.ng * d0));
+    const long r = t % (2 * G.ng * d0);
     const int jl = (int)(r / d0);
-    j = jl < NG ? jl - NG : G.n[1] + jl - NG;
-    i = (int)(r % d0) - NG;
+    j = jl < G.ng ? jl - G.ng : G.n[1] + jl - G.ng;
+    i = (int)(r % d0) - G.ng;
     return true;
   }
   t -= NB;
   if (t < NC) {
-    k = (int)(t / ((long)G.n[1] * 2 * NG));
-    const long r = t % ((long)G.n[1] * 2 * NG);
-    j = (int)(r / (2 * NG));
-    const int il = (int)(r % (2 * NG));
-    i = il < NG ? il - NG : G.n[0] + il - NG;
+    k = (int)(t / ((long)G.n[1] * 2 * G.ng));
+    const long r = t % ((long)G.n[1] * 2 * G.ng);
+    j = (int)(r / (2 * G.ng));
+    const int il = (int)(r % (2 * G.ng));
+    i = il < G.ng ? il - G.ng : G.n[0] + il - G.ng;
     return true;
   }
   t -= NC;
@@ -595,7 +595,7 @@ __device__ __forceinline__ bool ghost_index(const Geom& G, long t, bool axis_row
 
 __device__ __forceinline__ long ghost_total(const Geom& G, bool axis_row) {
   const long d0 = G.dims[0], d1 = G.dims[1];
-  return 2L * NG * d1 * d0 + (long)G.n[2] * 2 * NG * d0 + (long)G.n[2] * G.n[1] * 2 * NG +
+  return 2L * G.ng * d1 * d0 + (long)G.n[2] * 2 * G.ng * d0 + (long)G.n[2] * G.n[1] * 2 * G.ng +
          (axis_row ? (long)G.n[2] * G.n[0] : 0);
 }
 
@@ -723,7 +723,7 @@ unsigned zone_blocks(const Geom& G) { return nblk((long)G.n[0] * G.n[1] * G.n[2]
 
 static long ghost_count(const Geom& G, bool axis_row) {
   const long d0 = G.dims[0], d1 = G.dims[1];
-  return 2L * NG * d1 * d0 + (long)G.n[2] * 2 * NG * d0 + (long)G.n[2] * G.n[1] * 2 * NG +
+  return 2L * G.ng * d1 * d0 + (long)G.n[2] * 2 * G.ng * d0 + (long)G.n[2] * G.n[1] * 2 * G.ng +
          (axis_row ? (long)G.n[2] * G.n[0] : 0);
 }
 

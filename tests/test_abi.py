@@ -51,12 +51,14 @@ def _desc(L, **kw):
 
 @pytest.mark.parametrize("field,value,msg", [
     ("ng", 4, "ng must be 5"),
+    ("ng", 7, "ng must be 5"),
     ("precision", 7, "bad precision"),
     ("c2p_guess", 3, "bad c2p_guess"),
     ("newton_maxit", 0, "bad newton_maxit"),
     ("gamma_ad", 1.0, "gamma_ad"),
-    ("recon", 3, "bad recon"),
+    ("recon", 4, "bad recon"),
     ("recon", -1, "bad recon"),
+    ("recon", 3, "MP7 needs ng = 6"),
     ("deriv_order", 5, "deriv_order"),
     ("reserved", 1, "reserved"),
 ])
@@ -81,7 +83,7 @@ def test_descriptor_validation_of_boundaries():
     d.bc[2] = d.bc[3] = L.BC_AXIS
     d.n[1] = 4
     assert lib.grmhd_init_grid(C.byref(d), None, C.byref(h)) == L.EINVAL
-    assert "n2 >= 6" in lib.grmhd_last_error().decode()
+    assert "n2 >= ng + 1" in lib.grmhd_last_error().decode()
 
 
 def test_null_handles_are_rejected():

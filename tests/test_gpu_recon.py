@@ -1,9 +1,10 @@
-"""GPU parity of the alternative reconstructions (WENO5, PLM-MC) against the
-oracle's own WENO5 / PLM-MC, through the C ABI: one RHS evaluation on small
-and ragged boxes (1e-11 of each field's scale), ten SSP-RK3 steps of the 32^3
-box with the device CFL step (1e-10 relative per zone and field, the FP64
-bar), one step of the Kerr-Schild torus (table metric), and the FP32-flux form
-against the oracle's float32 form."""
+"""GPU parity of the alternative reconstructions (WENO5, PLM-MC, and MP7 on
+grids with six ghost layers) against the oracle's own, through the C ABI: one
+RHS evaluation on small and ragged boxes (1e-11 of each field's scale), ten
+SSP-RK3 steps of the 32^3 box with the device CFL step (1e-10 relative per
+zone and field, the FP64 bar), one step of the Kerr-Schild torus (table
+metric), and the FP32-flux form against the oracle's float32 form; six ghost
+layers change nothing for MP5."""
 import numpy as np
 import pytest
 
@@ -12,7 +13,8 @@ from helpers import max_rel, interior
 gpu = pytest.mark.gpu
 PRIM = ("rho", "u1", "u2", "u3", "p", "B1", "B2", "B3")
 CONS = ("D", "S1", "S2", "S3", "tau", "Bf1", "Bf2", "Bf3")
-RECONS = ["weno5", "plm"]
+RECONS = ["weno5", "plm", "mp7"]
+NG_OF = {"mp5": 5, "weno5": 5, "plm": 5, "mp7": 6}
 
 
 def _torch():
@@ -40,7 +42,7 @@ def _pair(g, d, recon, tab=None, precision="fp64"):
 def test_rhs_matches_oracle(recon, n):
     _torch()
     from workloads import box
-    g, d = box.turbulent_box(n)
+    g, d = box.turbulent_box(n, ng=NG_OF[recon])
     s, G = _pair(g, d, recon)
     L_o = s.rhs()
     L_g = G.read_group(G.rhs(), CONS, interior=True)
@@ -54,15 +56,15 @@ def test_rhs_matches_oracle(recon, n):
 def test_ten_steps_parity(recon):
     _torch()
     from workloads import box
-    g, d = box.turbulent_box(32)
+    g, d = box.turbulent_box(32, ng=NG_OF[recon])
     s, G = _pair(g, d, recon)
     for _ in range(10):
         dt_o = s.cfl_dt()
         dt_g = G.rk_step(0.0, want_dt=True)
         assert abs(dt_g / dt_o - 1) < 1e-11
         s.rk_step(dt_o)
-    P = {k: interior(v) for k, v in s.P.items()}
-    U = {k: interior(v) for k, v in s.U.items()}
+    P = {k: interior(v, s.g) for k, v in s.P.items()}
+    U = {k: interior(v, s.g) for k, v in s.U.items()}
     e = max_rel(G.to_numpy("prim", interior=True), P, PRIM)
     e.update(max_rel(G.to_numpy("cons", interior=True), U, CONS))
     assert max(e.values()) < 1e-10, e
@@ -83,14 +85,14 @@ def test_torus_one_step_parity(recon):
     sensitivity to that perturbation is below 1e-12."""
     _torch()
     from workloads.torus import torus
-    g, d, tab = torus(48, 24, 24)
+    g, d, tab = torus(48, 24, 24, ng=NG_OF[recon])
     s, G = _pair(g, d, recon, tab)
     dt = 0.005
     s.rk_step(dt)
     G.rk_step(dt)
     assert s.stats["n_fail"] == 0 and G.diagnostics()["n_c2p_fail"] == 0
-    P = {k: interior(v) for k, v in s.P.items()}
-    U = {k: interior(v) for k, v in s.U.items()}
+    P = {k: interior(v, s.g) for k, v in s.P.items()}
+    U = {k: interior(v, s.g) for k, v in s.U.items()}
     e = max_rel(G.to_numpy("prim", interior=True), P, PRIM)
     e.update(max_rel(G.to_numpy("cons", interior=True), U, CONS))
     assert max(e.values()) < 1e-10, e
@@ -102,7 +104,7 @@ def test_torus_one_step_parity(recon):
 def test_fp32_form_rhs_matches_oracle_fp32_form(recon):
     _torch()
     from workloads import box
-    g, d = box.turbulent_box(16)
+    g, d = box.turbulent_box(16, ng=NG_OF[recon])
     s, G = _pair(g, d, recon, precision="fp32")
     L_o = s.rhs()
     L_g = G.read_group(G.rhs(), CONS, interior=True)
@@ -131,3 +133,27 @@ def test_reconstructions_differ_and_mp5_is_default():
         assert np.array_equal(out["default"][k], out["mp5"][k]), k
     for a, b in (("mp5", "weno5"), ("mp5", "plm"), ("weno5", "plm")):
         assert max(np.max(np.abs(out[a][k] - out[b][k])) for k in CONS) > 1e-8, (a, b)
+
+
+@gpu
+def test_six_ghost_layers_change_nothing_for_mp5():
+    """The same 16^3 box on five and six ghost layers: interior results of
+    one RHS and of two RK3 steps equal bit for bit (the stencils read the
+    same cells; only the layout's offsets differ)."""
+    _torch()
+    from workloads import box
+    from paper_1810_04597_amd.grid import Grid
+    out = {}
+    for ng in (5, 6):
+        g, d = box.turbulent_box(16, ng=ng)
+        G = Grid(g)
+        G.curl_potential(d)
+        G.set_primitives(d)
+        L = G.read_group(G.rhs(), CONS, interior=True)
+        G.rk_step(0.0)
+        G.rk_step(0.0)
+        out[ng] = (L, G.to_numpy("prim", interior=True), G.to_numpy("cons", interior=True))
+        G.close()
+    for a, b in zip(out[5], out[6]):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
