@@ -32,25 +32,38 @@ constexpr int PX = 16, PY = 64 / PX;
 // Direct (unstaged) kernels: a 256-thread workgroup covers PX x^1 positions
 // times 4 PY positions of the middle axis at one position of the slow axis;
 // wavefront w owns middle-axis rows w PY .. w PY + PY - 1 of the tile.
+// x^1 alignment: a row segment of PX = 16 doubles is one 128-byte line when
+// it starts at a multiple of 16 in storage.  x^1 position a of a range whose
+// first element sits `shift` doubles past such a line (rows start on one:
+// the pitch is a multiple of 16) goes to lane slot a + shift, so every
+// segment a wavefront loads or stores covers whole lines instead of
+// straddling two; the slots before the range's start stay idle.
 struct TilePos {
   int a, m, s;
   bool ok;
 };
-__device__ __forceinline__ TilePos tile_pos(int ext0, int extm) {
+__device__ __forceinline__ TilePos tile_pos(int ext0, int extm, int shift) {
   const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-  const unsigned nt0 = (ext0 + PX - 1) / PX, ntm = (extm + 4 * PY - 1) / (4 * PY);
+  const unsigned nt0 = (ext0 + shift + PX - 1) / PX, ntm = (extm + 4 * PY - 1) / (4 * PY);
   const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
   TilePos p;
-  p.a = (int)(b % nt0) * PX + lane % PX;
+  p.a = (int)(b % nt0) * PX + lane % PX - shift;
   const unsigned r = b / nt0;
   p.m = (int)(r % ntm) * (4 * PY) + w * PY + lane / PX;
   p.s = (int)(r / ntm);
-  p.ok = p.a < ext0 && p.m < extm;
+  p.ok = p.a >= 0 && p.a < ext0 && p.m < extm;
   return p;
 }
-static inline unsigned tile_blocks(long ext0, long extm, long exts) {
-  return (unsigned)(((ext0 + PX - 1) / PX) * ((extm + 4 * PY - 1) / (4 * PY)) * exts);
+static inline unsigned tile_blocks(long ext0, long extm, long exts, int shift) {
+  return (unsigned)(((ext0 + shift + PX - 1) / PX) * ((extm + 4 * PY - 1) / (4 * PY)) * exts);
 }
+// Offset (doubles past a 16-double line) of x^1 index i0 in storage.
+__host__ __device__ __forceinline__ int line_shift(int ng, int i0) { return (ng + i0) & 15; }
+// Line-aligned lane map per edge family: it pays where the kernel's x^1
+// segments are both loaded and stored from a misaligned start (family 0,
+// x^1 interior); families 1 and 2 (x^1 from -3) measured faster without it,
+// their idle slots costing more than the straddled lines.
+constexpr bool EDGE_ALIGN[3] = {true, false, false};
 
 // Flattened map (x^1 fastest, then the middle axis): one 64-position row
 // segment per wavefront, no idle lanes at the tile edges.  The x^1 sweep on
@@ -80,7 +93,8 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
   // tiles: x^1 fastest; for the x^3 sweep x^3 comes next, so the six planes
   // of a stencil are read by neighbouring workgroups (L2 reuse)
   constexpr int MID = DIR == 2 ? 2 : 1, SLOW = DIR == 2 ? 1 : 2;
-  const TilePos tp = MET::flat ? tile_pos(ext[0], ext[MID]) : flat_pos(ext[0], ext[MID], ext[SLOW]);
+  const TilePos tp = MET::flat ? tile_pos(ext[0], ext[MID], line_shift(G.ng, DIR == 0 ? -3 : -G.ng))
+                               : flat_pos(ext[0], ext[MID], ext[SLOW]);
   if (!tp.ok) return;
   int ii[3];
   ii[0] = tp.a;
@@ -151,8 +165,11 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   constexpr int W = Stencil<RC>::W, LO = Stencil<RC>::LO;
   constexpr int SR = SF + W - 1, NRR = (SR + SF - 1) / SF;
   __shared__ T sh[7][SR][SX + LPAD];
-  const int nA = G.dims[0];
-  const long M = (long)nA * G.dims[TB];
+  // transverse positions flattened with x^1 fastest over rows of the pitch
+  // (a multiple of 16, so 16-lane segments are whole 128-byte lines); the
+  // pitch's padding positions past the ghosted x^1 range stay idle
+  const int nA = G.dims[0], rA = (int)G.pitch;
+  const long M = (long)rA * G.dims[TB];
   const int nface = G.n[DIR] + 5;               // faces -3 .. n + 1
   const int ntf = (nface + SF - 1) / SF;
   const long bid = xcd_block(blockIdx.x, gridDim.x);
@@ -161,11 +178,12 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   // ty (the face row) is the wavefront index: uniform, so row offsets go to the scalar unit
   const int tx = threadIdx.x % SX, ty = __builtin_amdgcn_readfirstlane(threadIdx.x / SX);
   const long mm = mt * SX + tx;
-  const bool m_ok = mm < M;
-  const unsigned mc = (unsigned)(m_ok ? mm : M - 1);   // clamped: every staging load is in bounds
+  const unsigned mc = (unsigned)(mm < M ? mm : M - 1);
+  const int xa = (int)(mc % (unsigned)rA);
+  const int ok = mm < M && xa < nA;                 // a position of the ghosted range
   int ii[3];
-  ii[0] = (int)(mc % (unsigned)nA) - G.ng;
-  ii[TB] = (int)(mc / (unsigned)nA) - G.ng;
+  ii[0] = min(xa, nA - 1) - G.ng;                   // clamped: every staging load is in bounds
+  ii[TB] = (int)(mc / (unsigned)rA) - G.ng;
   ii[DIR] = 0;
   const long base = G.idx(ii[0], ii[1], ii[2]);
   const long st = G.stride(DIR);
@@ -203,7 +221,8 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   // lane x of every wavefront staged tile position x: take its indices
   ii[0] = __shfl(ii[0], cx);
   ii[TB] = __shfl(ii[TB], cx);
-  if (mt * SX + cx >= M || f > G.n[DIR] + 1) return;
+  const int okc = __shfl(ok, cx);
+  if (!okc || f > G.n[DIR] + 1) return;
   ii[DIR] = f;
   const long c = G.idx(ii[0], ii[1], ii[2]);
   const T gam = T(G.gam);
@@ -244,7 +263,7 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
   for (int a = 0; a < 3; ++a) ext[a] = (a == E) ? G.n[a] : G.n[a] + 5;
   // families 1 and 2 reconstruct along x^3: tiles traverse x^3 before x^2
   constexpr int MID = E == 2 ? 1 : 2, SLOW = E == 2 ? 2 : 1;
-  const TilePos tp = tile_pos(ext[0], ext[MID]);
+  const TilePos tp = tile_pos(ext[0], ext[MID], EDGE_ALIGN[E] ? line_shift(G.ng, E == 0 ? 0 : -3) : 0);
   if (!tp.ok) return;
   int ii[3];
   ii[0] = tp.a;
@@ -299,7 +318,11 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   __shared__ T sh[5][SR][SX + LPAD];
   const int extA = (E == 0) ? G.n[0] : G.n[0] + 5, offA = (E == 0) ? 0 : -3;
   const int extB = (B == E) ? G.n[B] : G.n[B] + 5, offB = (B == E) ? 0 : -3;
-  const long M = (long)extA * extB;
+  // positions flattened with x^1 fastest over rows of rA slots, the x^1 range
+  // starting at slot shA so that 16-lane segments are whole 128-byte lines
+  const int shA = EDGE_ALIGN[E] ? line_shift(G.ng, offA) : 0;
+  const int rA = EDGE_ALIGN[E] ? (extA + shA + 15) / 16 * 16 : extA;
+  const long M = (long)rA * extB;
   const int nc = G.n[C] + 5;                    // edges -3 .. n + 1 along c
   const int ntc = (nc + SF - 1) / SF;
   const long bid = xcd_block(blockIdx.x, gridDim.x);
@@ -308,11 +331,12 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   // ty (the face row) is the wavefront index: uniform, so row offsets go to the scalar unit
   const int tx = threadIdx.x % SX, ty = __builtin_amdgcn_readfirstlane(threadIdx.x / SX);
   const long mm = mt * SX + tx;
-  const bool m_ok = mm < M;
-  const unsigned mc = (unsigned)(m_ok ? mm : M - 1);   // clamped: every staging load is in bounds
+  const unsigned mc = (unsigned)(mm < M ? mm : M - 1);
+  const int xa = (int)(mc % (unsigned)rA) - shA;
+  const int ok = mm < M && xa >= 0 && xa < extA;
   int ii[3];
-  ii[0] = (int)(mc % (unsigned)extA) + offA;
-  ii[B] = (int)(mc / (unsigned)extA) + offB;
+  ii[0] = min(max(xa, 0), extA - 1) + offA;      // clamped: every staging load is in bounds
+  ii[B] = (int)(mc / (unsigned)rA) + offB;
   ii[C] = 0;
   const long base = G.idx(ii[0], ii[1], ii[2]);
   const long sd = G.stride(D), sc = G.stride(C);
@@ -346,7 +370,8 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   // lane x of every wavefront staged tile position x: take its indices
   ii[0] = __shfl(ii[0], cx);
   ii[B] = __shfl(ii[B], cx);
-  if (mt * SX + cx >= M || cc > G.n[C] + 1) return;
+  const int okc = __shfl(ok, cx);
+  if (!okc || cc > G.n[C] + 1) return;
   ii[C] = cc;
   const long b = G.idx(ii[0], ii[1], ii[2]);
   T qc[W];
@@ -382,13 +407,14 @@ static void launch_sweep_t(int d, const Geom& G, const double* prim, const doubl
   T* cd = reinterpret_cast<T*>(ctd) + (long)d * 6 * G.field;
   if (d == 0) {
     const long nf = (long)(G.n[0] + 5) * G.dims[1] * G.dims[2];
-    const unsigned nb = MET::flat ? tile_blocks(G.n[0] + 5, G.dims[1], G.dims[2]) : (unsigned)((nf + 255) / 256);
+    const unsigned nb = MET::flat ? tile_blocks(G.n[0] + 5, G.dims[1], G.dims[2], line_shift(G.ng, -3))
+                                  : (unsigned)((nf + 255) / 256);
     hipLaunchKernelGGL((k_sweep<0, MET, T, RC>), dim3(nb), dim3(256), 0, s, G, prim, cons, tab, fl, cd);
     return;
   }
-  // tiles: SX transverse positions x SF faces
+  // tiles: SX transverse positions (rows of the pitch) x SF faces
   constexpr int SF = SWEEP_SF;
-  const long M = (long)G.dims[0] * G.dims[d == 1 ? 2 : 1];
+  const long M = (long)G.pitch * G.dims[d == 1 ? 2 : 1];
   const long tiles = ((M + SX - 1) / SX) * ((G.n[d] + 5 + SF - 1) / SF);
   if (d == 1) hipLaunchKernelGGL((k_sweep_lds<1, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, prim, cons, tab, fl, cd);
   if (d == 2) hipLaunchKernelGGL((k_sweep_lds<2, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, prim, cons, tab, fl, cd);
@@ -402,14 +428,19 @@ static void launch_edge_t(int e, const Geom& G, const double* cons, const double
   const T* cc = reinterpret_cast<const T*>(ctd) + (long)c * 6 * G.field;
   T* ed = reinterpret_cast<T*>(edges) + (long)e * G.field;
   if (e == 1) {
-    hipLaunchKernelGGL((k_edge<1, MET, T, RC>), dim3(tile_blocks(G.n[0] + 5, G.n[2] + 5, G.n[1])),
+    hipLaunchKernelGGL((k_edge<1, MET, T, RC>),
+                       dim3(tile_blocks(G.n[0] + 5, G.n[2] + 5, G.n[1], EDGE_ALIGN[1] ? line_shift(G.ng, -3) : 0)),
                        dim3(256), 0, s, G, cons, tab, cd, cc, ed);
     return;
   }
-  // staged families: tiles of SX positions (x^1 and the remaining axis) x SF edges along c
+  // staged families: tiles of SX positions (x^1 rows of whole lines, and the
+  // remaining axis) x SF edges along c
   constexpr int SF = EDGE_SF;
   const int B = 3 - c;
-  const long M = (long)((e == 0) ? G.n[0] : G.n[0] + 5) * ((B == e) ? G.n[B] : G.n[B] + 5);
+  const int extA = (e == 0) ? G.n[0] : G.n[0] + 5;
+  const int shA = EDGE_ALIGN[e] ? line_shift(G.ng, (e == 0) ? 0 : -3) : 0;
+  const long rA = EDGE_ALIGN[e] ? (extA + shA + 15) / 16 * 16 : extA;
+  const long M = rA * ((B == e) ? G.n[B] : G.n[B] + 5);
   const long tiles = ((M + SX - 1) / SX) * ((G.n[c] + 5 + SF - 1) / SF);
   if (e == 0) hipLaunchKernelGGL((k_edge_lds<0, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, cons, tab, cd, cc, ed);
   if (e == 2) hipLaunchKernelGGL((k_edge_lds<2, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, cons, tab, cd, cc, ed);
