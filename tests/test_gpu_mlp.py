@@ -189,7 +189,7 @@ def test_grid_inversion_with_learned_guess_matches_oracle():
     dg = G.diagnostics()
     print("learned-guess torus: max rel err", e, "fallbacks", dg["n_mlp_fallback"], "iters",
           dg["newton_iters_sum"] / g.zones)
-    assert max(e.values()) < 1e-9, e
+    assert max(e.values()) < 1e-10, e
 
 
 @gpu
@@ -230,7 +230,7 @@ def test_learned_start_wins_when_warm_start_is_poor():
         # u^2 of the initial torus is zero up to round-off: absolute bound
         e = max_rel(gp, P, ("rho", "u1", "u3", "p"))
         e["u2"] = float(np.max(np.abs(gp["u2"] - P["u2"])))
-        assert max(e.values()) < 1e-9, (guess, e)
+        assert max(e.values()) < 1e-10, (guess, e)
         res[guess] = dg
     warm, learned = res[L.GUESS_WARM], res[L.GUESS_MLP]
     print("poor warm start: iterations warm %d learned %d, learned chosen %d of %d, fallbacks %d" % (
@@ -282,4 +282,4 @@ def test_network_start_beats_cold_start_on_the_torus():
     assert w["run_mlp_deferred"] == 0
     e = max_rel(prims["network"], prims["cold"], ("rho", "u1", "u3", "p"))
     e["u2"] = float(np.max(np.abs(prims["network"]["u2"] - prims["cold"]["u2"])))
-    assert max(e.values()) < 1e-9, e
+    assert max(e.values()) < 1e-10, e
