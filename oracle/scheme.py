@@ -25,7 +25,20 @@ after ECHO.  One right-hand-side evaluation, in order:
 SSP-RK3 (Shu & Osher 1988): U^(s) = a_s U^n + b_s (U^(s-1) + dt L(U^(s-1)))
 with (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3), every stage followed by the
 ghost fill of the face fields and the inversion (with floors) at interior
-cells.  dt = C / max_cells sum_d max(|lambda+_d|, |lambda-_d|)/Delta_d from
+cells.
+
+Lower-order fallback (option, off by default): the flux derivative is the
+difference of corrected face fluxes, D f = (G_{m+1/2} - G_{m-1/2}) / Delta
+with G = f - Delta^2 f / 24 + 3 Delta^4 f / 640 (sixth order; the fourth
+keeps the first correction).  After a stage's combination, an interior zone
+whose hydro state is unphysical -- D <= 0, tau <= 0 or S^2 >= (tau + D)^2
+(undensitised, S^2 with the inverse 3-metric) -- is troubled; at every face
+next to a troubled zone G is replaced by the first-order HLL flux of the two
+cells' states (the stage's primitives, face metric, normal face field; 0
+where sqrt(gamma) = 0), and both zones sharing the face take the
+difference: U_m -= b dt (F1 - G)/Delta, U_{m+1} += b dt (F1 - G)/Delta
+(conservative).  Neighbours across a periodic boundary are the zones at the
+other end; ghost zones are not corrected.  Applied once per stage.  dt = C / max_cells sum_d max(|lambda+_d|, |lambda-_d|)/Delta_d from
 P^n with the centre metric.
 """
 import math
@@ -112,9 +125,12 @@ class Solver:
     deriv_order: order of the staggered derivative and interpolation, 6
     (default) or 4; one order serves the flux derivative, the induction
     equation, the curl of the vector potential, the centred field and div B,
-    so the discrete div B stays zero."""
+    so the discrete div B stays zero.
+    fallback: the lower-order fallback at the faces of troubled zones (module
+    docstring); n_troubled counts the troubled zones over all stages."""
 
-    def __init__(self, grid, tables=None, precision="fp64", recon="mp5", deriv_order=6):
+    def __init__(self, grid, tables=None, precision="fp64", recon="mp5", deriv_order=6,
+                 fallback=False):
         if recon not in RECON_METHODS:
             raise ValueError("unknown reconstruction %r" % (recon,))
         if deriv_order not in (4, 6):
@@ -123,6 +139,8 @@ class Solver:
             raise ValueError("%s needs %d ghost layers" % (recon, NG_OF[recon]))
         self.recon = recon
         self.order = deriv_order
+        self.fallback = fallback
+        self.n_troubled = 0
         self.grid = grid
         self.ftype = np.float32 if precision == "fp32" else np.float64
         self.g = grid.ng
@@ -423,13 +441,93 @@ class Solver:
             tot = tot + np.maximum(np.abs(lp), np.abs(lm)) / gr.dx[d]
         return gr.cfl / float(np.max(tot))
 
+    # ---------------------------------------------------------- fallback
+    def first_order_face_fluxes(self, d):
+        """First-order HLL hydro fluxes at the d-faces -1/2 .. n-1/2 (stored
+        -1 .. n-1) from the states of the two cells beside each face."""
+        g, gr, gam = self.g, self.grid, self.gam
+        n = gr.n[d]
+        lo, hi = -1, n
+        rec = {k: (take(self.P[k], d, lo, hi, g), take(self.P[k], d, lo + 1, hi + 1, g))
+               for k in PRIM}
+        mf = Metric.sel(self.met.loc[FACE_LOC[d]], d, lo, hi, g)
+        sg = mf["sqrtg"]
+        bn_face = take(self.U["Bf%d" % (d + 1)], d, lo, hi, g)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            bn = np.where(sg != 0.0, bn_face / np.where(sg != 0.0, sg, 1.0), 0.0)
+        sts = []
+        for side in (0, 1):
+            u = tuple(rec["u%d" % (t + 1)][side] for t in range(3))
+            b = tuple(bn if t == d else rec["B%d" % (t + 1)][side] for t in range(3))
+            sts.append(state(rec["rho"][side], u, rec["p"][side], b, mf, gam))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            fl, fr = flux(sts[0], mf, d), flux(sts[1], mf, d)
+            ul, ur = cons(sts[0], mf), cons(sts[1], mf)
+        lpl, lml = speeds(sts[0], mf, d, gam)
+        lpr, lmr = speeds(sts[1], mf, d, gam)
+        ap, am = hll_speeds(lpl, lml, lpr, lmr)
+        axis = np.broadcast_to(sg == 0.0, ap.shape)
+        out = {}
+        with np.errstate(divide="ignore", invalid="ignore"):
+            for q, name in enumerate(HYDRO):
+                out[name] = np.where(axis, 0.0, hll_flux(fl[q], fr[q], ul[q], ur[q], ap, am))
+        return out
+
+    def troubled(self, new):
+        """Interior zones whose hydro state `new` (densitised) is unphysical."""
+        from .physics import raise_
+        m = self.centre_metric()
+        sg = m["sqrtg"]
+        dd, tau = new["D"] / sg, new["tau"] / sg
+        s = (new["S1"] / sg, new["S2"] / sg, new["S3"] / sg)
+        su = raise_(m, s)
+        s2 = s[0] * su[0] + s[1] * su[1] + s[2] * su[2]
+        return (dd <= 0.0) | (tau <= 0.0) | (s2 >= (tau + dd) ** 2)
+
+    def corrected_flux(self, f, d):
+        """G at the d-faces -1/2 .. n-1/2 from the face fluxes f."""
+        g, n = self.g, self.grid.n[d]
+        t = lambda s: take(f, d, -1 + s, n + s, g)
+        if self.order == 4:
+            return t(0) - (t(1) - 2.0 * t(0) + t(-1)) / 24.0
+        return (t(0) - (t(1) - 2.0 * t(0) + t(-1)) / 24.0
+                + 3.0 * (t(2) - 4.0 * t(1) + 6.0 * t(0) - 4.0 * t(-1) + t(-2)) / 640.0)
+
+    def apply_fallback(self, new, fdat, b, dt):
+        g, gr = self.g, self.grid
+        bad = self.troubled(new)
+        self.n_troubled += int(bad.sum())
+        if not bad.any():
+            return new
+        out = dict(new)
+        for d in range(3):
+            ax, n = fd.AXIS[d], gr.n[d]
+            periodic = gr.bc[2 * d] == 0
+            widths = [(1, 1) if a_ == ax else (0, 0) for a_ in range(3)]
+            pad = np.pad(bad, widths, mode="wrap") if periodic else np.pad(bad, widths, constant_values=False)
+            lo_sl, hi_sl = [slice(None)] * 3, [slice(None)] * 3
+            lo_sl[ax], hi_sl[ax] = slice(0, n + 1), slice(1, n + 2)
+            face_bad = pad[tuple(lo_sl)] | pad[tuple(hi_sl)]        # faces -1/2 .. n-1/2
+            f1 = self.first_order_face_fluxes(d)
+            for name in HYDRO:
+                G = _restrict_others(self.corrected_flux(fdat[d]["F_" + name], d), d, g, gr)
+                F1 = _restrict_others(f1[name], d, g, gr)
+                delta = np.where(face_bad, F1 - G, 0.0)
+                up, dn = [slice(None)] * 3, [slice(None)] * 3
+                up[ax], dn[ax] = slice(1, n + 1), slice(0, n)
+                out[name] = out[name] - b * dt * (delta[tuple(up)] - delta[tuple(dn)]) / gr.dx[d]
+        return out
+
     def stage(self, un, a, b, dt):
         g = self.g
         fill_centred(self.P, self.grid)
-        lh, lf, _, _ = self.rhs_parts()
+        lh, lf, fdat, _ = self.rhs_parts()
+        new = {name: rk_combine(self.interior(un[name]), self.interior(self.U[name]), lh[name], a, b, dt)
+               for name in HYDRO}
+        if self.fallback:
+            new = self.apply_fallback(new, fdat, b, dt)
         for name in HYDRO:
-            cur = self.interior(self.U[name])
-            self.set_interior(self.U[name], rk_combine(self.interior(un[name]), cur, lh[name], a, b, dt))
+            self.set_interior(self.U[name], new[name])
         for name in FACE:
             cur = self.interior(self.U[name])
             self.set_interior(self.U[name], rk_combine(self.interior(un[name]), cur, lf[name], a, b, dt))
