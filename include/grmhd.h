@@ -105,7 +105,18 @@ typedef struct {
                               correction only); one order serves the flux
                               derivative, the induction equation, the curl of
                               the vector potential, the centred field and div B */
-  int32_t reserved;        /* must be 0                                           */
+  int32_t fallback;        /* 0: off; 1: lower-order fallback at troubled zones. A
+                              zone whose new hydro state after a stage's update is
+                              unphysical (D <= 0, tau <= 0 or S^2 >= (tau + D)^2)
+                              is troubled; at each face of a troubled zone the
+                              stage replaces the high-order flux (the face flux G
+                              = f - Delta^2 f/24 + 3 Delta^4 f/640 whose difference
+                              is the staggered derivative; its first correction
+                              alone at deriv_order 4) by the first-order HLL flux
+                              of the two cells, in both zones beside the face
+                              (conservative).  Off: the step is unchanged bit for
+                              bit.  On: the update runs as two launches around the
+                              fix, plus a flag byte per zone                      */
 } grmhd_grid_desc;
 
 typedef struct {
@@ -139,6 +150,8 @@ typedef struct {
   int64_t run_mlp_deferred;  /* zones inverted in the learned-guess pass        */
   int64_t run_mlp_chosen;    /* zones that started from the network's guess     */
   int64_t run_mlp_fallback;  /* learned starts rerun from the warm guess         */
+  int64_t run_troubled;    /* zones taken by the lower-order fallback (summed over
+                              the stages; 0 unless grmhd_grid_desc.fallback)   */
 } grmhd_diag;
 
 /* Create a grid.  desc is copied.  hip_stream: hipStream_t or NULL.

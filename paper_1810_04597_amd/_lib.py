@@ -37,7 +37,7 @@ class GridDesc(C.Structure):
                 ("x0", C.c_double * 3), ("dx", C.c_double * 3), ("gamma_ad", C.c_double),
                 ("cfl", C.c_double), ("rho_fl_a", C.c_double), ("rho_fl_n", C.c_double),
                 ("p_fl_a", C.c_double), ("p_fl_n", C.c_double), ("w_max", C.c_double),
-                ("newton_tol", C.c_double), ("deriv_order", C.c_int32), ("reserved", C.c_int32)]
+                ("newton_tol", C.c_double), ("deriv_order", C.c_int32), ("fallback", C.c_int32)]
 
 
 class Layout(C.Structure):
@@ -59,7 +59,7 @@ class Diag(C.Structure):
                 ("run_c2p_fail", C.c_int64), ("run_floor_rho", C.c_int64),
                 ("run_floor_p", C.c_int64), ("run_wcap", C.c_int64),
                 ("run_mlp_deferred", C.c_int64), ("run_mlp_chosen", C.c_int64),
-                ("run_mlp_fallback", C.c_int64)]
+                ("run_mlp_fallback", C.c_int64), ("run_troubled", C.c_int64)]
 
     def as_dict(self):
         out = {}
@@ -140,7 +140,7 @@ def check(rc):
     return rc
 
 
-def make_desc(grid, precision=FP64, guess=GUESS_WARM, recon=RECON_MP5, deriv_order=6):
+def make_desc(grid, precision=FP64, guess=GUESS_WARM, recon=RECON_MP5, deriv_order=6, fallback=False):
     """GridDesc from a workloads.GridSpec-like object."""
     d = GridDesc()
     for a in range(3):
@@ -162,7 +162,7 @@ def make_desc(grid, precision=FP64, guess=GUESS_WARM, recon=RECON_MP5, deriv_ord
     d.w_max = grid.w_max
     d.newton_tol = grid.newton_tol
     d.deriv_order = deriv_order
-    d.reserved = 0
+    d.fallback = 1 if fallback else 0
     return d
 
 

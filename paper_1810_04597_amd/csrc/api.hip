@@ -19,7 +19,8 @@ static_assert(sizeof(grmhd_grid_desc) == 184 && offsetof(grmhd_grid_desc, recon)
                   offsetof(grmhd_grid_desc, newton_tol) == 168 &&
                   offsetof(grmhd_grid_desc, deriv_order) == 176,
               "grmhd_grid_desc layout");
-static_assert(sizeof(grmhd_diag) == 272 && offsetof(grmhd_diag, run_c2p_fail) == 216,
+static_assert(sizeof(grmhd_diag) == 280 && offsetof(grmhd_diag, run_c2p_fail) == 216 &&
+                  offsetof(grmhd_diag, run_troubled) == 272,
               "grmhd_diag layout, which the Python binding mirrors");
 static_assert(GRMHD_RECON_MP5 == grmhd::RECON_MP5 && GRMHD_RECON_WENO5 == grmhd::RECON_WENO5 &&
                   GRMHD_RECON_PLM == grmhd::RECON_PLM && GRMHD_RECON_MP7 == grmhd::RECON_MP7,
@@ -119,6 +120,8 @@ struct grmhd_grid {
   long long* d_spart = nullptr;  // per-block inversion statistics
   long long* d_stats = nullptr;  // reduced inversion statistics (8)
   unsigned long long* d_run = nullptr;  // accumulated inversion counters (RUN_SLOTS x RUN_STRIDE)
+  unsigned char* d_trouble = nullptr;   // lower-order fallback: a flag per interior zone
+  int* d_ntrouble = nullptr;            // troubled zones of the current stage
   double* d_diag = nullptr;      // reduced diagnostics (16)
   unsigned nblk = 0;
   int64_t step = 0;
@@ -213,7 +216,7 @@ int validate(const grmhd_grid_desc* d) {
   if (d->recon == GRMHD_RECON_MP7 && d->ng != 6) return fail(GRMHD_EINVAL, "MP7 needs ng = 6");
   if (d->deriv_order != 0 && d->deriv_order != 4 && d->deriv_order != 6)
     return fail(GRMHD_EINVAL, "deriv_order must be 0, 4 or 6");
-  if (d->reserved != 0) return fail(GRMHD_EINVAL, "reserved must be 0");
+  if (d->fallback != 0 && d->fallback != 1) return fail(GRMHD_EINVAL, "fallback must be 0 or 1");
   return GRMHD_OK;
 }
 
@@ -321,6 +324,11 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** 
   if (e == hipSuccess) e = hipMalloc(&h->d_diag, (DIAG_NSUM + DIAG_NMAX) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc(&h->d_run, (size_t)RUN_SLOTS * RUN_STRIDE * sizeof(unsigned long long));
   if (e == hipSuccess) launch_zero_u64(h->d_run, RUN_SLOTS * RUN_STRIDE, h->stream);
+  if (e == hipSuccess && desc->fallback) {
+    e = hipMalloc(&h->d_trouble, (size_t)desc->n[0] * desc->n[1] * desc->n[2]);
+    if (e == hipSuccess) e = hipMalloc(&h->d_ntrouble, sizeof(int));
+    if (e == hipSuccess) launch_zero_int(h->d_ntrouble, h->stream);
+  }
   if (e == hipSuccess) e = hipMemsetAsync(h->d_dt, 0, 3 * sizeof(double), h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->d_stats, 0, C2P_NSTAT * sizeof(long long), h->stream);
   if (e != hipSuccess) {
@@ -505,10 +513,27 @@ static void step_stages(grmhd_grid* h, double dt) {
     double* const cur = s == 0 ? Un : S;        // state the stage's RHS reads
     double* const next = s == 2 ? Un : S;       // state the stage produces
     rhs_pieces(h, !img, cur);
+    const bool fp32 = h->desc.precision == GRMHD_FP32_FLUX;
     h->timed(7, [&] {
-      launch_update(h->G, h->flat, h->desc.precision == GRMHD_FP32_FLUX, 0, h->prim, s == 0 ? Un : S,
-                    s == 0 ? S : Un, h->flux(), h->edges(),
-                    h->tab, A[s], B[s], dt, dt_src, nullptr, s + 1, h->stream, img ? 1 : 0);
+      if (!h->desc.fallback) {
+        launch_update(h->G, h->flat, fp32, 0, h->prim, s == 0 ? Un : S, s == 0 ? S : Un, h->flux(),
+                      h->edges(), h->tab, A[s], B[s], dt, dt_src, nullptr, s + 1, h->stream, img ? 1 : 0);
+      } else {
+        // lower-order fallback: the hydro update flags troubled zones, the
+        // fix replaces the fluxes at their faces (reading the face fields of
+        // the stage's start, which stage 2 updates in place), then the
+        // induction update
+        UpdateFallback fb{h->d_trouble, h->d_ntrouble};
+        launch_zero_int(h->d_ntrouble, h->stream);
+        launch_update(h->G, h->flat, fp32, 0, h->prim, s == 0 ? Un : S, s == 0 ? S : Un, h->flux(),
+                      h->edges(), h->tab, A[s], B[s], dt, dt_src, nullptr, s + 1, h->stream, img ? 1 : 0,
+                      UPD_HYDRO, &fb);
+        launch_fallback(h->G, h->flat, fp32, h->bc, h->prim, cur, next, h->flux(), h->tab, h->d_trouble,
+                        h->d_ntrouble, B[s], dt, dt_src, h->d_run, h->stream);
+        launch_update(h->G, h->flat, fp32, 0, h->prim, s == 0 ? Un : S, s == 0 ? S : Un, h->flux(),
+                      h->edges(), h->tab, A[s], B[s], dt, dt_src, nullptr, s + 1, h->stream, img ? 1 : 0,
+                      UPD_INDUCTION);
+      }
     });
     // dt and time are recorded once the last update has consumed d_dt[2]
     if (s == 2) h->timed(12, [&] { launch_advance(h->d_dt, dt_src, dt, h->stream); });
@@ -699,7 +724,7 @@ int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out) {
   out->n_wcap = st[5];
   out->n_mlp_fallback = st[6];
   out->n_mlp_chosen = st[7];
-  int64_t acc[RUN_NCOUNT] = {0, 0, 0, 0};
+  int64_t acc[RUN_NCOUNT] = {0};
   for (int sl = 0; sl < RUN_SLOTS; ++sl)
     for (int q = 0; q < RUN_NCOUNT; ++q) acc[q] += (int64_t)run[(size_t)sl * RUN_STRIDE + q];
   out->run_c2p_fail = acc[0];
@@ -709,6 +734,7 @@ int grmhd_diagnostics(grmhd_grid* h, grmhd_diag* out) {
   out->run_mlp_deferred = acc[4];
   out->run_mlp_chosen = acc[5];
   out->run_mlp_fallback = acc[6];
+  out->run_troubled = acc[7];
   return GRMHD_OK;
 }
 
@@ -920,6 +946,8 @@ void grmhd_destroy(grmhd_grid* h) {
   (void)hipFree(h->d_stats);
   (void)hipFree(h->d_diag);
   (void)hipFree(h->d_run);
+  (void)hipFree(h->d_trouble);
+  (void)hipFree(h->d_ntrouble);
   delete h;
 }
 

@@ -200,13 +200,15 @@ GR_HD T plm_mc(T qm1, T q0, T qp1) {
 }
 
 // Interface reconstructions: RECON_MP5 (default), RECON_WENO5, RECON_PLM,
-// RECON_MP7.
-constexpr int RECON_MP5 = 0, RECON_WENO5 = 1, RECON_PLM = 2, RECON_MP7 = 3;
+// RECON_MP7; RECON_PCM (the cell values themselves, first order) is internal:
+// the lower-order fallback's face fluxes.
+constexpr int RECON_MP5 = 0, RECON_WENO5 = 1, RECON_PLM = 2, RECON_MP7 = 3, RECON_PCM = 4;
 
 // Cells a reconstruction reads for face f+1/2: W cells f-LO .. f-LO+W-1
 // (both states); cell f is c[LO], cell f+1 is c[LO+1].
 template <int RC> struct Stencil { static constexpr int W = 6, LO = 2; };
 template <> struct Stencil<RECON_MP7> { static constexpr int W = 8, LO = 3; };
+template <> struct Stencil<RECON_PCM> { static constexpr int W = 2, LO = 0; };
 
 template <int RC, typename T>
 GR_HD void recon_lr(const T c[Stencil<RC>::W], T& l, T& r) {
@@ -219,6 +221,9 @@ GR_HD void recon_lr(const T c[Stencil<RC>::W], T& l, T& r) {
   } else if constexpr (RC == RECON_PLM) {
     l = plm_mc(c[1], c[2], c[3]);
     r = plm_mc(c[4], c[3], c[2]);
+  } else if constexpr (RC == RECON_PCM) {
+    l = c[0];
+    r = c[1];
   } else {
     mp5_lr(c, l, r);
   }

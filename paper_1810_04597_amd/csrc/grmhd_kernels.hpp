@@ -27,8 +27,9 @@ struct C2PParams {
 // each slot sits on its own 128-byte line.  The host sums the slots.
 // Counters: failed zones, rho floors, p floors, W caps, zones inverted in the
 // learned-guess pass, zones started from the network's guess, learned starts
-// rerun from the warm guess.
-constexpr int RUN_NCOUNT = 7;
+// rerun from the warm guess, zones taken by the lower-order fallback.
+constexpr int RUN_NCOUNT = 8;
+constexpr int RUN_TROUBLED = 7;
 constexpr int RUN_SLOTS = 64;
 constexpr int RUN_STRIDE = 16;
 
@@ -59,10 +60,31 @@ void launch_edge(int e, const Geom& G, bool flat, bool fp32, int recon, const do
 // face fields are also written to their ghost images (no separate face fill).
 // fp32: flux and edges hold float fields (the FP32 form's storage), read at
 // the same element offsets.
+// parts (mode 0): UPD_ALL, or the hydro fields alone (UPD_HYDRO, which also
+// writes the fallback's flag per interior zone, 1 where the new state is
+// unphysical, and counts those zones into fb->count) or the face fields alone
+// (UPD_INDUCTION, with the ghost images when img).
+enum { UPD_HYDRO = 1, UPD_INDUCTION = 2, UPD_ALL = 3 };
+struct UpdateFallback {
+  unsigned char* flags;   // n1 n2 n3 bytes, x^1 fastest
+  int* count;             // zeroed before the launch
+};
 void launch_update(const Geom& G, bool flat, bool fp32, int mode, const double* prim, double* x, double* y,
                    const double* flux, const double* edges, const double* tab, double a, double b,
                    double dt_host, const double* d_dt, double* out, int stage, hipStream_t s,
-                   int img = 0);
+                   int img = 0, int parts = UPD_ALL, const UpdateFallback* fb = nullptr);
+// Lower-order fallback of one stage (after the UPD_HYDRO update, before the
+// UPD_INDUCTION one): each interior zone with a flagged zone on either side of
+// one of its faces (periodic directions wrap; elsewhere zones outside count as
+// unflagged) adds b dt times the difference of (F1 - G) over those faces to
+// its new hydro state in `next`, F1 the first-order HLL flux from the
+// primitives of the two cells and the face field in `cur`, G the corrected
+// flux of the stored face fluxes.  Exits at once when count is 0; adds count
+// to the accumulated counters (run_acc, nullable).
+void launch_fallback(const Geom& G, bool flat, bool fp32, const BCSpec& bc, const double* prim,
+                     const double* cur, double* next, const double* flux, const double* tab,
+                     const unsigned char* flags, const int* count, double b, double dt_host,
+                     const double* d_dt, unsigned long long* run_acc, hipStream_t s);
 void launch_advance(double* d_dt, const double* src, double dt_host, hipStream_t s);
 // Inversion of all interior zones; per-block counters into partials[0, nblk),
 // CFL partials (nullable) into cfl_partials[0, nblk).  list != nullptr: defer

@@ -138,9 +138,30 @@ __device__ __forceinline__ double rk_store_rt(double* __restrict__ x, double* __
   return rk_store<3>(x, y, o, a, b, dt, L);
 }
 
+// Troubled state of the lower-order fallback: the new (densitised) hydro
+// state nv = (D, S_1..3, tau) has D <= 0, tau <= 0 or S^2 >= (tau + D)^2 (no
+// physical primitives can give it); the comparisons are false for NaN.
+template <class MET>
+__device__ __forceinline__ bool troubled_state(const double nv[5], const MET& m) {
+  const double dd = m.undens(nv[0]), tau = m.undens(nv[4]);
+  const double sl[3] = {m.undens(nv[1]), m.undens(nv[2]), m.undens(nv[3])};
+  double su[3];
+  m.raise(sl, su);
+  const double s2 = sl[0] * su[0] + sl[1] * su[1] + sl[2] * su[2];
+  const double u = tau + dd;
+  return dd <= 0.0 || tau <= 0.0 || s2 >= u * u;
+}
+
+__device__ __forceinline__ void flag_zone(const Geom& G, int i, int j, int k, bool bad,
+                                          unsigned char* __restrict__ flags, int* __restrict__ count) {
+  flags[i + (long)G.n[0] * (j + (long)G.n[1] * k)] = bad ? 1 : 0;
+  if (bad) atomicAdd(count, 1);
+}
+
 // FS: storage type of the fluxes and edge fields (double, or float in the
-// FP32 form), widened to double on load.
-template <class MET, int DO, typename FS>
+// FP32 form), widened to double on load.  PARTS: UPD_ALL, UPD_HYDRO (with the
+// fallback's flags) or UPD_INDUCTION.
+template <class MET, int DO, typename FS, int PARTS>
 __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* __restrict__ prim,
                                                 double* __restrict__ x,
                                                 double* __restrict__ y,
@@ -148,65 +169,79 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
                                                 const FS* __restrict__ edges,
                                                 const double* __restrict__ tab, double a, double b,
                                                 double dt_host, const double* __restrict__ d_dt,
-                                                double* __restrict__ out, int stage) {
+                                                double* __restrict__ out, int stage,
+                                                unsigned char* __restrict__ tflags,
+                                                int* __restrict__ tcount) {
   const long t = flat_thread();
   if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
   int i, j, k;
   zone_of(G, strip_zone_order<UPDATE_STRIP>(G, t), i, j, k);
   const long c = G.idx(i, j, k);
-  double src[5] = {0, 0, 0, 0, 0};
-  if constexpr (!MET::flat) {
-    const long tt = G.tidx(i, j);
-    MET m;
-    m.load(tab, G.tab_plane, LOC_C, tt);
-    PState<double> s;
-    s.rho = prim[P_RHO * G.field + c];
-    s.p = prim[P_P * G.field + c];
-    for (int q = 0; q < 3; ++q) {
-      s.u[q] = prim[(P_U1 + q) * G.field + c];
-      s.B[q] = prim[(P_B1 + q) * G.field + c];
+  auto stage_dt = [&]() { return (mode != 0) ? 0.0 : (dt_host > 0.0 ? dt_host : *d_dt); };
+  double dt = 0.0, f[6];
+  if constexpr ((PARTS & UPD_HYDRO) != 0) {
+    double src[5] = {0, 0, 0, 0, 0};
+    if constexpr (!MET::flat) {
+      const long tt = G.tidx(i, j);
+      MET m;
+      m.load(tab, G.tab_plane, LOC_C, tt);
+      PState<double> s;
+      s.rho = prim[P_RHO * G.field + c];
+      s.p = prim[P_P * G.field + c];
+      for (int q = 0; q < 3; ++q) {
+        s.u[q] = prim[(P_U1 + q) * G.field + c];
+        s.B[q] = prim[(P_B1 + q) * G.field + c];
+      }
+      make_state(s, m, G.gam);
+      sources_of(s, m, tab, G.tab_plane, tt, src);
     }
-    make_state(s, m, G.gam);
-    sources_of(s, m, tab, G.tab_plane, tt, src);
-  }
-  const double dt = (mode != 0) ? 0.0 : (dt_host > 0.0 ? dt_host : *d_dt);
-  double f[6];
+    dt = stage_dt();
+    double nv[5];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    double L = 0.0;
+    for (int q = 0; q < 5; ++q) {
+      double L = 0.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const FS* fp = flux + ((long)d * 5 + q) * G.field + c;
-      const long st = G.stride(d);
+      for (int d = 0; d < 3; ++d) {
+        const FS* fp = flux + ((long)d * 5 + q) * G.field + c;
+        const long st = G.stride(d);
 #pragma unroll
-      for (int s = 0; s < 6; ++s) f[s] = fp[(s - 3) * st];
-      L = L - fd_deriv_o<DO>(f, 1.0 / G.dx[d]);
+        for (int s = 0; s < 6; ++s) f[s] = fp[(s - 3) * st];
+        L = L - fd_deriv_o<DO>(f, 1.0 / G.dx[d]);
+      }
+      L = L + src[q];
+      const long o = (long)q * G.field + c;
+      if (mode == 0)
+        nv[q] = rk_store_rt(x, y, o, a, b, dt, L, stage);
+      else
+        out[o] = L;
     }
-    L = L + src[q];
-    const long o = (long)q * G.field + c;
-    if (mode == 0)
-      rk_store_rt(x, y, o, a, b, dt, L, stage);
-    else
-      out[o] = L;
+    if constexpr (PARTS == UPD_HYDRO) {
+      MET mc;
+      if constexpr (!MET::flat) mc.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
+      flag_zone(G, i, j, k, troubled_state(nv, mc), tflags, tcount);
+    }
   }
+  if constexpr ((PARTS & UPD_INDUCTION) != 0) {
+    if constexpr ((PARTS & UPD_HYDRO) == 0) dt = stage_dt();
 #pragma unroll
-  for (int nd = 0; nd < 3; ++nd) {
-    const int d1 = (nd + 1) % 3, d2 = (nd + 2) % 3;
-    const FS* e2 = edges + (long)d2 * G.field + c;
-    const FS* e1 = edges + (long)d1 * G.field + c;
-    const long s1 = G.stride(d1), s2 = G.stride(d2);
+    for (int nd = 0; nd < 3; ++nd) {
+      const int d1 = (nd + 1) % 3, d2 = (nd + 2) % 3;
+      const FS* e2 = edges + (long)d2 * G.field + c;
+      const FS* e1 = edges + (long)d1 * G.field + c;
+      const long s1 = G.stride(d1), s2 = G.stride(d2);
 #pragma unroll
-    for (int s = 0; s < 6; ++s) f[s] = e2[(s - 3) * s1];
-    const double t1 = fd_deriv_o<DO>(f, 1.0 / G.dx[d1]);
+      for (int s = 0; s < 6; ++s) f[s] = e2[(s - 3) * s1];
+      const double t1 = fd_deriv_o<DO>(f, 1.0 / G.dx[d1]);
 #pragma unroll
-    for (int s = 0; s < 6; ++s) f[s] = e1[(s - 3) * s2];
-    const double t2 = fd_deriv_o<DO>(f, 1.0 / G.dx[d2]);
-    const double L = -t1 + t2;
-    const long o = (long)(C_BF1 + nd) * G.field + c;
-    if (mode == 0)
-      rk_store_rt(x, y, o, a, b, dt, L, stage);
-    else
-      out[o] = L;
+      for (int s = 0; s < 6; ++s) f[s] = e1[(s - 3) * s2];
+      const double t2 = fd_deriv_o<DO>(f, 1.0 / G.dx[d2]);
+      const double L = -t1 + t2;
+      const long o = (long)(C_BF1 + nd) * G.field + c;
+      if (mode == 0)
+        rk_store_rt(x, y, o, a, b, dt, L, stage);
+      else
+        out[o] = L;
+    }
   }
 }
 
@@ -215,9 +250,11 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
 // KZ zones along x^3.  The x^3 stencils (F of the x^3 sweep, E_1, E_2) are
 // kept in register windows, so each of their planes is read once per
 // segment instead of six times; x^1 and x^2 stencils are read per plane.
+// PARTS as in k_update (the hydro and the induction parts read disjoint
+// fields, so the split costs a launch, not bytes).
 constexpr int KZ = 16;
 
-template <class MET, int ST, int DO, typename FS>
+template <class MET, int ST, int DO, typename FS, int PARTS>
 __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restrict__ prim,
                                                    double* __restrict__ x,
                                                    double* __restrict__ y,
@@ -225,7 +262,10 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
                                                    const FS* __restrict__ edges,
                                                    const double* __restrict__ tab, double a,
                                                    double b, double dt_host,
-                                                   const double* __restrict__ d_dt, int img) {
+                                                   const double* __restrict__ d_dt, int img,
+                                                   unsigned char* __restrict__ tflags,
+                                                   int* __restrict__ tcount) {
+  constexpr bool HYD = (PARTS & UPD_HYDRO) != 0, IND = (PARTS & UPD_INDUCTION) != 0;
   const long t = flat_thread();
   const int nseg = (G.n[2] + KZ - 1) / KZ;
   if (t >= (long)G.n[0] * G.n[1] * nseg) return;
@@ -247,67 +287,85 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
 #pragma unroll
   for (int s = 0; s < 5; ++s) {
     const long cs = c + (s - 3) * sz;
+    if constexpr (HYD) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) wf[q][s] = fz[(long)q * G.field + cs];
-    w1[s] = e1[cs];
-    w2[s] = e2[cs];
+      for (int q = 0; q < 5; ++q) wf[q][s] = fz[(long)q * G.field + cs];
+    }
+    if constexpr (IND) {
+      w1[s] = e1[cs];
+      w2[s] = e2[cs];
+    }
   }
   for (int k = k0; k < k1; ++k, c += sz) {
     const long cn = c + 2 * sz;
+    if constexpr (HYD) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) wf[q][5] = fz[(long)q * G.field + cn];
-    w1[5] = e1[cn];
-    w2[5] = e2[cn];
+      for (int q = 0; q < 5; ++q) wf[q][5] = fz[(long)q * G.field + cn];
+    }
+    if constexpr (IND) {
+      w1[5] = e1[cn];
+      w2[5] = e2[cn];
+    }
     double f[6], bf[3];
+    if constexpr (HYD) {
+      double nv[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      double L = 0.0;
-      const FS* fx = flux + (long)q * G.field + c;
-      const FS* fy = flux + (5L + q) * G.field + c;
+      for (int q = 0; q < 5; ++q) {
+        double L = 0.0;
+        const FS* fx = flux + (long)q * G.field + c;
+        const FS* fy = flux + (5L + q) * G.field + c;
 #pragma unroll
-      for (int s = 0; s < 6; ++s) f[s] = fx[(s - 3) * sx];
-      L = L - fd_deriv_o<DO>(f, idx0);
+        for (int s = 0; s < 6; ++s) f[s] = fx[(s - 3) * sx];
+        L = L - fd_deriv_o<DO>(f, idx0);
 #pragma unroll
-      for (int s = 0; s < 6; ++s) f[s] = fy[(s - 3) * sy];
-      L = L - fd_deriv_o<DO>(f, idx1);
-      L = L - fd_deriv_o<DO>(wf[q], idx2);
-      rk_store<ST>(x, y, (long)q * G.field + c, a, b, dt, L);
-    }
-    // B^1: -D_2 E_3 + D_3 E_2
-    {
-#pragma unroll
-      for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sy];
-      const double L = -fd_deriv_o<DO>(f, idx1) + fd_deriv_o<DO>(w2, idx2);
-      bf[0] = rk_store<ST>(x, y, (long)C_BF1 * G.field + c, a, b, dt, L);
-    }
-    // B^2: -D_3 E_1 + D_1 E_3
-    {
-#pragma unroll
-      for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sx];
-      const double L = -fd_deriv_o<DO>(w1, idx2) + fd_deriv_o<DO>(f, idx0);
-      bf[1] = rk_store<ST>(x, y, (long)C_BF2 * G.field + c, a, b, dt, L);
-    }
-    // B^3: -D_1 E_2 + D_2 E_1
-    {
-      double g2[6];
-#pragma unroll
-      for (int s = 0; s < 6; ++s) {
-        f[s] = e2[c + (s - 3) * sx];
-        g2[s] = e1[c + (s - 3) * sy];
+        for (int s = 0; s < 6; ++s) f[s] = fy[(s - 3) * sy];
+        L = L - fd_deriv_o<DO>(f, idx1);
+        L = L - fd_deriv_o<DO>(wf[q], idx2);
+        nv[q] = rk_store<ST>(x, y, (long)q * G.field + c, a, b, dt, L);
       }
-      const double L = -fd_deriv_o<DO>(f, idx0) + fd_deriv_o<DO>(g2, idx1);
-      bf[2] = rk_store<ST>(x, y, (long)C_BF3 * G.field + c, a, b, dt, L);
+      if constexpr (!IND) flag_zone(G, i, j, k, troubled_state(nv, MET()), tflags, tcount);
     }
-    if (img) {
-      constexpr int ff[3] = {C_BF1, C_BF2, C_BF3};
-      write_images<3>(G, ST == 2 ? x : y, i, j, k, ff, bf);
+    if constexpr (IND) {
+      // B^1: -D_2 E_3 + D_3 E_2
+      {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sy];
+        const double L = -fd_deriv_o<DO>(f, idx1) + fd_deriv_o<DO>(w2, idx2);
+        bf[0] = rk_store<ST>(x, y, (long)C_BF1 * G.field + c, a, b, dt, L);
+      }
+      // B^2: -D_3 E_1 + D_1 E_3
+      {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) f[s] = e3[c + (s - 3) * sx];
+        const double L = -fd_deriv_o<DO>(w1, idx2) + fd_deriv_o<DO>(f, idx0);
+        bf[1] = rk_store<ST>(x, y, (long)C_BF2 * G.field + c, a, b, dt, L);
+      }
+      // B^3: -D_1 E_2 + D_2 E_1
+      {
+        double g2[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          f[s] = e2[c + (s - 3) * sx];
+          g2[s] = e1[c + (s - 3) * sy];
+        }
+        const double L = -fd_deriv_o<DO>(f, idx0) + fd_deriv_o<DO>(g2, idx1);
+        bf[2] = rk_store<ST>(x, y, (long)C_BF3 * G.field + c, a, b, dt, L);
+      }
+      if (img) {
+        constexpr int ff[3] = {C_BF1, C_BF2, C_BF3};
+        write_images<3>(G, ST == 2 ? x : y, i, j, k, ff, bf);
+      }
     }
 #pragma unroll
     for (int s = 0; s < 5; ++s) {
+      if constexpr (HYD) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q) wf[q][s] = wf[q][s + 1];
-      w1[s] = w1[s + 1];
-      w2[s] = w2[s + 1];
+        for (int q = 0; q < 5; ++q) wf[q][s] = wf[q][s + 1];
+      }
+      if constexpr (IND) {
+        w1[s] = w1[s + 1];
+        w2[s] = w2[s + 1];
+      }
     }
   }
 }
@@ -735,52 +793,82 @@ void launch_bc_faces(const Geom& G, const BCSpec& bc, double* cons, hipStream_t 
   hipLaunchKernelGGL(k_bc_faces, dim3(nblk(ghost_count(G, bc.bc[2] == 2))), dim3(256), 0, s, G, bc, cons);
 }
 
-template <int DO, typename FS>
-static void launch_update_o(const Geom& G, bool flat, int mode, const double* prim, double* x,
+template <int DO, typename FS, int PARTS>
+static void launch_update_p(const Geom& G, bool flat, int mode, const double* prim, double* x,
                             double* y, const FS* flux, const FS* edges,
                             const double* tab, double a, double b, double dt_host,
-                            const double* d_dt, double* out, int stage, hipStream_t s, int img) {
+                            const double* d_dt, double* out, int stage, hipStream_t s, int img,
+                            unsigned char* tflags, int* tcount) {
   const unsigned nb = zone_blocks(G);
   if (flat && mode == 0) {
     const long nseg = (G.n[2] + KZ - 1) / KZ;
     const unsigned ng = nblk((long)G.n[0] * G.n[1] * nseg);
     if (stage == 1)
-      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 1, DO, FS>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
-                         flux, edges, tab, a, b, dt_host, d_dt, img);
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 1, DO, FS, PARTS>), dim3(ng), dim3(256), 0, s, G, prim,
+                         x, y, flux, edges, tab, a, b, dt_host, d_dt, img, tflags, tcount);
     else if (stage == 2)
-      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 2, DO, FS>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
-                         flux, edges, tab, a, b, dt_host, d_dt, img);
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 2, DO, FS, PARTS>), dim3(ng), dim3(256), 0, s, G, prim,
+                         x, y, flux, edges, tab, a, b, dt_host, d_dt, img, tflags, tcount);
     else
-      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 3, DO, FS>), dim3(ng), dim3(256), 0, s, G, prim, x, y,
-                         flux, edges, tab, a, b, dt_host, d_dt, img);
-  } else if (flat)
-    hipLaunchKernelGGL((k_update<FlatMet<double>, DO, FS>), dim3(nb), dim3(256), 0, s, G, mode, prim, x, y,
-                       flux, edges, tab, a, b, dt_host, d_dt, out, stage);
+      hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 3, DO, FS, PARTS>), dim3(ng), dim3(256), 0, s, G, prim,
+                         x, y, flux, edges, tab, a, b, dt_host, d_dt, img, tflags, tcount);
+  } else if (flat) {
+    // the right-hand side alone (mode 1): every field
+    if constexpr (PARTS == UPD_ALL)
+      hipLaunchKernelGGL((k_update<FlatMet<double>, DO, FS, UPD_ALL>), dim3(nb), dim3(256), 0, s, G, mode,
+                         prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, tflags, tcount);
+  } else {
+    hipLaunchKernelGGL((k_update<TabMet<double>, DO, FS, PARTS>), dim3(nb), dim3(256), 0, s, G, mode, prim,
+                       x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, tflags, tcount);
+  }
+}
+
+template <int DO, typename FS>
+static void launch_update_o(const Geom& G, bool flat, int mode, const double* prim, double* x,
+                            double* y, const FS* flux, const FS* edges,
+                            const double* tab, double a, double b, double dt_host,
+                            const double* d_dt, double* out, int stage, hipStream_t s, int img,
+                            int parts, unsigned char* tflags, int* tcount) {
+  if (parts == UPD_HYDRO)
+    launch_update_p<DO, FS, UPD_HYDRO>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out,
+                                       stage, s, img, tflags, tcount);
+  else if (parts == UPD_INDUCTION)
+    launch_update_p<DO, FS, UPD_INDUCTION>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt,
+                                           out, stage, s, img, tflags, tcount);
   else
-    hipLaunchKernelGGL((k_update<TabMet<double>, DO, FS>), dim3(nb), dim3(256), 0, s, G, mode, prim, x, y,
-                       flux, edges, tab, a, b, dt_host, d_dt, out, stage);
+    launch_update_p<DO, FS, UPD_ALL>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out,
+                                     stage, s, img, tflags, tcount);
 }
 
 template <typename FS>
 static void launch_update_s(const Geom& G, bool flat, int mode, const double* prim, double* x, double* y,
                             const FS* flux, const FS* edges, const double* tab, double a, double b,
                             double dt_host, const double* d_dt, double* out, int stage, hipStream_t s,
-                            int img) {
+                            int img, int parts, unsigned char* tflags, int* tcount) {
   if (G.dorder == 4)
-    launch_update_o<4, FS>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img);
+    launch_update_o<4, FS>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img,
+                           parts, tflags, tcount);
   else
-    launch_update_o<6, FS>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img);
+    launch_update_o<6, FS>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img,
+                           parts, tflags, tcount);
 }
 
 void launch_update(const Geom& G, bool flat, bool fp32, int mode, const double* prim, double* x, double* y,
                    const double* flux, const double* edges, const double* tab, double a, double b,
-                   double dt_host, const double* d_dt, double* out, int stage, hipStream_t s, int img) {
+                   double dt_host, const double* d_dt, double* out, int stage, hipStream_t s, int img,
+                   int parts, const UpdateFallback* fb) {
+  // split updates are stage updates (mode 0); the hydro part always flags
+  if (mode != 0) parts = UPD_ALL;
+  if (parts == UPD_HYDRO && !fb) return;
+  unsigned char* tflags = fb ? fb->flags : nullptr;
+  int* tcount = fb ? fb->count : nullptr;
   if (fp32)
     launch_update_s<float>(G, flat, mode, prim, x, y, reinterpret_cast<const float*>(flux),
-                           reinterpret_cast<const float*>(edges), tab, a, b, dt_host, d_dt, out, stage, s, img);
+                           reinterpret_cast<const float*>(edges), tab, a, b, dt_host, d_dt, out, stage, s, img,
+                           parts, tflags, tcount);
   else
     launch_update_s<double>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s,
-                            img);
+                            img, parts, tflags, tcount);
 }
 
 // d_dt[0]: dt of the last step, d_dt[1]: time; src: where the device dt was read

@@ -11,9 +11,11 @@ CONS = ("D", "S1", "S2", "S3", "tau", "Bf1", "Bf2", "Bf3")
 
 class Grid:
     def __init__(self, spec, tables=None, precision=L.FP64, guess=L.GUESS_WARM,
-                 device="cuda:0", stream=None, recon=L.RECON_MP5, deriv_order=6):
-        """recon: reconstruction code (L.RECON_MP5, _WENO5, _PLM) or its name;
-        deriv_order: 6 or 4 (staggered derivative and interpolation)."""
+                 device="cuda:0", stream=None, recon=L.RECON_MP5, deriv_order=6, fallback=False):
+        """recon: reconstruction code (L.RECON_MP5, _WENO5, _PLM, _MP7) or its
+        name; deriv_order: 6 or 4 (staggered derivative and interpolation);
+        fallback: first-order HLL fluxes at the faces of zones whose new state
+        is unphysical (diagnostics run_troubled counts those zones)."""
         if isinstance(recon, str):
             recon = L.RECON[recon]
         if not torch.cuda.is_available():
@@ -23,7 +25,7 @@ class Grid:
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.desc = L.make_desc(spec, precision, guess, recon, deriv_order)
+        self.desc = L.make_desc(spec, precision, guess, recon, deriv_order, fallback)
         h = C.c_void_p()
         self._call(self.lib.grmhd_init_grid, C.byref(self.desc), C.c_void_p(self.stream.cuda_stream),
                                          C.byref(h))

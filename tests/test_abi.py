@@ -41,6 +41,14 @@ def test_library_exports_every_declared_function():
     assert sorted(L.EXPORTS) == _declared()
 
 
+def test_binding_structs_match_the_library_layout():
+    # the library checks the same sizes with static_assert when it is built
+    from paper_1810_04597_amd import _lib as L
+    assert C.sizeof(L.GridDesc) == 184
+    assert C.sizeof(L.Diag) == 280
+    assert L.Diag.run_c2p_fail.offset == 216 and L.Diag.run_troubled.offset == 272
+
+
 def _desc(L, **kw):
     from workloads.grid import box
     d = L.make_desc(box(8))
@@ -60,7 +68,8 @@ def _desc(L, **kw):
     ("recon", -1, "bad recon"),
     ("recon", 3, "MP7 needs ng = 6"),
     ("deriv_order", 5, "deriv_order"),
-    ("reserved", 1, "reserved"),
+    ("fallback", 2, "fallback must be 0 or 1"),
+    ("fallback", -1, "fallback must be 0 or 1"),
 ])
 def test_descriptor_validation_before_any_device_call(field, value, msg):
     L, lib = _lib()
