@@ -410,6 +410,80 @@ def torus_report(args):
     print(json.dumps(out))
 
 
+def fallback_report(args):
+    """The lower-order fallback (grmhd_grid_desc.fallback).  (a) The
+    Kerr-Schild torus (args.torus) with MP5 and WENO5, with and without the
+    fallback: args.warmup steps, then args.steps timed steps at the device
+    CFL step; failed inversions and troubled zones over the timed steps, the
+    step time and the per-class kernel times (the fix kernel is its own
+    class; with the option on, 'update' counts two launches per stage, the
+    hydro and the induction parts).  (b) The turbulent box (args.n^3) with
+    and without it, where no zone is troubled: the cost of the split update
+    and of the fix kernel's early exit."""
+    import torch
+    from workloads.torus import torus
+    from workloads import box
+    from paper_1810_04597_amd.grid import Grid
+
+    def timed_run(G, steps):
+        for _ in range(args.warmup):
+            G.rk_step()
+        G.synchronize()
+        G.reset_run_counters()
+        G.set_profiling(True)
+        G.profile(reset=True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(G.stream)
+        for _ in range(steps):
+            G.rk_step()
+        e1.record(G.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        prof = G.profile(reset=True)
+        dg = G.diagnostics()
+        return {"ms_per_step": ms / steps,
+                "zone_updates_per_s": G.spec.zones * steps / (ms / 1e3),
+                "c2p_fail": dg["run_c2p_fail"], "troubled": dg["run_troubled"],
+                "floor_rho": dg["run_floor_rho"], "floor_p": dg["run_floor_p"], "t": dg["t"],
+                "kernels_avg_ms": {k: t / c for k, (t, c) in prof.items()},
+                "kernels_launches": {k: c for k, (t, c) in prof.items()}}
+
+    n1, n2, n3 = (int(x) for x in args.torus.split(","))
+    g, d, tab = torus(n1, n2, n3)
+    tor = {}
+    for recon in ("mp5", "weno5"):
+        for fb in (False, True):
+            G = Grid(g, tables=tab, recon=recon, fallback=fb)
+            G.curl_potential(d)
+            G.set_primitives(d)
+            tor["%s_%s" % (recon, "fallback" if fb else "plain")] = timed_run(G, args.steps)
+            G.close()
+            del G
+            print("bench: torus %s fallback=%s done" % (recon, fb), file=sys.stderr, flush=True)
+    gb, db = box.turbulent_box(args.n)
+    bx = {}
+    for fb in (False, True):
+        G = Grid(gb, fallback=fb)
+        G.curl_potential(db)
+        G.set_primitives(db)
+        bx["fallback" if fb else "plain"] = timed_run(G, args.steps)
+        G.close()
+        del G
+        print("bench: box fallback=%s done" % fb, file=sys.stderr, flush=True)
+    w = tor["weno5_fallback"]
+    out = {"metric": "zone-updates/s per RK3 step with the lower-order fallback, KS torus %dx%dx%d, WENO5"
+                     % (n1, n2, n3),
+           "value": w["zone_updates_per_s"], "unit": "zone-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": w["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "Kerr-Schild a=0.9 torus %dx%dx%d (floors, device CFL), MP5 and WENO5, "
+                                  "fallback off/on; turbulent box %d^3" % (n1, n2, n3, args.n)},
+           "torus": tor, "box": bx}
+    print(json.dumps(out))
+
+
 def torus_long_report(args):
     """Long Kerr-Schild torus run (device CFL step): every --every steps the
     diagnostics, the fluxes through the first sphere outside the horizon
@@ -616,13 +690,15 @@ def main():
     ap.add_argument("--eager", action="store_true",
                     help="time steps launched one by one instead of graph replays")
     ap.add_argument("--mode", default="step",
-                    choices=["step", "precision", "learned", "torus", "torus-long", "recon", "split"],
+                    choices=["step", "precision", "learned", "torus", "torus-long", "recon", "split",
+                             "fallback"],
                     help="step: the FP64 RK3 step (default); precision: FP32-flux form "
                          "against FP64 on the same grid, fixed dt, per-field error; learned: "
                          "train the Newton-guess network on the GPU, then the Kerr-Schild "
                          "torus in plain FP64 vs FP32 flux + learned guess; recon: the step "
                          "with MP5, WENO5 and PLM-MC reconstruction; split: the split "
-                         "(load-balanced) Newton inversion against one pass")
+                         "(load-balanced) Newton inversion against one pass; fallback: the "
+                         "lower-order fallback on the torus and the box, off and on")
     ap.add_argument("--train-samples", type=int, default=1 << 22)
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--torus", default="384,192,192")
@@ -647,6 +723,8 @@ def main():
         return recon_report(args)
     if args.mode == "split":
         return split_report(args)
+    if args.mode == "fallback":
+        return fallback_report(args)
 
     import torch
     from workloads import box

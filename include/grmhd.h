@@ -360,7 +360,7 @@ int grmhd_mlp_forward(grmhd_grid* h, const float* feat, int64_t n, float* out);
  * grmhd_get_profile synchronises the stream, accumulates the elapsed times
  * per kernel class and returns totals (ms) and launch counts since the last
  * reset.  Class names: grmhd_profile_class_name(0 .. GRMHD_PROF_NCLASS-1). */
-#define GRMHD_PROF_NCLASS 16
+#define GRMHD_PROF_NCLASS 17
 typedef struct {
   double ms[GRMHD_PROF_NCLASS];
   int64_t launches[GRMHD_PROF_NCLASS];

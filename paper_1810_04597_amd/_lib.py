@@ -27,7 +27,7 @@ EXPORTS = ("grmhd_init_grid", "grmhd_get_layout", "grmhd_bind_fields", "grmhd_se
            "grmhd_set_learned_guess")
 MLP_NPARAM = 10448
 MLP_NNORM = 32
-PROF_NCLASS = 16
+PROF_NCLASS = 17
 
 
 class GridDesc(C.Structure):
@@ -70,7 +70,7 @@ class Diag(C.Structure):
 
 
 class Profile(C.Structure):
-    _fields_ = [("ms", C.c_double * 16), ("launches", C.c_int64 * 16)]
+    _fields_ = [("ms", C.c_double * PROF_NCLASS), ("launches", C.c_int64 * PROF_NCLASS)]
 
 
 class GrmhdError(RuntimeError):

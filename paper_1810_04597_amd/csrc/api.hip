@@ -22,6 +22,7 @@ static_assert(sizeof(grmhd_grid_desc) == 184 && offsetof(grmhd_grid_desc, recon)
 static_assert(sizeof(grmhd_diag) == 280 && offsetof(grmhd_diag, run_c2p_fail) == 216 &&
                   offsetof(grmhd_diag, run_troubled) == 272,
               "grmhd_diag layout, which the Python binding mirrors");
+static_assert(sizeof(grmhd_profile) == GRMHD_PROF_NCLASS * 16, "grmhd_profile layout");
 static_assert(GRMHD_RECON_MP5 == grmhd::RECON_MP5 && GRMHD_RECON_WENO5 == grmhd::RECON_WENO5 &&
                   GRMHD_RECON_PLM == grmhd::RECON_PLM && GRMHD_RECON_MP7 == grmhd::RECON_MP7,
               "reconstruction codes of the ABI and the kernels agree");
@@ -93,7 +94,7 @@ constexpr int MLP_MAX_WAVES = 256;
 const char* const PROF_NAMES[GRMHD_PROF_NCLASS] = {
     "bc_centred", "sweep_x1", "sweep_x2", "sweep_x3", "edge_x1", "edge_x2", "edge_x3",
     "update", "bc_faces", "cons2prim", "cfl", "newton_split", "advance", "rhs_out",
-    "learned_guess", "learned_train"};
+    "learned_guess", "learned_train", "fallback"};
 }  // namespace
 
 struct grmhd_grid {
@@ -528,13 +529,19 @@ static void step_stages(grmhd_grid* h, double dt) {
         launch_update(h->G, h->flat, fp32, 0, h->prim, s == 0 ? Un : S, s == 0 ? S : Un, h->flux(),
                       h->edges(), h->tab, A[s], B[s], dt, dt_src, nullptr, s + 1, h->stream, img ? 1 : 0,
                       UPD_HYDRO, &fb);
+      }
+    });
+    if (h->desc.fallback) {
+      h->timed(16, [&] {
         launch_fallback(h->G, h->flat, fp32, h->bc, h->prim, cur, next, h->flux(), h->tab, h->d_trouble,
                         h->d_ntrouble, B[s], dt, dt_src, h->d_run, h->stream);
+      });
+      h->timed(7, [&] {
         launch_update(h->G, h->flat, fp32, 0, h->prim, s == 0 ? Un : S, s == 0 ? S : Un, h->flux(),
                       h->edges(), h->tab, A[s], B[s], dt, dt_src, nullptr, s + 1, h->stream, img ? 1 : 0,
                       UPD_INDUCTION);
-      }
-    });
+      });
+    }
     // dt and time are recorded once the last update has consumed d_dt[2]
     if (s == 2) h->timed(12, [&] { launch_advance(h->d_dt, dt_src, dt, h->stream); });
     if (!img) h->timed(8, [&] { launch_bc_faces(h->G, h->bc, next, h->stream); });

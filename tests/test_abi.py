@@ -47,6 +47,7 @@ def test_binding_structs_match_the_library_layout():
     assert C.sizeof(L.GridDesc) == 184
     assert C.sizeof(L.Diag) == 280
     assert L.Diag.run_c2p_fail.offset == 216 and L.Diag.run_troubled.offset == 272
+    assert C.sizeof(L.Profile) == 16 * L.PROF_NCLASS
 
 
 def _desc(L, **kw):
@@ -105,5 +106,5 @@ def test_null_handles_are_rejected():
 def test_profile_class_names():
     L, lib = _lib()
     names = [lib.grmhd_profile_class_name(c).decode() for c in range(L.PROF_NCLASS)]
-    for n in ("sweep_x1", "edge_x3", "update", "cons2prim", "learned_guess"):
+    for n in ("sweep_x1", "edge_x3", "update", "cons2prim", "learned_guess", "fallback"):
         assert n in names
