@@ -68,7 +68,8 @@ enum { GRMHD_GUESS_WARM = 0, GRMHD_GUESS_COLD = 1, GRMHD_GUESS_MLP = 2 };
  * indicators, point-value form, eps = 1e-6), PLM with the monotonized-central
  * limiter (second order, the lower-order member); MP7 (the same limiter on
  * the degree-6 interpolant of the seven cells f-3 .. f+3, seventh order;
- * eight-cell stencils f-3 .. f+4, so it needs ng = 6). */
+ * eight-cell stencils f-3 .. f+4, so it needs ng = 6, or 5 with
+ * deriv_order 4). */
 enum { GRMHD_RECON_MP5 = 0, GRMHD_RECON_WENO5 = 1, GRMHD_RECON_PLM = 2, GRMHD_RECON_MP7 = 3 };
 enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_TABLE_AXISYM = 1 };
 
@@ -83,8 +84,11 @@ enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_TABLE_AXISYM = 1 };
 
 typedef struct {
   int32_t n[3];            /* interior zones n1, n2, n3 (each >= 1)              */
-  int32_t ng;              /* ghost layers: 5 (MP5/WENO5/PLM + 6th-order D), or 6
-                              (required by MP7; allowed for the others)        */
+  int32_t ng;              /* ghost layers: 5 (MP5/WENO5/PLM + 6th-order D), 6
+                              (required by MP7 with the 6th-order D; allowed for
+                              the others) or 4 (MP5/WENO5/PLM + 4th-order D:
+                              faces and edges are formed at -2 .. n instead of
+                              -3 .. n+1)                                      */
   int32_t coord;           /* GRMHD_CART | GRMHD_LOGSPH (floors use r = e^{x^1}) */
   int32_t bc[6];           /* -x1,+x1,-x2,+x2,-x3,+x3; periodic in pairs; axis
                               only on x^2 (n2 >= ng+1) with periodic x^3, n3 even */

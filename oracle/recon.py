@@ -46,9 +46,10 @@ from . import mp5 as _mp5
 WENO_EPS = 1e-6
 WENO_D = (1.0 / 16.0, 10.0 / 16.0, 5.0 / 16.0)
 METHODS = ("mp5", "weno5", "plm", "mp7")
-# ghost layers each method needs: its stencil's reach past the face (3 for
-# the five- and six-cell stencils, 4 for MP7's eight) plus the two further
-# faces of the sixth-order flux derivative
+# ghost layers each method needs with the sixth-order derivative: its
+# stencil's reach past the face (3 for the five- and six-cell stencils, 4 for
+# MP7's eight) plus the two further faces of that derivative (one fewer with
+# the fourth-order derivative, whose stencil reaches one face less)
 NG_OF = {"mp5": 5, "weno5": 5, "plm": 5, "mp7": 6}
 
 

@@ -4,8 +4,9 @@ Paper, Introduction: 3-D finite differences with high-order reconstruction,
 after ECHO.  One right-hand-side evaluation, in order:
   1. ghost fill of the 8 centred primitives;
   2. for each direction d: MP5 states of rho, p, u^1..3 and the two
-     transverse centred B at d-faces f in [-3, n_d + 1] over the whole
-     transverse ghosted range (reconstructed rho and p are kept at or above
+     transverse centred B at d-faces f in [-3, n_d + 1] (the faces the
+     sixth-order derivative of the edges and fluxes reads; [-2, n_d] for the
+     fourth-order one) over the whole transverse ghosted range (reconstructed rho and p are kept at or above
      0.1 times the cell value on their side); normal B = B_face / sqrt(gamma_face);
      pointwise fluxes, conserved variables and speeds of both states; HLL
      flux (0 on faces where sqrt(gamma) = 0); the per-face data for the
@@ -135,8 +136,15 @@ class Solver:
             raise ValueError("unknown reconstruction %r" % (recon,))
         if deriv_order not in (4, 6):
             raise ValueError("deriv_order must be 4 or 6")
-        if grid.ng < NG_OF[recon]:
-            raise ValueError("%s needs %d ghost layers" % (recon, NG_OF[recon]))
+        # faces and edges are formed from -flo to n + flo - 2 along their
+        # offset directions (the stored indices the staggered derivative reads
+        # at the interior: 3 and 2 below and above for the sixth order, 2 and
+        # 1 for the fourth); a face reads cells down to flo plus the
+        # reconstruction's reach below it (NG_OF is that for the sixth order)
+        self.flo = 3 if deriv_order == 6 else 2
+        need = NG_OF[recon] - 3 + self.flo
+        if grid.ng < need:
+            raise ValueError("%s with deriv_order %d needs %d ghost layers" % (recon, deriv_order, need))
         self.recon = recon
         self.order = deriv_order
         self.fallback = fallback
@@ -221,7 +229,7 @@ class Solver:
     def sweep(self, d):
         g, gr, gam = self.g, self.grid, self.gam
         n = gr.n[d]
-        lo, hi = -3, n + 2
+        lo, hi = -self.flo, n + self.flo - 1
         c = (d + 1) % 3
         ft = self.ftype
         P = {k: v.astype(ft) for k, v in self.P.items()}
@@ -280,30 +288,31 @@ class Solver:
         D = {k: v.astype(ft) for k, v in fdat[d].items()}
         C = {k: v.astype(ft) for k, v in fdat[c].items()}
         UB = {k: self.U[k].astype(ft) for k in FACE}
+        lo, hd, hc = -self.flo, nd + self.flo - 1, nc + self.flo - 1
         # reconstruct d-face data along c to the edge (side b)
         def along_c(q):
-            l, r = face_states(q, c, -3, nc + 2, g, take, self.recon)
-            return take(l, d, -3, nd + 2, g), take(r, d, -3, nd + 2, g)
+            l, r = face_states(q, c, lo, hc, g, take, self.recon)
+            return take(l, d, lo, hd, g), take(r, d, lo, hd, g)
         vd = {("L", b): x for b, x in zip("LR", along_c(D["vdL"]))}
         vd.update({("R", b): x for b, x in zip("LR", along_c(D["vdR"]))})
         vc = {("L", b): x for b, x in zip("LR", along_c(D["vcL"]))}
         vc.update({("R", b): x for b, x in zip("LR", along_c(D["vcR"]))})
         bd = dict(zip("LR", along_c(UB["Bf%d" % (d + 1)])))
         # reconstruct B^c (c-faces) along d (side a)
-        l, r = face_states(UB["Bf%d" % (c + 1)], d, -3, nd + 2, g, take, self.recon)
-        bc = {"L": take(l, c, -3, nc + 2, g), "R": take(r, c, -3, nc + 2, g)}
+        l, r = face_states(UB["Bf%d" % (c + 1)], d, lo, hd, g, take, self.recon)
+        bc = {"L": take(l, c, lo, hc, g), "R": take(r, c, lo, hc, g)}
         # speeds: max over the two faces adjacent to the edge
-        def adj(q, along, other, n_along, n_other):
-            x0 = take(q, along, -3, n_along + 2, g)
-            x1 = take(q, along, -2, n_along + 3, g)
+        def adj(q, along, other, h_along, h_other):
+            x0 = take(q, along, lo, h_along, g)
+            x1 = take(q, along, lo + 1, h_along + 1, g)
             m = np.maximum(x0, x1)
-            return take(m, other, -3, n_other + 2, g)
-        apd = adj(D["ap"], c, d, nc, nd)
-        amd = adj(D["am"], c, d, nc, nd)
-        apc = adj(C["ap"], d, c, nd, nc)
-        amc = adj(C["am"], d, c, nd, nc)
-        me = Metric.sel(Metric.sel(self.met.loc[EDGE_LOC[e]], d, -3, nd + 2, g),
-                        c, -3, nc + 2, g)
+            return take(m, other, lo, h_other, g)
+        apd = adj(D["ap"], c, d, hc, hd)
+        amd = adj(D["am"], c, d, hc, hd)
+        apc = adj(C["ap"], d, c, hd, hc)
+        amc = adj(C["am"], d, c, hd, hc)
+        me = Metric.sel(Metric.sel(self.met.loc[EDGE_LOC[e]], d, lo, hd, g),
+                        c, lo, hc, g)
         me = {k: v.astype(ft) for k, v in me.items()}
         al = me["alpha"]
         betd, betc = me["beta%d" % (d + 1)], me["beta%d" % (c + 1)]
@@ -327,8 +336,8 @@ class Solver:
         ee = ee + kd * (bc["R"] - bc["L"]) - kc * (bd["R"] - bd["L"])
         out = _nan(gr.shape)
         sl = [slice(None)] * 3
-        sl[fd.AXIS[d]] = slice(-3 + g, nd + 2 + g)
-        sl[fd.AXIS[c]] = slice(-3 + g, nc + 2 + g)
+        sl[fd.AXIS[d]] = slice(lo + g, hd + g)
+        sl[fd.AXIS[c]] = slice(lo + g, hc + g)
         out[tuple(sl)] = np.asarray(ee, dtype=np.float64)
         return out
 

@@ -185,8 +185,7 @@ int validate(const grmhd_grid_desc* d) {
     if (!(d->dx[a] > 0.0) || !std::isfinite(d->dx[a])) return fail(GRMHD_EINVAL, "dx must be > 0");
     if (!std::isfinite(d->x0[a])) return fail(GRMHD_EINVAL, "x0 not finite");
   }
-  if (d->ng != 5 && d->ng != 6)
-    return fail(GRMHD_EINVAL, "ng must be 5 (five- and six-cell stencils + sixth-order derivative) or 6");
+  if (d->ng < 4 || d->ng > 6) return fail(GRMHD_EINVAL, "ng must be 4, 5 or 6");
   if (d->coord != GRMHD_CART && d->coord != GRMHD_LOGSPH) return fail(GRMHD_EINVAL, "bad coord");
   for (int s = 0; s < 6; ++s)
     if (d->bc[s] < 0 || d->bc[s] > 2) return fail(GRMHD_EINVAL, "bad boundary code");
@@ -214,7 +213,14 @@ int validate(const grmhd_grid_desc* d) {
   if (d->recon != GRMHD_RECON_MP5 && d->recon != GRMHD_RECON_WENO5 && d->recon != GRMHD_RECON_PLM &&
       d->recon != GRMHD_RECON_MP7)
     return fail(GRMHD_EINVAL, "bad recon");
-  if (d->recon == GRMHD_RECON_MP7 && d->ng != 6) return fail(GRMHD_EINVAL, "MP7 needs ng = 6");
+  {
+    // faces from -3 (sixth-order derivative) or -2 (fourth) read cells down
+    // to the reconstruction's reach below them: 2 more, 3 for MP7
+    const int need = (d->deriv_order == 4 ? 2 : 3) + (d->recon == GRMHD_RECON_MP7 ? 3 : 2);
+    if (d->ng < need)
+      return fail(GRMHD_EINVAL, d->recon == GRMHD_RECON_MP7 ? "MP7 needs ng = 6 (5 with deriv_order 4)"
+                                                          : "ng = 4 needs deriv_order 4");
+  }
   if (d->deriv_order != 0 && d->deriv_order != 4 && d->deriv_order != 6)
     return fail(GRMHD_EINVAL, "deriv_order must be 0, 4 or 6");
   if (d->fallback != 0 && d->fallback != 1) return fail(GRMHD_EINVAL, "fallback must be 0 or 1");

@@ -64,6 +64,12 @@ struct Geom {
   __host__ __device__ long tidx(int i, int j) const {
     return (long)(j + ng) * tab_n1 + (i + ng);
   }
+  // Faces and edges are formed at stored indices face_lo() .. n + face_lo()
+  // + face_count - 1 along their offset directions: the ones the staggered
+  // derivative reads at the interior, -3 .. n+1 for the sixth order and
+  // -2 .. n for the fourth (whose grids may then have four ghost layers).
+  __host__ __device__ int face_lo() const { return dorder == 4 ? -2 : -3; }
+  __host__ __device__ int face_count(int d) const { return n[d] - 2 * face_lo() - 1; }
 };
 
 // ------------------------------------------------------------------ XCD-aware block order

@@ -30,7 +30,8 @@ namespace grmhd {
 // (F1 - G) of the five hydro fields at the DIR-face stored at (fi, fj, fk)
 // (the face +1/2 of that cell): F1 from the primitives of cells (fi, fj, fk)
 // and its DIR neighbour and the face field of the stage's start state cur;
-// G from the stored face fluxes of faces -2 .. +2 around it.
+// G from the stored face fluxes of faces -2 .. +2 around it (-1 .. +1 for the
+// fourth-order form).
 template <int DIR, class MET, typename FS, int DO>
 __device__ __noinline__ void face_delta(const Geom G, const double* __restrict__ prim,
                                         const double* __restrict__ cur, const FS* __restrict__ flux,
@@ -58,9 +59,12 @@ __device__ __noinline__ void face_delta(const Geom G, const double* __restrict__
 #pragma unroll
   for (int q = 0; q < 5; ++q) {
     const FS* fp = flux + ((long)DIR * 5 + q) * G.field + c;
-    const double fm2 = fp[-2 * st], fm1 = fp[-st], f0 = fp[0], fp1 = fp[st], fp2 = fp[2 * st];
+    const double fm1 = fp[-st], f0 = fp[0], fp1 = fp[st];
     double g = f0 - (fp1 - 2.0 * f0 + fm1) / 24.0;
-    if constexpr (DO == 6) g = g + 3.0 * (fp2 - 4.0 * fp1 + 6.0 * f0 - 4.0 * fm1 + fm2) / 640.0;
+    if constexpr (DO == 6) {
+      const double fm2 = fp[-2 * st], fp2 = fp[2 * st];
+      g = g + 3.0 * (fp2 - 4.0 * fp1 + 6.0 * f0 - 4.0 * fm1 + fm2) / 640.0;
+    }
     out[q] = fh[q] - g;
   }
 }

@@ -1,7 +1,8 @@
 // Face sweeps and constrained-transport edge fields (gfx950).
 //
-// k_sweep<DIR>: one thread per DIR-face, faces f in [-3, n_DIR + 1] over the
-// whole ghosted transverse range, flattened with x^1 fastest so a wavefront
+// k_sweep<DIR>: one thread per DIR-face, faces f in [-3, n_DIR + 1] ([-2, n_DIR]
+// with the fourth-order derivative; Geom::face_lo) over the whole ghosted
+// transverse range, flattened with x^1 fastest so a wavefront
 // reads 64 consecutive x^1 cells (coalesced).  Per face: MP5 left/right
 // states of rho, p, u^1..3 and the two transverse centred B (paper,
 // Introduction: high-order reconstruction; rho and p bounded below by 0.1 of
@@ -12,7 +13,7 @@
 // (v^d and v^c of both states, a+ and a-), c = d+1 mod 3.
 //
 // k_edge<E>: one thread per edge of family E (offsets 1/2 in d = E+1 and
-// c = E+2 mod 3), over d, c in [-3, n + 1] and interior x^E: upwind
+// c = E+2 mod 3), over d, c in the face range and interior x^E: upwind
 // constrained transport (Londrillo & Del Zanna 2004) from MP5 along c of the
 // d-face velocities and B^d, MP5 along d of B^c, and the speeds of the two
 // adjacent faces of each family.
@@ -89,11 +90,11 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
                                                T* __restrict__ ctd) {
   int ext[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) ext[a] = (a == DIR) ? G.n[a] + 5 : G.dims[a];
+  for (int a = 0; a < 3; ++a) ext[a] = (a == DIR) ? G.face_count(a) : G.dims[a];
   // tiles: x^1 fastest; for the x^3 sweep x^3 comes next, so the six planes
   // of a stencil are read by neighbouring workgroups (L2 reuse)
   constexpr int MID = DIR == 2 ? 2 : 1, SLOW = DIR == 2 ? 1 : 2;
-  const TilePos tp = MET::flat ? tile_pos(ext[0], ext[MID], line_shift(G.ng, DIR == 0 ? -3 : -G.ng))
+  const TilePos tp = MET::flat ? tile_pos(ext[0], ext[MID], line_shift(G.ng, DIR == 0 ? G.face_lo() : -G.ng))
                                : flat_pos(ext[0], ext[MID], ext[SLOW]);
   if (!tp.ok) return;
   int ii[3];
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
   ii[MID] = tp.m;
   ii[SLOW] = tp.s;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) ii[a] += (a == DIR) ? -3 : -G.ng;
+  for (int a = 0; a < 3; ++a) ii[a] += (a == DIR) ? G.face_lo() : -G.ng;
   const long c = G.idx(ii[0], ii[1], ii[2]);
   const long st = G.stride(DIR);
   const T gam = T(G.gam);
@@ -149,7 +150,7 @@ __global__ __launch_bounds__(256) void k_sweep(Geom G, const double* __restrict_
 // LDS-staged sweep for DIR = 1, 2 (stencils across rows or planes, which a
 // wavefront would otherwise fetch as six separate row loads per variable).
 // A workgroup owns SX consecutive transverse positions (flattened, x^1
-// fastest) times SF consecutive faces along DIR; it stages the SF + 5 cells
+// fastest) times SF consecutive faces along DIR; it stages the SF + W - 1 cells
 // of each reconstructed variable its faces need in LDS, so each cell row is
 // read once per workgroup, then each wavefront runs the per-face body on one
 // face row.  Workgroups of one column follow each other along DIR.
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   // pitch's padding positions past the ghosted x^1 range stay idle
   const int nA = G.dims[0], rA = (int)G.pitch;
   const long M = (long)rA * G.dims[TB];
-  const int nface = G.n[DIR] + 5;               // faces -3 .. n + 1
+  const int nface = G.face_count(DIR);          // faces face_lo .. face_lo + nface - 1
   const int ntf = (nface + SF - 1) / SF;
   const long bid = xcd_block(blockIdx.x, gridDim.x);
   const int ft = (int)(bid % ntf);
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   ii[DIR] = 0;
   const long base = G.idx(ii[0], ii[1], ii[2]);
   const long st = G.stride(DIR);
-  const int f0 = -3 + ft * SF;
+  const int f0 = G.face_lo() + ft * SF;
   // stage cells f0 - LO .. f0 + SF - LO + W - 2; wavefront ty loads rows ty + SF rr
   // (a wave-uniform condition).  Rows past the last ghost cell are clamped to
   // it: no face of the tile that exists reads them.  All loads are issued
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   ii[0] = __shfl(ii[0], cx);
   ii[TB] = __shfl(ii[TB], cx);
   const int okc = __shfl(ok, cx);
-  if (!okc || f > G.n[DIR] + 1) return;
+  if (!okc || f >= G.face_lo() + nface) return;
   ii[DIR] = f;
   const long c = G.idx(ii[0], ii[1], ii[2]);
   const T gam = T(G.gam);
@@ -264,17 +265,17 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
   constexpr int W = Stencil<RC>::W, LO = Stencil<RC>::LO;
   int ext[3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) ext[a] = (a == E) ? G.n[a] : G.n[a] + 5;
+  for (int a = 0; a < 3; ++a) ext[a] = (a == E) ? G.n[a] : G.face_count(a);
   // families 1 and 2 reconstruct along x^3: tiles traverse x^3 before x^2
   constexpr int MID = E == 2 ? 1 : 2, SLOW = E == 2 ? 2 : 1;
-  const TilePos tp = tile_pos(ext[0], ext[MID], EDGE_ALIGN[E] ? line_shift(G.ng, E == 0 ? 0 : -3) : 0);
+  const TilePos tp = tile_pos(ext[0], ext[MID], EDGE_ALIGN[E] ? line_shift(G.ng, E == 0 ? 0 : G.face_lo()) : 0);
   if (!tp.ok) return;
   int ii[3];
   ii[0] = tp.a;
   ii[MID] = tp.m;
   ii[SLOW] = tp.s;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) ii[a] += (a == E) ? 0 : -3;
+  for (int a = 0; a < 3; ++a) ii[a] += (a == E) ? 0 : G.face_lo();
   const long b = G.idx(ii[0], ii[1], ii[2]);
   const long sd = G.stride(D), sc = G.stride(C);
 
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
 // LDS-staged edge field for families E = 0, 2, whose five d-face inputs are
 // reconstructed across rows (along x^3 for E = 0, x^2 for E = 2).  Tiles of
 // SX consecutive positions (flattened, x^1 fastest) times SF edges along c;
-// the SF + 5 rows of the five inputs are staged once per workgroup.  The
+// the SF + W - 1 rows of the five inputs are staged once per workgroup.  The
 // c-face B (along d) and the four speeds are read directly.
 template <int E, int SF, class MET, typename T, int RC>
 __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __restrict__ cons,
@@ -320,14 +321,14 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   constexpr int W = Stencil<RC>::W, LO = Stencil<RC>::LO;
   constexpr int SR = SF + W - 1, NRR = (SR + SF - 1) / SF;
   __shared__ T sh[5][SR][SX + LPAD];
-  const int extA = (E == 0) ? G.n[0] : G.n[0] + 5, offA = (E == 0) ? 0 : -3;
-  const int extB = (B == E) ? G.n[B] : G.n[B] + 5, offB = (B == E) ? 0 : -3;
+  const int extA = (E == 0) ? G.n[0] : G.face_count(0), offA = (E == 0) ? 0 : G.face_lo();
+  const int extB = (B == E) ? G.n[B] : G.face_count(B), offB = (B == E) ? 0 : G.face_lo();
   // positions flattened with x^1 fastest over rows of rA slots, the x^1 range
   // starting at slot shA so that 16-lane segments are whole 128-byte lines
   const int shA = EDGE_ALIGN[E] ? line_shift(G.ng, offA) : 0;
   const int rA = EDGE_ALIGN[E] ? (extA + shA + 15) / 16 * 16 : extA;
   const long M = (long)rA * extB;
-  const int nc = G.n[C] + 5;                    // edges -3 .. n + 1 along c
+  const int nc = G.face_count(C);               // edges face_lo .. face_lo + nc - 1 along c
   const int ntc = (nc + SF - 1) / SF;
   const long bid = xcd_block(blockIdx.x, gridDim.x);
   const int ct = (int)(bid % ntc);
@@ -344,7 +345,7 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   ii[C] = 0;
   const long base = G.idx(ii[0], ii[1], ii[2]);
   const long sd = G.stride(D), sc = G.stride(C);
-  const int c0 = -3 + ct * SF;
+  const int c0 = G.face_lo() + ct * SF;
   {
     const double* bds = cons + (long)(C_BF1 + D) * G.field;
     const int cmax = G.n[C] + G.ng - 1;
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
   ii[0] = __shfl(ii[0], cx);
   ii[B] = __shfl(ii[B], cx);
   const int okc = __shfl(ok, cx);
-  if (!okc || cc > G.n[C] + 1) return;
+  if (!okc || cc >= G.face_lo() + nc) return;
   ii[C] = cc;
   const long b = G.idx(ii[0], ii[1], ii[2]);
   T qc[W];
@@ -410,8 +411,8 @@ static void launch_sweep_t(int d, const Geom& G, const double* prim, const doubl
   T* fl = reinterpret_cast<T*>(flux) + (long)d * 5 * G.field;
   T* cd = reinterpret_cast<T*>(ctd) + (long)d * 6 * G.field;
   if (d == 0) {
-    const long nf = (long)(G.n[0] + 5) * G.dims[1] * G.dims[2];
-    const unsigned nb = MET::flat ? tile_blocks(G.n[0] + 5, G.dims[1], G.dims[2], line_shift(G.ng, -3))
+    const long nf = (long)G.face_count(0) * G.dims[1] * G.dims[2];
+    const unsigned nb = MET::flat ? tile_blocks(G.face_count(0), G.dims[1], G.dims[2], line_shift(G.ng, G.face_lo()))
                                   : (unsigned)((nf + 255) / 256);
     hipLaunchKernelGGL((k_sweep<0, MET, T, RC>), dim3(nb), dim3(256), 0, s, G, prim, cons, tab, fl, cd);
     return;
@@ -419,7 +420,7 @@ static void launch_sweep_t(int d, const Geom& G, const double* prim, const doubl
   // tiles: SX transverse positions (rows of the pitch) x SF faces
   constexpr int SF = SWEEP_SF;
   const long M = (long)G.pitch * G.dims[d == 1 ? 2 : 1];
-  const long tiles = ((M + SX - 1) / SX) * ((G.n[d] + 5 + SF - 1) / SF);
+  const long tiles = ((M + SX - 1) / SX) * ((G.face_count(d) + SF - 1) / SF);
   if (d == 1) hipLaunchKernelGGL((k_sweep_lds<1, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, prim, cons, tab, fl, cd);
   if (d == 2) hipLaunchKernelGGL((k_sweep_lds<2, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, prim, cons, tab, fl, cd);
 }
@@ -433,7 +434,8 @@ static void launch_edge_t(int e, const Geom& G, const double* cons, const double
   T* ed = reinterpret_cast<T*>(edges) + (long)e * G.field;
   if (e == 1) {
     hipLaunchKernelGGL((k_edge<1, MET, T, RC>),
-                       dim3(tile_blocks(G.n[0] + 5, G.n[2] + 5, G.n[1], EDGE_ALIGN[1] ? line_shift(G.ng, -3) : 0)),
+                       dim3(tile_blocks(G.face_count(0), G.face_count(2), G.n[1],
+                                        EDGE_ALIGN[1] ? line_shift(G.ng, G.face_lo()) : 0)),
                        dim3(256), 0, s, G, cons, tab, cd, cc, ed);
     return;
   }
@@ -441,11 +443,11 @@ static void launch_edge_t(int e, const Geom& G, const double* cons, const double
   // remaining axis) x SF edges along c
   constexpr int SF = EDGE_SF;
   const int B = 3 - c;
-  const int extA = (e == 0) ? G.n[0] : G.n[0] + 5;
-  const int shA = EDGE_ALIGN[e] ? line_shift(G.ng, (e == 0) ? 0 : -3) : 0;
+  const int extA = (e == 0) ? G.n[0] : G.face_count(0);
+  const int shA = EDGE_ALIGN[e] ? line_shift(G.ng, (e == 0) ? 0 : G.face_lo()) : 0;
   const long rA = EDGE_ALIGN[e] ? (extA + shA + 15) / 16 * 16 : extA;
-  const long M = rA * ((B == e) ? G.n[B] : G.n[B] + 5);
-  const long tiles = ((M + SX - 1) / SX) * ((G.n[c] + 5 + SF - 1) / SF);
+  const long M = rA * ((B == e) ? G.n[B] : G.face_count(B));
+  const long tiles = ((M + SX - 1) / SX) * ((G.face_count(c) + SF - 1) / SF);
   if (e == 0) hipLaunchKernelGGL((k_edge_lds<0, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, cons, tab, cd, cc, ed);
   if (e == 2) hipLaunchKernelGGL((k_edge_lds<2, SF, MET, T, RC>), dim3(tiles), dim3(SX * SF), 0, s, G, cons, tab, cd, cc, ed);
 }

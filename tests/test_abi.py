@@ -59,15 +59,16 @@ def _desc(L, **kw):
 
 
 @pytest.mark.parametrize("field,value,msg", [
-    ("ng", 4, "ng must be 5"),
-    ("ng", 7, "ng must be 5"),
+    ("ng", 3, "ng must be 4, 5 or 6"),
+    ("ng", 7, "ng must be 4, 5 or 6"),
+    ("ng", 4, "ng = 4 needs deriv_order 4"),
     ("precision", 7, "bad precision"),
     ("c2p_guess", 3, "bad c2p_guess"),
     ("newton_maxit", 0, "bad newton_maxit"),
     ("gamma_ad", 1.0, "gamma_ad"),
     ("recon", 4, "bad recon"),
     ("recon", -1, "bad recon"),
-    ("recon", 3, "MP7 needs ng = 6"),
+    ("recon", 3, "MP7 needs ng = 6 (5 with deriv_order 4)"),
     ("deriv_order", 5, "deriv_order"),
     ("fallback", 2, "fallback must be 0 or 1"),
     ("fallback", -1, "fallback must be 0 or 1"),
@@ -108,3 +109,17 @@ def test_profile_class_names():
     names = [lib.grmhd_profile_class_name(c).decode() for c in range(L.PROF_NCLASS)]
     for n in ("sweep_x1", "edge_x3", "update", "cons2prim", "learned_guess", "fallback"):
         assert n in names
+
+
+@pytest.mark.parametrize("ng,order,recon", [(4, 4, 0), (4, 4, 1), (4, 4, 2), (5, 4, 3)])
+def test_narrow_grids_pass_validation_with_the_fourth_order(ng, order, recon):
+    """Four ghost layers with the fourth-order derivative (five for MP7) get
+    past the descriptor checks (without a device the call then fails at its
+    first HIP call, with another code)."""
+    L, lib = _lib()
+    h = C.c_void_p()
+    rc = lib.grmhd_init_grid(C.byref(_desc(L, ng=ng, deriv_order=order, recon=recon)), None, C.byref(h))
+    if rc == L.OK:
+        lib.grmhd_destroy(h)
+    else:
+        assert rc != L.EINVAL, lib.grmhd_last_error().decode()

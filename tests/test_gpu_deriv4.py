@@ -2,7 +2,10 @@
 (grid option deriv_order = 4) against the oracle's fourth-order form: one RHS
 on small and ragged boxes, ten SSP-RK3 steps of the 32^3 box with the device
 CFL step, one step of the Kerr-Schild torus (table metric, sources), and the
-discrete div B of the fourth-order curl."""
+discrete div B of the fourth-order curl.  With the fourth-order derivative
+the faces and edges are formed at -2 .. n, so four ghost layers suffice: on
+such grids the same parity, and the interior equal bit for bit to the
+five-layer grid's (box, ghost images and separate fills; torus)."""
 import numpy as np
 import pytest
 
@@ -106,3 +109,89 @@ def test_d4_differs_from_d6_and_default_is_d6():
     for k in CONS:
         assert np.array_equal(out["default"][k], out["d6"][k]), k
     assert max(np.max(np.abs(out["d4"][k] - out["d6"][k])) for k in CONS) > 1e-6
+
+
+def _run(g, d, tab=None, steps=3, dt=None, recon="mp5"):
+    from paper_1810_04597_amd.grid import Grid
+    G = Grid(g, tables=tab, deriv_order=4, recon=recon)
+    G.curl_potential(d)
+    G.set_primitives(d)
+    L = G.read_group(G.rhs(), CONS, interior=True)
+    for _ in range(steps):
+        G.rk_step(dt if dt is not None else 0.0)
+    out = (L, G.to_numpy("prim", interior=True), G.to_numpy("cons", interior=True), G.diagnostics())
+    G.close()
+    return out
+
+
+@gpu
+@pytest.mark.parametrize("n,recon,ng", [(16, "mp5", 4), (9, "mp5", 4), (7, "weno5", 4), (16, "mp7", 5)])
+def test_one_ghost_layer_fewer_equals_bit_for_bit(n, recon, ng):
+    """16^3 (every n >= 2 ng: ghost images written by the update and the
+    inversion on both grids), 9^3 (images on the narrower grid only), 7^3
+    (separate ghost fills on both); MP7 on five layers against six."""
+    _torch()
+    from workloads import box
+    res = {}
+    for g_ in (ng, ng + 1):
+        g, d = box.turbulent_box(n, ng=g_)
+        res[g_] = _run(g, d, dt=2e-3, recon=recon)
+    for a in range(3):
+        for k in res[ng][a]:
+            assert np.array_equal(res[ng][a][k], res[ng + 1][a][k]), (a, k)
+    assert res[ng][3]["max_divb"] <= 1e-12
+
+
+@gpu
+def test_four_ghost_layers_parity_with_oracle():
+    _torch()
+    from workloads import box
+    g, d = box.turbulent_box(24, ng=4)
+    s, G = _pair(g, d)
+    L_o = s.rhs()
+    L_g = G.read_group(G.rhs(), CONS, interior=True)
+    errs = {k: float(np.max(np.abs(L_g[k] - L_o[k])) / np.max(np.abs(L_o[k]))) for k in CONS}
+    assert max(errs.values()) < 1e-11, errs
+    for _ in range(5):
+        dt_o = s.cfl_dt()
+        dt_g = G.rk_step(0.0, want_dt=True)
+        assert abs(dt_g / dt_o - 1) < 1e-11
+        s.rk_step(dt_o)
+    P = {k: interior(v, 4) for k, v in s.P.items()}
+    U = {k: interior(v, 4) for k, v in s.U.items()}
+    e = max_rel(G.to_numpy("prim", interior=True), P, PRIM)
+    e.update(max_rel(G.to_numpy("cons", interior=True), U, CONS))
+    assert max(e.values()) < 1e-10, e
+    G.close()
+
+
+@gpu
+def test_four_ghost_layers_torus():
+    """Torus 48 x 24 x 24 with four ghost layers: one step at the oracle's CFL
+    step within 1e-10 of the oracle on the same grid, and equal bit for bit
+    to the five-layer grid."""
+    _torch()
+    from workloads.torus import torus
+    g, d, tab = torus(48, 24, 24, ng=4)
+    s, G = _pair(g, d, tab)
+    dt = s.cfl_dt()
+    s.rk_step(dt)
+    G.rk_step(dt)
+    P = {k: interior(v, 4) for k, v in s.P.items()}
+    U = {k: interior(v, 4) for k, v in s.U.items()}
+    e = max_rel(G.to_numpy("prim", interior=True), P, PRIM)
+    e.update(max_rel(G.to_numpy("cons", interior=True), U, CONS))
+    assert max(e.values()) < 1e-10, e
+    got4 = (G.to_numpy("prim", interior=True), G.to_numpy("cons", interior=True))
+    G.close()
+    g5, d5, tab5 = torus(48, 24, 24, ng=5)
+    from paper_1810_04597_amd.grid import Grid
+    G5 = Grid(g5, tables=tab5, deriv_order=4)
+    G5.curl_potential(d5)
+    G5.set_primitives(d5)
+    G5.rk_step(dt)
+    got5 = (G5.to_numpy("prim", interior=True), G5.to_numpy("cons", interior=True))
+    G5.close()
+    for a in range(2):
+        for k in got4[a]:
+            assert np.array_equal(got4[a][k], got5[a][k]), (a, k)

@@ -71,6 +71,39 @@ def test_torus_cfl_step_matches_oracle(recon, order):
 
 
 @gpu
+def test_torus_fp32_form_with_fallback():
+    """FP32 form (fluxes from float32 face physics): against the oracle's
+    float32 form with the fallback, the same troubled zones up to decisions
+    at float32 rounding, no failed inversion, and the float32 difference
+    level (the oracle's own FP32-vs-FP64 difference here: rho 3e-6, u 5e-6,
+    p 4e-4 in the cold atmosphere)."""
+    _torch()
+    from workloads.torus import torus
+    from oracle.scheme import Solver
+    from paper_1810_04597_amd.grid import Grid
+    g, d, tab = torus(48, 24, 24)
+    s = Solver(g, tab, recon="weno5", precision="fp32", fallback=True)
+    s.curl_potential(d)
+    s.set_primitives(d)
+    G = Grid(g, tables=tab, recon="weno5", precision=1, fallback=True)
+    G.curl_potential(d)
+    G.set_primitives(d)
+    dt = s.cfl_dt()
+    s.rk_step(dt)
+    G.rk_step(dt)
+    dg = G.diagnostics()
+    print("fp32 form: troubled oracle %d gpu %d, failed gpu %d" % (s.n_troubled, dg["run_troubled"],
+                                                                 dg["run_c2p_fail"]))
+    assert dg["run_c2p_fail"] == 0
+    assert abs(dg["run_troubled"] - s.n_troubled) <= 0.01 * s.n_troubled
+    P = {k: interior(v, s.g) for k, v in s.P.items()}
+    e = max_rel(G.to_numpy("prim", interior=True), P, PRIM)
+    print("fp32 form vs oracle fp32 form:", e)
+    assert max(e[k] for k in PRIM if k != "p") < 1e-4, e
+    assert e["p"] < 5e-3, e
+
+
+@gpu
 def test_torus_without_fallback_fails_where_it_does_not():
     """The same step without the option: the GPU leaves failed inversions."""
     _torch()
