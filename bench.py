@@ -489,7 +489,9 @@ def torus_long_report(args):
     diagnostics, the fluxes through the first sphere outside the horizon
     (accretion rate -F_D, magnetic flux) and the MRI resolution of the torus
     body (rho > --mri-rho-cut: mass-weighted mean Q along theta and phi, the
-    fraction of body zones with Q >= 8); wall time per step over the run."""
+    fraction of body zones with Q >= 8); wall time per step over the run.
+    --recon and --fallback select the reconstruction and the lower-order
+    fallback; failed inversions and troubled zones are counted over the run."""
     import math
     import numpy as np
     import torch
@@ -497,7 +499,7 @@ def torus_long_report(args):
     from paper_1810_04597_amd.grid import Grid
     n1, n2, n3 = (int(x) for x in args.torus.split(","))
     g, d, tab = torus(n1, n2, n3)
-    G = Grid(g, tables=tab)
+    G = Grid(g, tables=tab, recon=args.recon, fallback=args.fallback)
     G.curl_potential(d)
     G.set_primitives(d)
     r = np.exp(g.x0[0] + (np.arange(n1) + 0.5) * g.dx[0])
@@ -516,9 +518,11 @@ def torus_long_report(args):
                    "mri_Q2": mq["Q2_mean"], "mri_Q3": mq["Q3_mean"],
                    "mri_frac_Q2_ok": mq["frac_Q2_ok"], "mri_frac_Q3_ok": mq["frac_Q3_ok"],
                    "sum_D": dg["sum_cons"][0], "w_max": dg["w_max"], "n_c2p_fail": dg["n_c2p_fail"],
-                   "n_nonfinite": dg["n_nonfinite"], "newton_iters_max": dg["newton_iters_max"]}
+                   "n_nonfinite": dg["n_nonfinite"], "newton_iters_max": dg["newton_iters_max"],
+                   "run_c2p_fail": dg["run_c2p_fail"], "run_troubled": dg["run_troubled"]}
             series.append(rec)
-            print("bench: step %d t %.3f mdot %.3e divb %.2e" % (s, rec["t"], rec["mdot_horizon"], rec["max_divb"]),
+            print("bench: step %d t %.3f mdot %.3e divb %.2e failed %d troubled %d"
+                  % (s, rec["t"], rec["mdot_horizon"], rec["max_divb"], rec["run_c2p_fail"], rec["run_troubled"]),
                   file=sys.stderr, flush=True)
             if dg["n_nonfinite"]:
                 break
@@ -528,8 +532,10 @@ def torus_long_report(args):
            "unit": "t (M)", "n_gpus": 1, "steps": series[-1]["step"], "warmup": 0,
            "ms_per_step": 1e3 * wall / series[-1]["step"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "Kerr-Schild a=0.9 torus %dx%dx%d, device CFL, diagnostics every %d steps"
-                                  % (n1, n2, n3, args.every), "r_shell": float(r[ih])},
+           "config": {"workload": "Kerr-Schild a=0.9 torus %dx%dx%d, device CFL, diagnostics every %d steps, "
+                                  "%s%s" % (n1, n2, n3, args.every, args.recon.upper(),
+                                            " with the lower-order fallback" if args.fallback else ""),
+                      "r_shell": float(r[ih])},
            "series": series}
     G.close()
     print(json.dumps(out))
@@ -703,6 +709,10 @@ def main():
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--torus", default="384,192,192")
     ap.add_argument("--every", type=int, default=250, help="torus-long: steps between diagnostics")
+    ap.add_argument("--recon", default="mp5", choices=["mp5", "weno5", "plm"],
+                    help="torus-long: reconstruction")
+    ap.add_argument("--fallback", action="store_true",
+                    help="torus-long: the lower-order fallback at troubled zones")
     ap.add_argument("--mri-rho-cut", type=float, default=1e-2,
                     help="torus-long: density above which a zone counts as torus body")
     args = ap.parse_args()

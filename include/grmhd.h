@@ -191,7 +191,9 @@ int grmhd_prim2cons(grmhd_grid* h);
 
 /* Right-hand side L(U) of the bound state: rhs_out (cons layout, 8 fields)
  * receives -sum_d D_d F_d + s at interior cells and -curl_D E at owned
- * faces; other elements are left untouched.  Uses the bound prim/cons. */
+ * faces; other elements are left untouched.  Uses the bound prim/cons.  The
+ * lower-order fallback (grmhd_grid_desc.fallback) corrects a stage's result,
+ * not L: it does not act here. */
 int grmhd_rhs(grmhd_grid* h, double* rhs_out);
 
 /* One SSP-RK3 step of the bound state.  dt > 0: that step; dt <= 0: the CFL

@@ -60,10 +60,10 @@ void launch_edge(int e, const Geom& G, bool flat, bool fp32, int recon, const do
 // face fields are also written to their ghost images (no separate face fill).
 // fp32: flux and edges hold float fields (the FP32 form's storage), read at
 // the same element offsets.
-// parts (mode 0): UPD_ALL, or the hydro fields alone (UPD_HYDRO, which also
-// writes the fallback's flag per interior zone, 1 where the new state is
-// unphysical, and counts those zones into fb->count) or the face fields alone
-// (UPD_INDUCTION, with the ghost images when img).
+// parts (mode 0): UPD_ALL, or the hydro fields alone (UPD_HYDRO, which with
+// fb also writes the fallback's flag per interior zone, 1 where the new state
+// is unphysical, and counts those zones into fb->count) or the face fields
+// alone (UPD_INDUCTION, with the ghost images when img).
 enum { UPD_HYDRO = 1, UPD_INDUCTION = 2, UPD_ALL = 3 };
 struct UpdateFallback {
   unsigned char* flags;   // n1 n2 n3 bytes, x^1 fastest

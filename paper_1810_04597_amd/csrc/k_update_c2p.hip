@@ -152,8 +152,11 @@ __device__ __forceinline__ bool troubled_state(const double nv[5], const MET& m)
   return dd <= 0.0 || tau <= 0.0 || s2 >= u * u;
 }
 
+// flags (nullable: then nothing is recorded): one byte per interior zone,
+// x^1 fastest; count: the number of flagged zones.
 __device__ __forceinline__ void flag_zone(const Geom& G, int i, int j, int k, bool bad,
                                           unsigned char* __restrict__ flags, int* __restrict__ count) {
+  if (!flags) return;
   flags[i + (long)G.n[0] * (j + (long)G.n[1] * k)] = bad ? 1 : 0;
   if (bad) atomicAdd(count, 1);
 }
@@ -857,9 +860,8 @@ void launch_update(const Geom& G, bool flat, bool fp32, int mode, const double* 
                    const double* flux, const double* edges, const double* tab, double a, double b,
                    double dt_host, const double* d_dt, double* out, int stage, hipStream_t s, int img,
                    int parts, const UpdateFallback* fb) {
-  // split updates are stage updates (mode 0); the hydro part always flags
+  // split updates are stage updates (mode 0); the hydro part flags when fb is given
   if (mode != 0) parts = UPD_ALL;
-  if (parts == UPD_HYDRO && !fb) return;
   unsigned char* tflags = fb ? fb->flags : nullptr;
   int* tcount = fb ? fb->count : nullptr;
   if (fp32)
