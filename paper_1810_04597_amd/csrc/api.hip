@@ -121,8 +121,9 @@ struct grmhd_grid {
   long long* d_spart = nullptr;  // per-block inversion statistics
   long long* d_stats = nullptr;  // reduced inversion statistics (8)
   unsigned long long* d_run = nullptr;  // accumulated inversion counters (RUN_SLOTS x RUN_STRIDE)
-  unsigned char* d_trouble = nullptr;   // lower-order fallback: a flag per interior zone
-  int* d_ntrouble = nullptr;            // troubled zones of the current stage
+  unsigned char* d_trouble = nullptr;   // lower-order fallback: a flag per interior zone,
+  int* d_tlist = nullptr;               // the flagged zones of the current stage,
+  int* d_ntrouble = nullptr;            // and their number
   double* d_diag = nullptr;      // reduced diagnostics (16)
   unsigned nblk = 0;
   int64_t step = 0;
@@ -332,7 +333,9 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, void* hip_stream, grmhd_grid** 
   if (e == hipSuccess) e = hipMalloc(&h->d_run, (size_t)RUN_SLOTS * RUN_STRIDE * sizeof(unsigned long long));
   if (e == hipSuccess) launch_zero_u64(h->d_run, RUN_SLOTS * RUN_STRIDE, h->stream);
   if (e == hipSuccess && desc->fallback) {
-    e = hipMalloc(&h->d_trouble, (size_t)desc->n[0] * desc->n[1] * desc->n[2]);
+    const size_t nz = (size_t)desc->n[0] * desc->n[1] * desc->n[2];
+    e = hipMalloc(&h->d_trouble, nz);
+    if (e == hipSuccess) e = hipMalloc(&h->d_tlist, nz * sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&h->d_ntrouble, sizeof(int));
     if (e == hipSuccess) launch_zero_int(h->d_ntrouble, h->stream);
   }
@@ -530,7 +533,7 @@ static void step_stages(grmhd_grid* h, double dt) {
         // fix replaces the fluxes at their faces (reading the face fields of
         // the stage's start, which stage 2 updates in place), then the
         // induction update
-        UpdateFallback fb{h->d_trouble, h->d_ntrouble};
+        UpdateFallback fb{h->d_trouble, h->d_tlist, h->d_ntrouble};
         launch_zero_int(h->d_ntrouble, h->stream);
         launch_update(h->G, h->flat, fp32, 0, h->prim, s == 0 ? Un : S, s == 0 ? S : Un, h->flux(),
                       h->edges(), h->tab, A[s], B[s], dt, dt_src, nullptr, s + 1, h->stream, img ? 1 : 0,
@@ -539,8 +542,10 @@ static void step_stages(grmhd_grid* h, double dt) {
     });
     if (h->desc.fallback) {
       h->timed(16, [&] {
+        // the face deltas go to the per-face edge-field data, which the
+        // stage's edge fields have consumed and the next sweeps overwrite
         launch_fallback(h->G, h->flat, fp32, h->bc, h->prim, cur, next, h->flux(), h->tab, h->d_trouble,
-                        h->d_ntrouble, B[s], dt, dt_src, h->d_run, h->stream);
+                        h->d_tlist, h->d_ntrouble, h->ctd(), B[s], dt, dt_src, h->d_run, h->stream);
       });
       h->timed(7, [&] {
         launch_update(h->G, h->flat, fp32, 0, h->prim, s == 0 ? Un : S, s == 0 ? S : Un, h->flux(),
@@ -960,6 +965,7 @@ void grmhd_destroy(grmhd_grid* h) {
   (void)hipFree(h->d_diag);
   (void)hipFree(h->d_run);
   (void)hipFree(h->d_trouble);
+  (void)hipFree(h->d_tlist);
   (void)hipFree(h->d_ntrouble);
   delete h;
 }

@@ -67,24 +67,31 @@ void launch_edge(int e, const Geom& G, bool flat, bool fp32, int recon, const do
 enum { UPD_HYDRO = 1, UPD_INDUCTION = 2, UPD_ALL = 3 };
 struct UpdateFallback {
   unsigned char* flags;   // n1 n2 n3 bytes, x^1 fastest
-  int* count;             // zeroed before the launch
+  int* list;              // n1 n2 n3 ints: the flagged zones (any order)
+  int* count;             // their number; zeroed before the launch
 };
 void launch_update(const Geom& G, bool flat, bool fp32, int mode, const double* prim, double* x, double* y,
                    const double* flux, const double* edges, const double* tab, double a, double b,
                    double dt_host, const double* d_dt, double* out, int stage, hipStream_t s,
                    int img = 0, int parts = UPD_ALL, const UpdateFallback* fb = nullptr);
 // Lower-order fallback of one stage (after the UPD_HYDRO update, before the
-// UPD_INDUCTION one): each interior zone with a flagged zone on either side of
-// one of its faces (periodic directions wrap; elsewhere zones outside count as
-// unflagged) adds b dt times the difference of (F1 - G) over those faces to
-// its new hydro state in `next`, F1 the first-order HLL flux from the
+// UPD_INDUCTION one), two launches.  (1) Over the listed zones' faces (a
+// fixed grid walking 6 count items): (F1 - G) of the five hydro fields at
+// each face of a flagged zone, written to `delta` (15 face fields, the
+// layout of the fluxes; each face once, and at its periodic image when it
+// lies on a periodic boundary), F1 the first-order HLL flux from the
 // primitives of the two cells and the face field in `cur`, G the corrected
-// flux of the stored face fluxes.  Exits at once when count is 0; adds count
-// to the accumulated counters (run_acc, nullable).
+// flux of the stored face fluxes.  (2) Each interior zone with a flagged
+// zone on either side of one of its faces (periodic directions wrap;
+// elsewhere zones outside count as unflagged) subtracts b dt times the
+// difference of those faces' deltas over the cell from its new hydro state
+// in `next`.  Both exit at once when count is 0; the second adds count to
+// the accumulated counters (run_acc, nullable).
 void launch_fallback(const Geom& G, bool flat, bool fp32, const BCSpec& bc, const double* prim,
                      const double* cur, double* next, const double* flux, const double* tab,
-                     const unsigned char* flags, const int* count, double b, double dt_host,
-                     const double* d_dt, unsigned long long* run_acc, hipStream_t s);
+                     const unsigned char* flags, const int* list, const int* count, double* delta,
+                     double b, double dt_host, const double* d_dt, unsigned long long* run_acc,
+                     hipStream_t s);
 void launch_advance(double* d_dt, const double* src, double dt_host, hipStream_t s);
 // Inversion of all interior zones; per-block counters into partials[0, nblk),
 // CFL partials (nullable) into cfl_partials[0, nblk).  list != nullptr: defer

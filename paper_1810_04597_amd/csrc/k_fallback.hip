@@ -16,11 +16,15 @@
 // state of a zone changes by -b dt sum_d [(F1 - G)_{+1/2} - (F1 - G)_{-1/2}]
 // / Delta_d over its replaced faces, so the step stays conservative.
 //
-// One thread per interior zone gathers the corrections of its own faces, so
-// no two threads write one value; each face shared by two zones is evaluated
-// by both, by the one (not inlined) routine, so both take the same value.
-// When no zone is troubled (the usual case) every workgroup exits after
-// reading the count.
+// Two launches.  The update lists the troubled zones; a fixed grid walks
+// the six faces of each listed zone (face-major, so a wavefront mostly takes
+// one direction) and writes (F1 - G) of each face once to face fields laid
+// out like the fluxes (a face shared by two troubled zones is written by the
+// lower one; a face on a periodic boundary also at its image, so both zones
+// beside it read the one value and the step stays conservative).  Then one
+// thread per interior zone gathers the values of its replaced faces, so no
+// two threads write one value.  When no zone is troubled (the usual case)
+// both exit after reading the count.
 #include "grmhd_device.hpp"
 #include "grmhd_kernels.hpp"
 #include "grmhd_c2p.hpp"
@@ -33,10 +37,10 @@ namespace grmhd {
 // G from the stored face fluxes of faces -2 .. +2 around it (-1 .. +1 for the
 // fourth-order form).
 template <int DIR, class MET, typename FS, int DO>
-__device__ __noinline__ void face_delta(const Geom G, const double* __restrict__ prim,
-                                        const double* __restrict__ cur, const FS* __restrict__ flux,
-                                        const double* __restrict__ tab, int fi, int fj, int fk,
-                                        double* __restrict__ out) {
+__device__ __forceinline__ void face_delta(const Geom& G, const double* __restrict__ prim,
+                                           const double* __restrict__ cur, const FS* __restrict__ flux,
+                                           const double* __restrict__ tab, int fi, int fj, int fk,
+                                           double* __restrict__ out) {
   constexpr int T1 = (DIR + 1) % 3, T2 = (DIR + 2) % 3;
   const long c = G.idx(fi, fj, fk);
   const long st = G.stride(DIR);
@@ -69,29 +73,99 @@ __device__ __noinline__ void face_delta(const Geom G, const double* __restrict__
   }
 }
 
-// The corrections of direction DIR at zone (i, j, k): faces -1/2 (stored at
-// the DIR neighbour below) where lo, +1/2 where hi.
+// Whether interior zone w (w[d] may be one past either end) is flagged: a
+// periodic direction wraps, elsewhere zones outside count as unflagged.
+__device__ __forceinline__ bool flagged(const Geom& G, const BCSpec& bc, const unsigned char* __restrict__ flags,
+                                        int w0, int w1, int w2) {
+  int w[3] = {w0, w1, w2};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (w[d] < 0 || w[d] >= G.n[d]) {
+      if (bc.bc[2 * d] != 0) return false;   // not periodic (0)
+      w[d] = w[d] < 0 ? w[d] + G.n[d] : w[d] - G.n[d];
+    }
+  }
+  return flags[w[0] + (long)G.n[0] * (w[1] + (long)G.n[1] * w[2])] != 0;
+}
+
+// Workgroups of the face pass (a fixed grid; each thread walks items).
+constexpr int FB_FACE_BLOCKS = 1024;
+
 template <int DIR, class MET, typename FS, int DO>
-__device__ __forceinline__ void correct_dir(const Geom& G, const double* __restrict__ prim,
-                                            const double* __restrict__ cur, const FS* __restrict__ flux,
-                                            const double* __restrict__ tab, int i, int j, int k, bool lo,
+__device__ __forceinline__ void store_face_delta(const Geom& G, const BCSpec& bc, const double* __restrict__ prim,
+                                                 const double* __restrict__ cur, const FS* __restrict__ flux,
+                                                 const double* __restrict__ tab, int f0, int f1, int f2,
+                                                 double* __restrict__ delta) {
+  double dl[5];
+  face_delta<DIR, MET, FS, DO>(G, prim, cur, flux, tab, f0, f1, f2, dl);
+  int f[3] = {f0, f1, f2};
+  const long c = G.idx(f0, f1, f2);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) delta[((long)DIR * 5 + q) * G.field + c] = dl[q];
+  // the same face seen from the other side of a periodic boundary: stored at
+  // -1 (face -1/2) and at n - 1 (face n - 1/2)
+  if (bc.bc[2 * DIR] == 0 && (f[DIR] == -1 || f[DIR] == G.n[DIR] - 1)) {
+    f[DIR] = f[DIR] == -1 ? G.n[DIR] - 1 : -1;
+    const long ci = G.idx(f[0], f[1], f[2]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) delta[((long)DIR * 5 + q) * G.field + ci] = dl[q];
+  }
+}
+
+template <class MET, typename FS, int DO>
+__global__ __launch_bounds__(256) void k_fallback_faces(Geom G, BCSpec bc, const double* __restrict__ prim,
+                                                        const double* __restrict__ cur,
+                                                        const FS* __restrict__ flux,
+                                                        const double* __restrict__ tab,
+                                                        const unsigned char* __restrict__ flags,
+                                                        const int* __restrict__ list,
+                                                        const int* __restrict__ count,
+                                                        double* __restrict__ delta) {
+  const long nt = *count;
+  if (nt == 0) return;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long w = (long)blockIdx.x * blockDim.x + threadIdx.x; w < 6 * nt; w += stride) {
+    const int face = (int)(w / nt);           // direction face / 2; side face % 2 (0: -1/2, 1: +1/2)
+    const int z = list[w - face * nt];
+    int ijk[3];
+    ijk[0] = z % G.n[0];
+    ijk[1] = (z / G.n[0]) % G.n[1];
+    ijk[2] = z / (G.n[0] * G.n[1]);
+    const int d = face >> 1;
+    if ((face & 1) == 0) {
+      // the -1/2 face is stored at the lower neighbour, which writes it
+      // itself (as its +1/2 face) when it is flagged too
+      int nb[3] = {ijk[0], ijk[1], ijk[2]};
+      nb[d] -= 1;
+      if (flagged(G, bc, flags, nb[0], nb[1], nb[2])) continue;
+      ijk[d] -= 1;
+    }
+    if (d == 0) store_face_delta<0, MET, FS, DO>(G, bc, prim, cur, flux, tab, ijk[0], ijk[1], ijk[2], delta);
+    else if (d == 1) store_face_delta<1, MET, FS, DO>(G, bc, prim, cur, flux, tab, ijk[0], ijk[1], ijk[2], delta);
+    else store_face_delta<2, MET, FS, DO>(G, bc, prim, cur, flux, tab, ijk[0], ijk[1], ijk[2], delta);
+  }
+}
+
+// The corrections of direction DIR at zone c: faces -1/2 (stored at the DIR
+// neighbour below) where lo, +1/2 where hi.
+template <int DIR>
+__device__ __forceinline__ void correct_dir(const Geom& G, const double* __restrict__ delta, long c, bool lo,
                                             bool hi, double bdt, double v[5]) {
   if (!lo && !hi) return;
   double dlo[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, dhi[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (lo)
-    face_delta<DIR, MET, FS, DO>(G, prim, cur, flux, tab, DIR == 0 ? i - 1 : i, DIR == 1 ? j - 1 : j,
-                                 DIR == 2 ? k - 1 : k, dlo);
-  if (hi) face_delta<DIR, MET, FS, DO>(G, prim, cur, flux, tab, i, j, k, dhi);
+  const long st = G.stride(DIR);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const double* f = delta + ((long)DIR * 5 + q) * G.field + c;
+    if (lo) dlo[q] = f[-st];
+    if (hi) dhi[q] = f[0];
+  }
 #pragma unroll
   for (int q = 0; q < 5; ++q) v[q] = v[q] - bdt * (dhi[q] - dlo[q]) / G.dx[DIR];
 }
 
-template <class MET, typename FS, int DO>
-__global__ __launch_bounds__(256) void k_fallback(Geom G, BCSpec bc, const double* __restrict__ prim,
-                                                  const double* __restrict__ cur,
-                                                  double* __restrict__ next,
-                                                  const FS* __restrict__ flux,
-                                                  const double* __restrict__ tab,
+__global__ __launch_bounds__(256) void k_fallback(Geom G, BCSpec bc, double* __restrict__ next,
+                                                  const double* __restrict__ delta,
                                                   const unsigned char* __restrict__ flags,
                                                   const int* __restrict__ count, double b,
                                                   double dt_host, const double* __restrict__ d_dt,
@@ -104,23 +178,13 @@ __global__ __launch_bounds__(256) void k_fallback(Geom G, BCSpec bc, const doubl
   if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
   int i, j, k;
   zone_of(G, t, i, j, k);
-  const int z[3] = {i, j, k};
-  auto flag_at = [&](int d, int off) -> bool {
-    int w[3] = {z[0], z[1], z[2]};
-    w[d] += off;
-    if (w[d] < 0 || w[d] >= G.n[d]) {
-      if (bc.bc[2 * d] != 0) return false;   // not periodic (0): outside counts as unflagged
-      w[d] = w[d] < 0 ? w[d] + G.n[d] : w[d] - G.n[d];
-    }
-    return flags[w[0] + (long)G.n[0] * (w[1] + (long)G.n[1] * w[2])] != 0;
-  };
-  const bool self = flag_at(0, 0);
+  const bool self = flags[t] != 0;
   bool lo[3], hi[3];
   bool any = self;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    lo[d] = self || flag_at(d, -1);
-    hi[d] = self || flag_at(d, 1);
+    lo[d] = self || flagged(G, bc, flags, i - (d == 0), j - (d == 1), k - (d == 2));
+    hi[d] = self || flagged(G, bc, flags, i + (d == 0), j + (d == 1), k + (d == 2));
     any = any || lo[d] || hi[d];
   }
   if (!any) return;
@@ -129,44 +193,41 @@ __global__ __launch_bounds__(256) void k_fallback(Geom G, BCSpec bc, const doubl
   double v[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) v[q] = next[(long)q * G.field + c];
-  correct_dir<0, MET, FS, DO>(G, prim, cur, flux, tab, i, j, k, lo[0], hi[0], bdt, v);
-  correct_dir<1, MET, FS, DO>(G, prim, cur, flux, tab, i, j, k, lo[1], hi[1], bdt, v);
-  correct_dir<2, MET, FS, DO>(G, prim, cur, flux, tab, i, j, k, lo[2], hi[2], bdt, v);
+  correct_dir<0>(G, delta, c, lo[0], hi[0], bdt, v);
+  correct_dir<1>(G, delta, c, lo[1], hi[1], bdt, v);
+  correct_dir<2>(G, delta, c, lo[2], hi[2], bdt, v);
 #pragma unroll
   for (int q = 0; q < 5; ++q) next[(long)q * G.field + c] = v[q];
 }
 
 template <class MET, typename FS>
-static void launch_fallback_m(const Geom& G, const BCSpec& bc, const double* prim, const double* cur,
-                              double* next, const FS* flux, const double* tab, const unsigned char* flags,
-                              const int* count, double b, double dt_host, const double* d_dt,
-                              unsigned long long* run_acc, hipStream_t s) {
-  const unsigned nb = zone_blocks(G);
+static void launch_faces_m(const Geom& G, const BCSpec& bc, const double* prim, const double* cur,
+                           const FS* flux, const double* tab, const unsigned char* flags, const int* list,
+                           const int* count, double* delta, hipStream_t s) {
   if (G.dorder == 4)
-    hipLaunchKernelGGL((k_fallback<MET, FS, 4>), dim3(nb), dim3(256), 0, s, G, bc, prim, cur, next, flux, tab,
-                       flags, count, b, dt_host, d_dt, run_acc);
+    hipLaunchKernelGGL((k_fallback_faces<MET, FS, 4>), dim3(FB_FACE_BLOCKS), dim3(256), 0, s, G, bc, prim, cur,
+                       flux, tab, flags, list, count, delta);
   else
-    hipLaunchKernelGGL((k_fallback<MET, FS, 6>), dim3(nb), dim3(256), 0, s, G, bc, prim, cur, next, flux, tab,
-                       flags, count, b, dt_host, d_dt, run_acc);
+    hipLaunchKernelGGL((k_fallback_faces<MET, FS, 6>), dim3(FB_FACE_BLOCKS), dim3(256), 0, s, G, bc, prim, cur,
+                       flux, tab, flags, list, count, delta);
 }
 
 void launch_fallback(const Geom& G, bool flat, bool fp32, const BCSpec& bc, const double* prim,
                      const double* cur, double* next, const double* flux, const double* tab,
-                     const unsigned char* flags, const int* count, double b, double dt_host,
-                     const double* d_dt, unsigned long long* run_acc, hipStream_t s) {
+                     const unsigned char* flags, const int* list, const int* count, double* delta,
+                     double b, double dt_host, const double* d_dt, unsigned long long* run_acc,
+                     hipStream_t s) {
   const float* ff = reinterpret_cast<const float*>(flux);
   if (flat && fp32)
-    launch_fallback_m<FlatMet<double>, float>(G, bc, prim, cur, next, ff, tab, flags, count, b, dt_host, d_dt,
-                                              run_acc, s);
+    launch_faces_m<FlatMet<double>, float>(G, bc, prim, cur, ff, tab, flags, list, count, delta, s);
   else if (flat)
-    launch_fallback_m<FlatMet<double>, double>(G, bc, prim, cur, next, flux, tab, flags, count, b, dt_host,
-                                               d_dt, run_acc, s);
+    launch_faces_m<FlatMet<double>, double>(G, bc, prim, cur, flux, tab, flags, list, count, delta, s);
   else if (fp32)
-    launch_fallback_m<TabMet<double>, float>(G, bc, prim, cur, next, ff, tab, flags, count, b, dt_host, d_dt,
-                                             run_acc, s);
+    launch_faces_m<TabMet<double>, float>(G, bc, prim, cur, ff, tab, flags, list, count, delta, s);
   else
-    launch_fallback_m<TabMet<double>, double>(G, bc, prim, cur, next, flux, tab, flags, count, b, dt_host,
-                                              d_dt, run_acc, s);
+    launch_faces_m<TabMet<double>, double>(G, bc, prim, cur, flux, tab, flags, list, count, delta, s);
+  hipLaunchKernelGGL(k_fallback, dim3(zone_blocks(G)), dim3(256), 0, s, G, bc, next, delta, flags, count, b,
+                     dt_host, d_dt, run_acc);
 }
 
 }  // namespace grmhd

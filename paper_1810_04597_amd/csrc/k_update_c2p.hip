@@ -153,12 +153,15 @@ __device__ __forceinline__ bool troubled_state(const double nv[5], const MET& m)
 }
 
 // flags (nullable: then nothing is recorded): one byte per interior zone,
-// x^1 fastest; count: the number of flagged zones.
+// x^1 fastest; the flagged zones' indices are appended to list, count holds
+// their number.
 __device__ __forceinline__ void flag_zone(const Geom& G, int i, int j, int k, bool bad,
-                                          unsigned char* __restrict__ flags, int* __restrict__ count) {
+                                          unsigned char* __restrict__ flags, int* __restrict__ list,
+                                          int* __restrict__ count) {
   if (!flags) return;
-  flags[i + (long)G.n[0] * (j + (long)G.n[1] * k)] = bad ? 1 : 0;
-  if (bad) atomicAdd(count, 1);
+  const int z = i + G.n[0] * (j + G.n[1] * k);
+  flags[z] = bad ? 1 : 0;
+  if (bad) list[atomicAdd(count, 1)] = z;
 }
 
 // FS: storage type of the fluxes and edge fields (double, or float in the
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
                                                 double dt_host, const double* __restrict__ d_dt,
                                                 double* __restrict__ out, int stage,
                                                 unsigned char* __restrict__ tflags,
-                                                int* __restrict__ tcount) {
+                                                int* __restrict__ tlist, int* __restrict__ tcount) {
   const long t = flat_thread();
   if (t >= (long)G.n[0] * G.n[1] * G.n[2]) return;
   int i, j, k;
@@ -221,7 +224,7 @@ __global__ __launch_bounds__(256) void k_update(Geom G, int mode, const double* 
     if constexpr (PARTS == UPD_HYDRO) {
       MET mc;
       if constexpr (!MET::flat) mc.load(tab, G.tab_plane, LOC_C, G.tidx(i, j));
-      flag_zone(G, i, j, k, troubled_state(nv, mc), tflags, tcount);
+      flag_zone(G, i, j, k, troubled_state(nv, mc), tflags, tlist, tcount);
     }
   }
   if constexpr ((PARTS & UPD_INDUCTION) != 0) {
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
                                                    double b, double dt_host,
                                                    const double* __restrict__ d_dt, int img,
                                                    unsigned char* __restrict__ tflags,
-                                                   int* __restrict__ tcount) {
+                                                   int* __restrict__ tlist, int* __restrict__ tcount) {
   constexpr bool HYD = (PARTS & UPD_HYDRO) != 0, IND = (PARTS & UPD_INDUCTION) != 0;
   const long t = flat_thread();
   const int nseg = (G.n[2] + KZ - 1) / KZ;
@@ -326,7 +329,7 @@ __global__ __launch_bounds__(256) void k_update_zm(Geom G, const double* __restr
         L = L - fd_deriv_o<DO>(wf[q], idx2);
         nv[q] = rk_store<ST>(x, y, (long)q * G.field + c, a, b, dt, L);
       }
-      if constexpr (!IND) flag_zone(G, i, j, k, troubled_state(nv, MET()), tflags, tcount);
+      if constexpr (!IND) flag_zone(G, i, j, k, troubled_state(nv, MET()), tflags, tlist, tcount);
     }
     if constexpr (IND) {
       // B^1: -D_2 E_3 + D_3 E_2
@@ -801,28 +804,28 @@ static void launch_update_p(const Geom& G, bool flat, int mode, const double* pr
                             double* y, const FS* flux, const FS* edges,
                             const double* tab, double a, double b, double dt_host,
                             const double* d_dt, double* out, int stage, hipStream_t s, int img,
-                            unsigned char* tflags, int* tcount) {
+                            unsigned char* tflags, int* tlist, int* tcount) {
   const unsigned nb = zone_blocks(G);
   if (flat && mode == 0) {
     const long nseg = (G.n[2] + KZ - 1) / KZ;
     const unsigned ng = nblk((long)G.n[0] * G.n[1] * nseg);
     if (stage == 1)
       hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 1, DO, FS, PARTS>), dim3(ng), dim3(256), 0, s, G, prim,
-                         x, y, flux, edges, tab, a, b, dt_host, d_dt, img, tflags, tcount);
+                         x, y, flux, edges, tab, a, b, dt_host, d_dt, img, tflags, tlist, tcount);
     else if (stage == 2)
       hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 2, DO, FS, PARTS>), dim3(ng), dim3(256), 0, s, G, prim,
-                         x, y, flux, edges, tab, a, b, dt_host, d_dt, img, tflags, tcount);
+                         x, y, flux, edges, tab, a, b, dt_host, d_dt, img, tflags, tlist, tcount);
     else
       hipLaunchKernelGGL((k_update_zm<FlatMet<double>, 3, DO, FS, PARTS>), dim3(ng), dim3(256), 0, s, G, prim,
-                         x, y, flux, edges, tab, a, b, dt_host, d_dt, img, tflags, tcount);
+                         x, y, flux, edges, tab, a, b, dt_host, d_dt, img, tflags, tlist, tcount);
   } else if (flat) {
     // the right-hand side alone (mode 1): every field
     if constexpr (PARTS == UPD_ALL)
       hipLaunchKernelGGL((k_update<FlatMet<double>, DO, FS, UPD_ALL>), dim3(nb), dim3(256), 0, s, G, mode,
-                         prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, tflags, tcount);
+                         prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, tflags, tlist, tcount);
   } else {
     hipLaunchKernelGGL((k_update<TabMet<double>, DO, FS, PARTS>), dim3(nb), dim3(256), 0, s, G, mode, prim,
-                       x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, tflags, tcount);
+                       x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, tflags, tlist, tcount);
   }
 }
 
@@ -831,29 +834,29 @@ static void launch_update_o(const Geom& G, bool flat, int mode, const double* pr
                             double* y, const FS* flux, const FS* edges,
                             const double* tab, double a, double b, double dt_host,
                             const double* d_dt, double* out, int stage, hipStream_t s, int img,
-                            int parts, unsigned char* tflags, int* tcount) {
+                            int parts, unsigned char* tflags, int* tlist, int* tcount) {
   if (parts == UPD_HYDRO)
     launch_update_p<DO, FS, UPD_HYDRO>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out,
-                                       stage, s, img, tflags, tcount);
+                                       stage, s, img, tflags, tlist, tcount);
   else if (parts == UPD_INDUCTION)
     launch_update_p<DO, FS, UPD_INDUCTION>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt,
-                                           out, stage, s, img, tflags, tcount);
+                                           out, stage, s, img, tflags, tlist, tcount);
   else
     launch_update_p<DO, FS, UPD_ALL>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out,
-                                     stage, s, img, tflags, tcount);
+                                     stage, s, img, tflags, tlist, tcount);
 }
 
 template <typename FS>
 static void launch_update_s(const Geom& G, bool flat, int mode, const double* prim, double* x, double* y,
                             const FS* flux, const FS* edges, const double* tab, double a, double b,
                             double dt_host, const double* d_dt, double* out, int stage, hipStream_t s,
-                            int img, int parts, unsigned char* tflags, int* tcount) {
+                            int img, int parts, unsigned char* tflags, int* tlist, int* tcount) {
   if (G.dorder == 4)
     launch_update_o<4, FS>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img,
-                           parts, tflags, tcount);
+                           parts, tflags, tlist, tcount);
   else
     launch_update_o<6, FS>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s, img,
-                           parts, tflags, tcount);
+                           parts, tflags, tlist, tcount);
 }
 
 void launch_update(const Geom& G, bool flat, bool fp32, int mode, const double* prim, double* x, double* y,
@@ -863,14 +866,15 @@ void launch_update(const Geom& G, bool flat, bool fp32, int mode, const double* 
   // split updates are stage updates (mode 0); the hydro part flags when fb is given
   if (mode != 0) parts = UPD_ALL;
   unsigned char* tflags = fb ? fb->flags : nullptr;
+  int* tlist = fb ? fb->list : nullptr;
   int* tcount = fb ? fb->count : nullptr;
   if (fp32)
     launch_update_s<float>(G, flat, mode, prim, x, y, reinterpret_cast<const float*>(flux),
                            reinterpret_cast<const float*>(edges), tab, a, b, dt_host, d_dt, out, stage, s, img,
-                           parts, tflags, tcount);
+                           parts, tflags, tlist, tcount);
   else
     launch_update_s<double>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s,
-                            img, parts, tflags, tcount);
+                            img, parts, tflags, tlist, tcount);
 }
 
 // d_dt[0]: dt of the last step, d_dt[1]: time; src: where the device dt was read
