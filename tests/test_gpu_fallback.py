@@ -14,6 +14,10 @@ with the oracle's Solver(fallback=True), through the C ABI.
     whose hydro part is admissible but which no primitives give with that
     field, which the criterion does not test; their failure decisions sit at
     round-off, so that case is no parity case.)
+  * the same blast centred on the box corner, so that troubled zones sit on
+    both sides of every periodic boundary (faces written at their periodic
+    images): parity with the oracle, and the centred run rolled by half the
+    box bit for bit;
   * where nothing is troubled (the turbulent box) the option changes no bit
     of the state, eager and graph-replayed, FP64 and FP32 forms.
 """
@@ -149,6 +153,36 @@ def test_blast_box_matches_oracle(n, recon):
     assert sum(x["n_fail"] for x in s.last_stage_stats) == 0
     assert dg["run_c2p_fail"] == 0
     _compare(s, G, 1e-10)
+
+
+@gpu
+@pytest.mark.parametrize("n", [16, (16, 16, 8)])
+def test_blast_on_the_corner(n):
+    _torch()
+    from workloads import box
+    from oracle.scheme import Solver
+    from paper_1810_04597_amd.grid import Grid
+    got = {}
+    for name, c in (("centre", (0.5, 0.5, 0.5)), ("corner", (0.0, 0.0, 0.0))):
+        g, d = box.blast_box(n, b0=0.0, centre=c)
+        G = Grid(g, recon="mp5", fallback=True)
+        G.set_face_fields(d)
+        G.set_primitives(d)
+        G.rk_step(2.0e-3)
+        got[name] = (G.to_numpy("cons", interior=True), G.diagnostics()["run_troubled"])
+        if name == "corner":
+            s = Solver(g, recon="mp5", fallback=True)
+            s.set_face_fields(d)
+            s.set_primitives(d)
+            s.rk_step(2.0e-3)
+            assert got[name][1] == s.n_troubled > 0
+            _compare(s, G, 1e-10)
+        G.close()
+    nn = (n, n, n) if np.isscalar(n) else n
+    shift = (nn[2] // 2, nn[1] // 2, nn[0] // 2)
+    for k in CONS:
+        rolled = np.roll(got["centre"][0][k], shift, axis=(0, 1, 2))
+        assert np.array_equal(got["corner"][0][k], rolled), k
 
 
 @gpu

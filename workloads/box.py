@@ -192,18 +192,21 @@ def entropy_wave_1d(n, axis=0, t=0.0, ng=5, amp=0.2, v=(0.3, 0.2, 0.1), p=1.0,
     return grid, data
 
 
-def blast_box(n, ng=5, rho_in=1e-2, p_in=1.0, rho_out=1e-4, p_out=3e-5, r0=0.08, b0=0.1):
+def blast_box(n, ng=5, rho_in=1e-2, p_in=1.0, rho_out=1e-4, p_out=3e-5, r0=0.08, b0=0.1,
+              centre=(0.5, 0.5, 0.5)):
     """Magnetised blast wave (the relativistic MHD blast problem of Komissarov
-    1999, scaled to the periodic unit box): a sphere of radius r0 about the
-    box centre at rho_in, p_in in a medium at rho_out, p_out, at rest, in a
-    uniform field B = (b0, 0, 0).  n: zones per side, or (n1, n2, n3).  The
-    jump of four orders of magnitude in pressure makes the high-order update
-    leave unphysical states next to the shell in the first steps.  Returns
-    (grid, data) with interior primitives and ghosted face fields."""
+    1999, scaled to the periodic unit box): a sphere of radius r0 about
+    `centre` (periodic distances) at rho_in, p_in in a medium at rho_out,
+    p_out, at rest, in a uniform field B = (b0, 0, 0).  n: zones per side, or
+    (n1, n2, n3).  The jump of four orders of magnitude in pressure makes the
+    high-order update leave unphysical states next to the shell in the first
+    steps.  Returns (grid, data) with interior primitives and ghosted face
+    fields."""
     from .grid import GridSpec
     nn = (n, n, n) if np.isscalar(n) else tuple(n)
     grid = GridSpec(n=nn, ng=ng, dx=tuple(1.0 / x for x in nn))
-    x = [(np.arange(nn[a]) + 0.5) / nn[a] - 0.5 for a in range(3)]
+    x = [(np.arange(nn[a]) + 0.5) / nn[a] - centre[a] for a in range(3)]
+    x = [v - np.round(v) for v in x]
     r = np.sqrt(x[0][None, None, :] ** 2 + x[1][None, :, None] ** 2 + x[2][:, None, None] ** 2)
     inside = r < r0
     shp = (nn[2], nn[1], nn[0])
