@@ -46,9 +46,10 @@ CLASS_OF = [(r"k_sweep(_lds)?<0", "sweep_x1"), (r"k_sweep(_lds)?<1", "sweep_x2")
             (r"k_bc_faces", "bc_faces"), (r"k_cfl", "cfl"), (r"k_dt_final", "dt_final"),
             (r"k_advance", "advance"), (r"__amd_rocclr_copyBuffer", "copy_calib")]
 # rows of the update split by RK stage (template argument after the metric)
-STAGE_ROW = [(r"k_update_zm<.*, 1, [0-9]>", "update (stage 1: U^n in, U^(1) out)"),
-             (r"k_update_zm<.*, 2, [0-9]>", "update (stage 2, in place)"),
-             (r"k_update_zm<.*, 3, [0-9]>", "update (stage 3: U^(3) over U^n)")]
+# (k_update_zm<metric, stage, derivative order, flux storage, parts>)
+STAGE_ROW = [(r"k_update_zm<.*>, 1, [0-9], ", "update (stage 1: U^n in, U^(1) out)"),
+             (r"k_update_zm<.*>, 2, [0-9], ", "update (stage 2, in place)"),
+             (r"k_update_zm<.*>, 3, [0-9], ", "update (stage 3: U^(3) over U^n)")]
 
 
 def class_of(name):
