@@ -11,7 +11,7 @@ import pytest
 
 from paper_1810_04597_amd import profsum, traffic
 
-UPDATE = "void grmhd::k_update_zm<grmhd::FlatMet<double>, 2, 6>(grmhd::Geom, double const*)"
+UPDATE = "void grmhd::k_update_zm<grmhd::FlatMet<double>, 2, 6, double, 3>(grmhd::Geom, double const*)"
 SWEEP = "void grmhd::k_sweep_lds<1, 4, grmhd::FlatMet<double>, double, 0>(grmhd::Geom)"
 COPY = "__amd_rocclr_copyBuffer"
 GiB = 1 << 30
