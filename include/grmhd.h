@@ -4,10 +4,12 @@
  * The library advances the 3+1 general-relativistic MHD equations on one
  * block of a 3-D finite-difference grid, the method the paper states in its
  * Introduction (3-D finite differences, high-order reconstruction, after the
- * ECHO scheme): MP5 reconstruction, HLL fluxes, a sixth-order staggered
- * finite-difference flux derivative with metric source terms, an upwind
- * constrained-transport edge field (div B constant to round-off), SSP-RK3
- * stages and a per-zone Newton conservative-to-primitive inversion.  The
+ * ECHO scheme): MP5 reconstruction (WENO5, PLM-MC and MP7 selectable), HLL
+ * fluxes, a sixth-order (or fourth-order) staggered finite-difference flux
+ * derivative with metric source terms, an upwind constrained-transport edge
+ * field (div B constant to round-off), SSP-RK3 stages with an optional
+ * lower-order fallback at zones the high-order update leaves unphysical, and
+ * a per-zone Newton conservative-to-primitive inversion.  The
  * paper's multi-node domain decomposition reduces here to one block whose
  * ghost zones are filled on the device.
  *
