@@ -30,6 +30,15 @@
  *    u^i = W v^i contravariant, B undensitised, at cell centres);
  *    cons = 8 fields (sqrt(gamma) D, sqrt(gamma) S_1..3, sqrt(gamma) tau at
  *    centres; sqrt(gamma) B^1, B^2, B^3 on the x^1, x^2, x^3 faces).
+ *  - Face fields at non-periodic boundaries: the field normal to an outflow
+ *    or polar-axis boundary is state (not filled from the owned faces) at
+ *    the ghost faces the staggered derivative of an interior cell reads,
+ *    stored -3 .. -1 and n .. n+1 (-2 .. -1 and n with deriv_order 4), the
+ *    polar axis faces among them: the step evolves them with the induction
+ *    equation like the owned faces, so the discrete div B of the cells
+ *    beside the boundary keeps its value; grmhd_curl_potential sets them, a
+ *    caller binding its own face fields supplies them.  The edge field on a
+ *    polar axis is 0.  Every other ghost is filled by the boundary rule.
  *  - Streams: every call enqueues work on the stream given at init (a
  *    hipStream_t, 0 = null stream) and returns at once.  Only calls with a
  *    host out-pointer (dt_used, n_fail, diagnostics, loss) synchronise it.
@@ -182,7 +191,8 @@ int grmhd_bind_fields(grmhd_grid* h, double* prim, double* cons, void* scratch,
 int grmhd_set_metric(grmhd_grid* h, int kind, const double* host_tables, size_t n_doubles);
 
 /* Face fields from an edge vector potential: B^n = D_{n+1} A_{n+2} - D_{n+2} A_{n+1}
- * at owned faces, then the face ghost fill.  A1, A2, A3: device arrays with
+ * at owned faces and at the evolved ghost faces of non-periodic boundaries,
+ * then the face ghost fill.  A1, A2, A3: device arrays with
  * the single-field layout (edge_doubles each), ghosts included. */
 int grmhd_curl_potential(grmhd_grid* h, const double* A1, const double* A2, const double* A3);
 

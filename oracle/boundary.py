@@ -7,15 +7,20 @@ the full extent of the other two directions, so edges and corners are filled.
 
   periodic : ghost index i <- i mod n (cells and faces alike; owned faces are
              the stored indices 0..n-1)
-  outflow  : cells copy the nearest interior cell; faces normal to the
-             boundary copy the nearest owned face (index 0 or n-1); at the
-             upper x^1 boundary u^1 <- max(u^1, 0) (no inflow)
+  outflow  : cells copy the nearest interior cell; at the upper x^1 boundary
+             u^1 <- max(u^1, 0) (no inflow)
   axis     : polar axis in x^2 = theta (only with periodic x^3 = phi):
              ghost cell row -1-m <- row m, ghost row n+m <- row n-1-m, taken at
-             the x^3 index shifted by n3/2; faces normal to x^2: the axis faces
-             (stored -1 and n-1) are 0, ghost face -2-m <- face m and
-             n+m <- n-2-m; the components u^2, u^3, B^2, B^3 and the face
-             fields of x^2 and x^3 change sign.
+             the x^3 index shifted by n3/2; the components u^2, u^3, B^2, B^3
+             and the face fields of x^2 and x^3 change sign.
+  Faces normal to an outflow or axis boundary: the ghost faces that the
+  staggered derivative of an interior cell reads, stored -flo .. -1 and
+  n .. n + flo - 2 (flo = 3 for the sixth order, 2 for the fourth), are not
+  filled: the scheme evolves them with the induction equation like the owned
+  faces (so the discrete div B of every interior cell keeps its value), and
+  the axis faces (stored -1 and n-1) with them.  Beyond those: outflow copies
+  the outermost evolved face; axis sets ghost face -2-m <- face m and
+  n+m <- n-2-m (half a turn away, sign changed).
 """
 import numpy as np
 
@@ -30,9 +35,10 @@ def _sl(axis, s):
     return tuple(out)
 
 
-def _fill_dir(q, name, grid, d, normal):
+def _fill_dir(q, name, grid, d, normal, flo=3):
     """Fill ghosts of array q along direction d.  normal: True if q is a face
-    field whose faces are normal to d."""
+    field whose faces are normal to d; flo: evolved ghost face layers below
+    the interior (flo - 1 above) of a non-periodic direction."""
     g = grid.ng
     n = grid.n[d]
     ax = AX[d]
@@ -62,11 +68,9 @@ def _fill_dir(q, name, grid, d, normal):
             out[g:g + n3] = rolled
             return sign * out
         if normal:
-            setv(-1, np.zeros_like(getv(-1)))
-            setv(n - 1, np.zeros_like(getv(n - 1)))
-            for m in range(0, g - 1):
+            for m in range(flo - 1, g - 1):
                 setv(-2 - m, shifted(m))
-            for m in range(0, g):
+            for m in range(flo - 1, g):
                 setv(n + m, shifted(n - 2 - m))
         else:
             for m in range(0, g):
@@ -75,14 +79,16 @@ def _fill_dir(q, name, grid, d, normal):
         return
     # outflow (each side may be outflow independently of the other)
     if lo_bc == OUTFLOW:
-        src = getv(0)
-        for m in range(-g, 0):
+        first = -flo if normal else 0
+        src = getv(first)
+        for m in range(-g, min(first, 0)):
             setv(m, src)
     if hi_bc == OUTFLOW:
-        src = getv(n - 1)
+        last = n + flo - 2 if normal else n - 1
+        src = getv(last)
         if d == 0 and name == "u1":
             src = np.maximum(src, 0.0)
-        for m in range(n, n + g):
+        for m in range(last + 1, n + g):
             setv(m, src)
 
 
@@ -93,8 +99,8 @@ def fill_centred(P, grid, names=None):
             _fill_dir(P[name], name, grid, d, normal=False)
 
 
-def fill_faces(U, grid):
+def fill_faces(U, grid, flo=3):
     for nd in range(3):
         name = "Bf%d" % (nd + 1)
         for d in range(3):
-            _fill_dir(U[name], name, grid, d, normal=(d == nd))
+            _fill_dir(U[name], name, grid, d, normal=(d == nd), flo=flo)

@@ -21,8 +21,15 @@ after ECHO.  One right-hand-side evaluation, in order:
        - E_e = sum_ab w^d_a w^c_b E^{ab} + a_d^+ a_d^-/(a_d^+ + a_d^-) (B^{c,R} - B^{c,L})
                - a_c^+ a_c^-/(a_c^+ + a_c^-) (B^{d,R} - B^{d,L}),
          w_L = a^+/(a^+ + a^-), w_R = a^-/(a^+ + a^-) (1/2 and 0 if a^+ + a^- < 1e-300);
+     On a polar-axis boundary the edges on the axis (families 1 and 3,
+     stored x^2 index -1 and n2-1) are 0: the covariant field there carries
+     sqrt(gamma) = 0.
   4. L[hydro] = -sum_d D_d F_d + s (metric sources) at interior cells;
-     L[B^n] = -D_{n+1} E_{n+2} + D_{n+2} E_{n+1} at owned faces (indices mod 3).
+     L[B^n] = -D_{n+1} E_{n+2} + D_{n+2} E_{n+1} at owned faces (indices mod 3)
+     and, normal to a non-periodic boundary, at the ghost faces the
+     staggered derivative of an interior cell reads (Solver.face_region), so
+     that the discrete div B of every interior cell keeps its value; the
+     boundary rule fills only the faces beyond those.
 SSP-RK3 (Shu & Osher 1988): U^(s) = a_s U^n + b_s (U^(s-1) + dt L(U^(s-1)))
 with (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3), every stage followed by the
 ghost fill of the face fields and the inversion (with floors) at interior
@@ -51,7 +58,7 @@ from .recon import face_states, METHODS as RECON_METHODS, NG_OF
 from .physics import state, flux, cons, speeds, prim2cons
 from .hll import hll_speeds, hll_flux
 from .c2p import newton, warm_guess
-from .boundary import fill_centred, fill_faces
+from .boundary import fill_centred, fill_faces, AXIS as AXIS_BC
 from .sources import sources
 
 PRIM = ("rho", "u1", "u2", "u3", "p", "B1", "B2", "B3")
@@ -179,23 +186,46 @@ class Solver:
 
     # ---------------------------------------------------------- initial data
     def curl_potential(self, A):
-        """B_face = curl_D A at owned faces: B^n = D_{n+1} A_{n+2} - D_{n+2} A_{n+1}."""
+        """B_face = curl_D A at the evolved faces (face_region):
+        B^n = D_{n+1} A_{n+2} - D_{n+2} A_{n+1}."""
         g, gr = self.g, self.grid
         for nd in range(3):
             d1, d2 = (nd + 1) % 3, (nd + 2) % 3
             t1 = deriv(A["A%d" % (d2 + 1)], d1, 0, gr.n[d1], gr.dx[d1], g, self.order)
             t2 = deriv(A["A%d" % (d1 + 1)], d2, 0, gr.n[d2], gr.dx[d2], g, self.order)
-            t1 = _restrict_others(t1, d1, g, gr)
-            t2 = _restrict_others(t2, d2, g, gr)
             f = _nan(gr.shape)
-            self.set_interior(f, t1 - t2)
+            f[self.face_region(nd)] = (self._restrict_face(t1, d1, nd)
+                                       - self._restrict_face(t2, d2, nd))
             self.U["Bf%d" % (nd + 1)] = f
-        fill_faces(self.U, gr)
+        fill_faces(self.U, gr, self.flo)
+
+    def face_region(self, nd):
+        """Slices (of a full array) of the faces of the face field normal to
+        nd that the scheme evolves: interior in the other two directions;
+        along nd the owned faces 0 .. n-1, and where nd is not periodic also
+        the ghost faces -flo .. -1 and n .. n + flo - 2 that the staggered
+        derivative of an interior cell reads."""
+        g, gr = self.g, self.grid
+        sl = [slice(g, g + gr.n[t]) for t in (2, 1, 0)]
+        if gr.bc[2 * nd] != 0:
+            sl[fd.AXIS[nd]] = slice(g - self.flo, g + gr.n[nd] + self.flo - 1)
+        return tuple(sl)
+
+    def _restrict_face(self, a, d, nd):
+        """Restrict a derivative along d (interior along d, full along the
+        others) to face_region(nd)."""
+        g, gr = self.g, self.grid
+        reg = self.face_region(nd)
+        sl = [slice(None)] * 3
+        for t in range(3):
+            if t != d:
+                sl[fd.AXIS[t]] = reg[fd.AXIS[t]]
+        return a[tuple(sl)]
 
     def set_face_fields(self, data):
         for k in FACE:
             self.U[k] = np.array(data["B%sf" % k[-1]], dtype=np.float64)
-        fill_faces(self.U, self.grid)
+        fill_faces(self.U, self.grid, self.flo)
 
     def centred_b(self):
         """B^i = I_i(B_face^i) / sqrt(gamma) at interior cells."""
@@ -339,6 +369,12 @@ class Solver:
         sl[fd.AXIS[d]] = slice(lo + g, hd + g)
         sl[fd.AXIS[c]] = slice(lo + g, hc + g)
         out[tuple(sl)] = np.asarray(ee, dtype=np.float64)
+        if gr.bc[2] == AXIS_BC and e != 1:
+            # edges on the polar axis (x^2 offset, stored -1 and n2-1): the
+            # covariant field there carries sqrt(gamma) = 0
+            n2 = gr.n[1]
+            out[:, g - 1, :] = 0.0
+            out[:, g + n2 - 1, :] = 0.0
         return out
 
     def rhs_parts(self):
@@ -358,19 +394,31 @@ class Solver:
                       self.centre_metric(), Metric.interior(self.met.der, g), self.gam)
         for name in HYDRO:
             lh[name] = lh[name] + src[name]
+        # the face fields over face_region (the owned faces and, normal to a
+        # non-periodic boundary, the ghost faces the divergence reads)
         lf = {}
         for nd in range(3):
             d1, d2 = (nd + 1) % 3, (nd + 2) % 3
-            t1 = _restrict_others(deriv(edges[d2], d1, 0, gr.n[d1], gr.dx[d1], g, self.order), d1, g, gr)
-            t2 = _restrict_others(deriv(edges[d1], d2, 0, gr.n[d2], gr.dx[d2], g, self.order), d2, g, gr)
+            t1 = self._restrict_face(deriv(edges[d2], d1, 0, gr.n[d1], gr.dx[d1], g, self.order), d1, nd)
+            t2 = self._restrict_face(deriv(edges[d1], d2, 0, gr.n[d2], gr.dx[d2], g, self.order), d2, nd)
             lf["Bf%d" % (nd + 1)] = -t1 + t2
         return lh, lf, fdat, edges
+
+    def owned(self, lf, nd):
+        """The owned faces (stored 0 .. n-1 along nd) of a face_region array."""
+        gr = self.grid
+        if gr.bc[2 * nd] == 0:
+            return lf
+        sl = [slice(None)] * 3
+        sl[fd.AXIS[nd]] = slice(self.flo, self.flo + gr.n[nd])
+        return lf[tuple(sl)]
 
     def rhs(self):
         fill_centred(self.P, self.grid)
         lh, lf, _, _ = self.rhs_parts()
         out = dict(lh)
-        out.update(lf)
+        for nd, name in enumerate(FACE):
+            out[name] = self.owned(lf[name], nd)
         return out
 
     # ---------------------------------------------------------- inversion
@@ -537,10 +585,10 @@ class Solver:
             new = self.apply_fallback(new, fdat, b, dt)
         for name in HYDRO:
             self.set_interior(self.U[name], new[name])
-        for name in FACE:
-            cur = self.interior(self.U[name])
-            self.set_interior(self.U[name], rk_combine(self.interior(un[name]), cur, lf[name], a, b, dt))
-        fill_faces(self.U, self.grid)
+        for nd, name in enumerate(FACE):
+            reg = self.face_region(nd)
+            self.U[name][reg] = rk_combine(un[name][reg], self.U[name][reg], lf[name], a, b, dt)
+        fill_faces(self.U, self.grid, self.flo)
         return self.cons2prim()
 
     def rk_step(self, dt=None):

@@ -251,6 +251,7 @@ void make_layout(const grmhd_grid_desc& d, grmhd_layout& L, Geom& G) {
   G.gam = d.gamma_ad;
   G.dorder = d.deriv_order == 4 ? 4 : 6;
   G.ng = d.ng;
+  G.axis2 = d.bc[2] == GRMHD_BC_AXIS ? 1 : 0;
   G.tab_n1 = (int)L.dims[0];
   G.tab_plane = L.dims[0] * L.dims[1];
 }
@@ -404,7 +405,10 @@ int grmhd_curl_potential(grmhd_grid* h, const double* A1, const double* A2, cons
   if (rc) return rc;
   if (!A1 || !A2 || !A3) return fail(GRMHD_EINVAL, "NULL potential");
   h->next_dt_valid = false;
-  h->timed(15, [&] { launch_curl(h->G, A1, A2, A3, h->cons, h->stream); });
+  h->timed(15, [&] {
+    launch_curl(h->G, A1, A2, A3, h->cons, h->stream);
+    launch_ghost_normal_curl(h->G, h->bc, A1, A2, A3, h->cons, h->stream);
+  });
   h->timed(8, [&] { launch_bc_faces(h->G, h->bc, h->cons, h->stream); });
   return hip_check("curl_potential");
 }
@@ -553,6 +557,13 @@ static void step_stages(grmhd_grid* h, double dt) {
                       UPD_INDUCTION);
       });
     }
+    // normal to a non-periodic boundary the ghost faces the divergence of
+    // the cells beside it reads evolve with the induction equation too
+    if (!img)
+      h->timed(7, [&] {
+        launch_ghost_normal_update(h->G, h->bc, fp32, s == 0 ? Un : S, s == 0 ? S : Un, h->edges(), A[s], B[s],
+                                   dt, dt_src, s + 1, h->stream);
+      });
     // dt and time are recorded once the last update has consumed d_dt[2]
     if (s == 2) h->timed(12, [&] { launch_advance(h->d_dt, dt_src, dt, h->stream); });
     if (!img) h->timed(8, [&] { launch_bc_faces(h->G, h->bc, next, h->stream); });

@@ -56,6 +56,7 @@ struct Geom {
   int dorder;          // order of the staggered derivative and interpolation (6 or 4)
   int ng;              // ghost layers (5, or 6 for the eight-cell MP7 stencil)
   int tab_n1;          // metric table row length (n1 + 2 ng)
+  int axis2;           // x^2 is a polar-axis direction (edges on the axis are 0)
   long tab_plane;      // metric table component stride
   __host__ __device__ long idx(int i, int j, int k) const {
     return off + (long)k * plane + (long)j * pitch + i;

@@ -92,6 +92,17 @@ void launch_fallback(const Geom& G, bool flat, bool fp32, const BCSpec& bc, cons
                      const unsigned char* flags, const int* list, const int* count, double* delta,
                      double b, double dt_host, const double* d_dt, unsigned long long* run_acc,
                      hipStream_t s);
+// The face field normal to each non-periodic direction at the ghost faces
+// the staggered derivative of an interior cell reads (-flo .. -1 and
+// n .. n + flo - 2, interior in the other directions): the RK stage of the
+// induction equation into x / y as launch_update (mode 0) does at the owned
+// faces, after it; or the curl of the edge potentials into cons (after
+// launch_curl).  The face ghost fill leaves these faces alone.
+void launch_ghost_normal_update(const Geom& G, const BCSpec& bc, bool fp32, double* x, double* y,
+                                const double* edges, double a, double b, double dt_host, const double* d_dt,
+                                int stage, hipStream_t s);
+void launch_ghost_normal_curl(const Geom& G, const BCSpec& bc, const double* a1, const double* a2,
+                              const double* a3, double* cons, hipStream_t s);
 void launch_advance(double* d_dt, const double* src, double dt_host, hipStream_t s);
 // Inversion of all interior zones; per-block counters into partials[0, nblk),
 // CFL partials (nullable) into cfl_partials[0, nblk).  list != nullptr: defer

@@ -253,6 +253,15 @@ __global__ __launch_bounds__(SX * SF) void k_sweep_lds(Geom G, const double* __r
   for (int q6 = 0; q6 < 6; ++q6) __builtin_nontemporal_store(cd[q6], &ctd[(long)q6 * G.field + c]);
 }
 
+// Edges of families 1 and 3 (E = 0, 2: offset in x^2) on a polar axis
+// (stored x^2 index -1 or n2 - 1): the covariant field there carries
+// sqrt(gamma) = 0, so they are 0 (which also keeps the axis faces' field).
+template <int E>
+__device__ __forceinline__ bool on_axis(const Geom& G, int j) {
+  if constexpr (E == 1) return false;
+  else return G.axis2 && (j == -1 || j == G.n[1] - 1);
+}
+
 // Edge field of family E.  ctd_d / ctd_c: per-face data of the d and c sweeps
 // (stored in the arithmetic type T, as the edge field itself).
 template <int E, class MET, typename T, int RC>
@@ -302,7 +311,7 @@ __global__ __launch_bounds__(256) void k_edge(Geom G, const double* __restrict__
                             ctd_d[5 * G.field + b], ctd_d[5 * G.field + b + sc],
                             ctd_c[4 * G.field + b], ctd_c[4 * G.field + b + sd],
                             ctd_c[5 * G.field + b], ctd_c[5 * G.field + b + sd], m);
-  edge[b] = ee;
+  edge[b] = on_axis<E>(G, ii[1]) ? T(0) : ee;
 }
 
 // LDS-staged edge field for families E = 0, 2, whose five d-face inputs are
@@ -395,7 +404,7 @@ __global__ __launch_bounds__(SX * SF) void k_edge_lds(Geom G, const double* __re
                                   ctd_d[5 * G.field + b], ctd_d[5 * G.field + b + sc],
                                   ctd_c[4 * G.field + b], ctd_c[4 * G.field + b + sd],
                                   ctd_c[5 * G.field + b], ctd_c[5 * G.field + b + sd], m);
-  edge[b] = ee;
+  edge[b] = on_axis<E>(G, ii[1]) ? T(0) : ee;
 }
 
 // ------------------------------------------------------------------ launchers

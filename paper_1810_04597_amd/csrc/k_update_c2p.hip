@@ -567,7 +567,7 @@ __global__ __launch_bounds__(256) void k_curl(Geom G, const double* __restrict__
 struct GhostSrc {
   int i, j, k;
   double sign;
-  bool zero, clamp_u1;
+  bool clamp_u1;
 };
 
 __device__ __forceinline__ int wrap(int m, int n) {
@@ -575,34 +575,45 @@ __device__ __forceinline__ int wrap(int m, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Outflow source index along one direction of n: cells and tangential faces
+// copy the nearest interior index; the face field normal to the direction
+// keeps its evolved ghost faces -flo .. -1 and n .. n + flo - 2 and copies
+// the outermost of them beyond.
+__device__ __forceinline__ int outflow_src(int m, int n, bool normal, int flo) {
+  if (!normal) return m < 0 ? 0 : n - 1;
+  return m < 0 ? max(m, -flo) : min(m, n + flo - 2);
+}
+
 __device__ __forceinline__ GhostSrc ghost_src(const Geom& G, const BCSpec& bc, int i, int j, int k,
                                               int normal, bool flip) {
-  GhostSrc s{i, j, k, 1.0, false, false};
+  GhostSrc s{i, j, k, 1.0, false};
   const int n1 = G.n[0], n2 = G.n[1], n3 = G.n[2];
+  const int flo = -G.face_lo();
   // x^1
-  if (i < 0) s.i = bc.bc[0] == 0 ? wrap(i, n1) : 0;
+  if (i < 0) s.i = bc.bc[0] == 0 ? wrap(i, n1) : outflow_src(i, n1, normal == 0, flo);
   else if (i >= n1) {
-    s.i = bc.bc[1] == 0 ? wrap(i, n1) : n1 - 1;
+    s.i = bc.bc[1] == 0 ? wrap(i, n1) : outflow_src(i, n1, normal == 0, flo);
     s.clamp_u1 = bc.bc[1] == 1;
   }
   // x^2
   bool shift = false;
   if (bc.bc[2] == 2) {
     if (normal == 1) {
-      if (j == -1 || j == n2 - 1) s.zero = true;
-      else if (j <= -2) { s.j = -j - 2; shift = true; }
-      else if (j >= n2) { s.j = 2 * n2 - j - 2; shift = true; }
+      // evolved: the ghost faces -flo .. -1 and n2 .. n2 + flo - 2 (with the
+      // axis faces -1 and n2 - 1); beyond, minus the face half a turn away
+      if (j < -flo) { s.j = -j - 2; shift = true; }
+      else if (j > n2 + flo - 2) { s.j = 2 * n2 - j - 2; shift = true; }
     } else {
       if (j < 0) { s.j = -1 - j; shift = true; }
       else if (j >= n2) { s.j = 2 * n2 - 1 - j; shift = true; }
     }
   } else {
-    if (j < 0) s.j = bc.bc[2] == 0 ? wrap(j, n2) : 0;
-    else if (j >= n2) s.j = bc.bc[3] == 0 ? wrap(j, n2) : n2 - 1;
+    if (j < 0) s.j = bc.bc[2] == 0 ? wrap(j, n2) : outflow_src(j, n2, normal == 1, flo);
+    else if (j >= n2) s.j = bc.bc[3] == 0 ? wrap(j, n2) : outflow_src(j, n2, normal == 1, flo);
   }
   // x^3
-  if (k < 0) s.k = bc.bc[4] == 0 ? wrap(k, n3) : 0;
-  else if (k >= n3) s.k = bc.bc[5] == 0 ? wrap(k, n3) : n3 - 1;
+  if (k < 0) s.k = bc.bc[4] == 0 ? wrap(k, n3) : outflow_src(k, n3, normal == 2, flo);
+  else if (k >= n3) s.k = bc.bc[5] == 0 ? wrap(k, n3) : outflow_src(k, n3, normal == 2, flo);
   if (shift) {
     s.k = wrap(s.k + n3 / 2, n3);
     if (flip) s.sign = -1.0;
@@ -611,16 +622,12 @@ __device__ __forceinline__ GhostSrc ghost_src(const Geom& G, const BCSpec& bc, i
 }
 
 // Enumerates exactly the ghost elements: slabs of ghost x^3 planes, then
-// ghost x^2 rows of interior planes, then ghost x^1 cells of interior rows;
-// with an axis boundary, the axis faces j = n2-1 of interior cells follow
-// (face fields only).
-__device__ __forceinline__ bool ghost_index(const Geom& G, long t, bool axis_row, int& i, int& j,
-                                            int& k) {
+// ghost x^2 rows of interior planes, then ghost x^1 cells of interior rows.
+__device__ __forceinline__ bool ghost_index(const Geom& G, long t, int& i, int& j, int& k) {
   const long d0 = G.dims[0], d1 = G.dims[1];
   const long NA = 2L * G.ng * d1 * d0;
   const long NB = (long)G.n[2] * 2 * G.ng * d0;
   const long NC = (long)G.n[2] * G.n[1] * 2 * G.ng;
-  const long ND = axis_row ? (long)G.n[2] * G.n[0] : 0;
   if (t < NA) {
     const int kl = (int)(t / (d1 * d0));
     const long r = t % (d1 * d0);
@@ -647,27 +654,19 @@ __device__ __forceinline__ bool ghost_index(const Geom& G, long t, bool axis_row
     i = il < G.ng ? il - G.ng : G.n[0] + il - G.ng;
     return true;
   }
-  t -= NC;
-  if (t < ND) {
-    k = (int)(t / G.n[0]);
-    i = (int)(t % G.n[0]);
-    j = G.n[1] - 1;
-    return true;
-  }
   return false;
 }
 
-__device__ __forceinline__ long ghost_total(const Geom& G, bool axis_row) {
+__device__ __forceinline__ long ghost_total(const Geom& G) {
   const long d0 = G.dims[0], d1 = G.dims[1];
-  return 2L * G.ng * d1 * d0 + (long)G.n[2] * 2 * G.ng * d0 + (long)G.n[2] * G.n[1] * 2 * G.ng +
-         (axis_row ? (long)G.n[2] * G.n[0] : 0);
+  return 2L * G.ng * d1 * d0 + (long)G.n[2] * 2 * G.ng * d0 + (long)G.n[2] * G.n[1] * 2 * G.ng;
 }
 
 __global__ __launch_bounds__(256) void k_bc_centred(Geom G, BCSpec bc, double* __restrict__ prim,
                                                     int nfields) {
   const long t = flat_thread();
   int i, j, k;
-  if (t >= ghost_total(G, false) || !ghost_index(G, t, false, i, j, k)) return;
+  if (t >= ghost_total(G) || !ghost_index(G, t, i, j, k)) return;
   const long dst = G.idx(i, j, k);
   for (int f = 0; f < nfields; ++f) {
     const bool flip = (f == P_U2 || f == P_U3 || f == P_B2 || f == P_B3);
@@ -678,19 +677,18 @@ __global__ __launch_bounds__(256) void k_bc_centred(Geom G, BCSpec bc, double* _
   }
 }
 
+// Face ghost fill: every source is an owned face or an evolved ghost face
+// (normal to a non-periodic boundary), which this kernel does not write.
 __global__ __launch_bounds__(256) void k_bc_faces(Geom G, BCSpec bc, double* __restrict__ cons) {
   const long t = flat_thread();
-  const bool axis = bc.bc[2] == 2;
   int i, j, k;
-  if (t >= ghost_total(G, axis) || !ghost_index(G, t, axis, i, j, k)) return;
-  const bool inside = i >= 0 && i < G.n[0] && j >= 0 && j < G.n[1] && k >= 0 && k < G.n[2];
-  const bool axis_face = axis && (j == -1 || j == G.n[1] - 1);
+  if (t >= ghost_total(G) || !ghost_index(G, t, i, j, k)) return;
   const long dst = G.idx(i, j, k);
   for (int nd = 0; nd < 3; ++nd) {
-    if (inside && !(nd == 1 && axis_face)) continue;
     const GhostSrc s = ghost_src(G, bc, i, j, k, nd, nd != 0);
+    if (s.i == i && s.j == j && s.k == k) continue;   // an evolved ghost face
     double* f = cons + (long)(C_BF1 + nd) * G.field;
-    f[dst] = s.zero ? 0.0 : f[G.idx(s.i, s.j, s.k)] * s.sign;
+    f[dst] = f[G.idx(s.i, s.j, s.k)] * s.sign;
   }
 }
 
@@ -785,18 +783,17 @@ __global__ __launch_bounds__(256) void k_diag_final(const double* __restrict__ p
 // ------------------------------------------------------------------ launchers
 unsigned zone_blocks(const Geom& G) { return nblk((long)G.n[0] * G.n[1] * G.n[2]); }
 
-static long ghost_count(const Geom& G, bool axis_row) {
+static long ghost_count(const Geom& G) {
   const long d0 = G.dims[0], d1 = G.dims[1];
-  return 2L * G.ng * d1 * d0 + (long)G.n[2] * 2 * G.ng * d0 + (long)G.n[2] * G.n[1] * 2 * G.ng +
-         (axis_row ? (long)G.n[2] * G.n[0] : 0);
+  return 2L * G.ng * d1 * d0 + (long)G.n[2] * 2 * G.ng * d0 + (long)G.n[2] * G.n[1] * 2 * G.ng;
 }
 
 void launch_bc_centred(const Geom& G, const BCSpec& bc, double* prim, int nfields, hipStream_t s) {
-  hipLaunchKernelGGL(k_bc_centred, dim3(nblk(ghost_count(G, false))), dim3(256), 0, s, G, bc, prim, nfields);
+  hipLaunchKernelGGL(k_bc_centred, dim3(nblk(ghost_count(G))), dim3(256), 0, s, G, bc, prim, nfields);
 }
 
 void launch_bc_faces(const Geom& G, const BCSpec& bc, double* cons, hipStream_t s) {
-  hipLaunchKernelGGL(k_bc_faces, dim3(nblk(ghost_count(G, bc.bc[2] == 2))), dim3(256), 0, s, G, bc, cons);
+  hipLaunchKernelGGL(k_bc_faces, dim3(nblk(ghost_count(G))), dim3(256), 0, s, G, bc, cons);
 }
 
 template <int DO, typename FS, int PARTS>
@@ -875,6 +872,97 @@ void launch_update(const Geom& G, bool flat, bool fp32, int mode, const double* 
   else
     launch_update_s<double>(G, flat, mode, prim, x, y, flux, edges, tab, a, b, dt_host, d_dt, out, stage, s,
                             img, parts, tflags, tlist, tcount);
+}
+
+// ------------------------------------------------------------------ evolved ghost faces
+// The face field normal to a non-periodic direction nd at the ghost faces
+// that the staggered derivative of an interior cell reads: stored
+// -flo .. -1 and n .. n + flo - 2 along nd (flo = 3, or 2 for the
+// fourth-order derivative), interior in the other two directions.  One
+// thread per face, the layer index fastest.  POT: the curl of the edge
+// potentials (initial data); otherwise the RK stage of the induction
+// equation with the stage's edge fields, as the update does at the owned
+// faces, so the discrete div B of the cells next to the boundary keeps its
+// value.
+template <int DO, typename FS, bool POT>
+__global__ __launch_bounds__(256) void k_ghost_normal(Geom G, int nd, double* __restrict__ x,
+                                                      double* __restrict__ y, const FS* __restrict__ edges,
+                                                      const double* __restrict__ a1,
+                                                      const double* __restrict__ a2,
+                                                      const double* __restrict__ a3, double a, double b,
+                                                      double dt_host, const double* __restrict__ d_dt,
+                                                      int stage) {
+  const int flo = -G.face_lo(), nl = 2 * flo - 1;
+  const int d1 = (nd + 1) % 3, d2 = (nd + 2) % 3;
+  const long t = flat_thread();
+  if (t >= (long)nl * G.n[d1] * G.n[d2]) return;
+  const int l = (int)(t % nl);
+  const long r = t / nl;
+  int ii[3];
+  ii[nd] = l < flo ? l - flo : G.n[nd] + (l - flo);
+  ii[d1] = (int)(r % G.n[d1]);
+  ii[d2] = (int)(r / G.n[d1]);
+  const long c = G.idx(ii[0], ii[1], ii[2]);
+  const long s1 = G.stride(d1), s2 = G.stride(d2);
+  const long o = (long)(C_BF1 + nd) * G.field + c;
+  double f[6];
+  if constexpr (POT) {
+    const double* A[3] = {a1, a2, a3};
+    for (int s = 0; s < 6; ++s) f[s] = A[d2][c + (s - 3) * s1];
+    const double t1 = fd_deriv_rt(f, 1.0 / G.dx[d1], G.dorder);
+    for (int s = 0; s < 6; ++s) f[s] = A[d1][c + (s - 3) * s2];
+    const double t2 = fd_deriv_rt(f, 1.0 / G.dx[d2], G.dorder);
+    x[o] = t1 - t2;
+  } else {
+    const FS* e2 = edges + (long)d2 * G.field + c;
+    const FS* e1 = edges + (long)d1 * G.field + c;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) f[s] = e2[(s - 3) * s1];
+    const double t1 = fd_deriv_o<DO>(f, 1.0 / G.dx[d1]);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) f[s] = e1[(s - 3) * s2];
+    const double t2 = fd_deriv_o<DO>(f, 1.0 / G.dx[d2]);
+    const double dt = dt_host > 0.0 ? dt_host : *d_dt;
+    rk_store_rt(x, y, o, a, b, dt, -t1 + t2, stage);
+  }
+}
+
+static unsigned ghost_normal_blocks(const Geom& G, int nd) {
+  const int flo = -G.face_lo();
+  return nblk((long)(2 * flo - 1) * G.n[(nd + 1) % 3] * G.n[(nd + 2) % 3]);
+}
+
+template <typename FS>
+static void launch_ghost_normal_s(const Geom& G, int nd, double* x, double* y, const FS* edges, double a,
+                                  double b, double dt_host, const double* d_dt, int stage, hipStream_t s) {
+  if (G.dorder == 4)
+    hipLaunchKernelGGL((k_ghost_normal<4, FS, false>), dim3(ghost_normal_blocks(G, nd)), dim3(256), 0, s, G, nd,
+                       x, y, edges, nullptr, nullptr, nullptr, a, b, dt_host, d_dt, stage);
+  else
+    hipLaunchKernelGGL((k_ghost_normal<6, FS, false>), dim3(ghost_normal_blocks(G, nd)), dim3(256), 0, s, G, nd,
+                       x, y, edges, nullptr, nullptr, nullptr, a, b, dt_host, d_dt, stage);
+}
+
+void launch_ghost_normal_update(const Geom& G, const BCSpec& bc, bool fp32, double* x, double* y,
+                                const double* edges, double a, double b, double dt_host, const double* d_dt,
+                                int stage, hipStream_t s) {
+  for (int nd = 0; nd < 3; ++nd) {
+    if (bc.bc[2 * nd] == 0) continue;   // periodic: the ghosts are images of owned faces
+    if (fp32)
+      launch_ghost_normal_s<float>(G, nd, x, y, reinterpret_cast<const float*>(edges), a, b, dt_host, d_dt,
+                                   stage, s);
+    else
+      launch_ghost_normal_s<double>(G, nd, x, y, edges, a, b, dt_host, d_dt, stage, s);
+  }
+}
+
+void launch_ghost_normal_curl(const Geom& G, const BCSpec& bc, const double* a1, const double* a2,
+                              const double* a3, double* cons, hipStream_t s) {
+  for (int nd = 0; nd < 3; ++nd) {
+    if (bc.bc[2 * nd] == 0) continue;
+    hipLaunchKernelGGL((k_ghost_normal<6, double, true>), dim3(ghost_normal_blocks(G, nd)), dim3(256), 0, s, G,
+                       nd, cons, nullptr, nullptr, a1, a2, a3, 0.0, 0.0, 0.0, nullptr, 0);
+  }
 }
 
 // d_dt[0]: dt of the last step, d_dt[1]: time; src: where the device dt was read

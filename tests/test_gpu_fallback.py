@@ -4,8 +4,8 @@ with the oracle's Solver(fallback=True), through the C ABI.
   * the Kerr-Schild torus (48 x 24 x 24) at its CFL step, where the
     high-order update leaves unphysical states in the first stage: the same
     troubled zones on both sides, every zone and field within 1e-10 of the
-    oracle, no failed inversion (WENO5, MP5; sixth- and fourth-order
-    derivatives);
+    oracle, no failed inversion (WENO5, MP5, MP7 on six ghost layers, PLM;
+    sixth- and fourth-order derivatives, the latter also on four layers);
   * the blast (pressure jump 3e4, unmagnetised) on a flat periodic box
     (the x^3-marching update with its flags; 16^3 writes the ghost images in
     the update, 16 x 16 x 8 fills ghosts separately): the same troubled
@@ -47,13 +47,14 @@ def _compare(s, G, tol):
 
 
 @gpu
-@pytest.mark.parametrize("recon,order", [("weno5", 6), ("mp5", 6), ("weno5", 4)])
-def test_torus_cfl_step_matches_oracle(recon, order):
+@pytest.mark.parametrize("recon,order,ng", [("weno5", 6, 5), ("mp5", 6, 5), ("weno5", 4, 5), ("mp7", 6, 6),
+                                            ("plm", 6, 5), ("mp5", 4, 4)])
+def test_torus_cfl_step_matches_oracle(recon, order, ng):
     _torch()
     from workloads.torus import torus
     from oracle.scheme import Solver
     from paper_1810_04597_amd.grid import Grid
-    g, d, tab = torus(48, 24, 24)
+    g, d, tab = torus(48, 24, 24, ng=ng)
     s = Solver(g, tab, recon=recon, deriv_order=order, fallback=True)
     s.curl_potential(d)
     s.set_primitives(d)

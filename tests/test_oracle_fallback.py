@@ -12,8 +12,8 @@
     takes its share);
   * untroubled zones next to no troubled zone are untouched, and on smooth
     data nothing is troubled (the option then changes nothing);
-  * on the 48 x 24 x 24 torus at its CFL step, where WENO5 and MP5 leave
-    failed inversions, the fallback leaves none; the same for the
+  * on the 48 x 24 x 24 torus at its CFL step, where WENO5, MP5, MP7 and PLM
+    leave failed inversions, the fallback leaves none; the same for the
     unmagnetised blast (pressure jump 3e4) on a 16 x 16 x 8 box;
   * translation invariance across the periodic boundaries: the blast
     centred on the box corner (its troubled zones on both sides of every
@@ -151,10 +151,10 @@ def test_smooth_data_has_no_troubled_zone_and_nothing_changes():
         assert np.array_equal(out[0].interior(out[0].U[k]), out[1].interior(out[1].U[k])), k
 
 
-@pytest.mark.parametrize("recon", ["weno5", "mp5"])
+@pytest.mark.parametrize("recon", ["weno5", "mp5", "mp7", "plm"])
 def test_fallback_removes_the_failed_inversions_on_the_coarse_torus(recon):
     from workloads.torus import torus
-    g, d, tab = torus(48, 24, 24)
+    g, d, tab = torus(48, 24, 24, ng=6 if recon == "mp7" else 5)
     res = {}
     for fb in (False, True):
         s = Solver(g, tab, recon=recon, fallback=fb)

@@ -234,32 +234,35 @@ def test_failed_zone_keeps_primitives_without_floors():
 
 
 # ------------------------------------------------------------------ face ghost fill
-def test_face_ghost_fill_torus_rules():
+@pytest.mark.parametrize("flo", [3, 2])
+def test_face_ghost_fill_torus_rules(flo):
+    """Faces normal to the outflow (x^1) and axis (x^2) boundaries: the
+    ghost faces -flo .. -1 and n .. n + flo - 2 and the axis faces keep their
+    (evolved) values; the rules fill only the faces beyond, and every face
+    field's tangential ghosts."""
     n1, n2, n3 = 6, 6, 4
     gr = torus_grid(n1, n2, n3)
     g = gr.ng
     rng = np.random.default_rng(21)
     U = {f: rng.normal(size=gr.shape) for f in ("Bf1", "Bf2", "Bf3")}
     src = {f: v.copy() for f, v in U.items()}
-    fill_faces(U, gr)
+    fill_faces(U, gr, flo)
     A = lambda f, i, j, k: U[f][k + g, j + g, i + g]
     S = lambda f, i, j, k: src[f][k + g, j + g, i + g]
-    # interior elements are untouched (owned faces), except the x^2 face at
-    # the upper axis, stored at n2-1 inside the interior range, which is zero
+    # interior elements are untouched (owned faces, the upper axis face too)
     for f in U:
-        a, b = U[f][g:-g, g:-g, g:-g], src[f][g:-g, g:-g, g:-g].copy()
-        if f == "Bf2":
-            b[:, n2 - 1, :] = 0.0
-        assert np.array_equal(a, b), f
+        assert np.array_equal(U[f][g:-g, g:-g, g:-g], src[f][g:-g, g:-g, g:-g]), f
     for k in range(n3):
         kk = (k + n3 // 2) % n3
         for i in range(n1):
-            # x^2-normal faces: both axis faces are zero; ghost face -2-m is
-            # minus face m half a turn away, ghost face n2+m minus face n2-2-m
-            assert A("Bf2", i, -1, k) == 0.0 and A("Bf2", i, n2 - 1, k) == 0.0
-            for m in range(g - 1):
+            # x^2-normal faces: the evolved ghosts (the lower axis face among
+            # them) are untouched; beyond, ghost face -2-m is minus face m
+            # half a turn away, ghost face n2+m minus face n2-2-m
+            for j in list(range(-flo, 0)) + list(range(n2, n2 + flo - 1)):
+                assert A("Bf2", i, j, k) == S("Bf2", i, j, k), (i, j, k)
+            for m in range(flo - 1, g - 1):
                 assert A("Bf2", i, -2 - m, k) == -S("Bf2", i, m, kk)
-            for m in range(g):
+            for m in range(flo - 1, g):
                 assert A("Bf2", i, n2 + m, k) == -S("Bf2", i, n2 - 2 - m, kk)
             # tangential faces across the axis: rows mirror, x^3 faces flip
             for m in range(g):
@@ -268,14 +271,18 @@ def test_face_ghost_fill_torus_rules():
                 assert A("Bf1", i, -1 - m, k) == S("Bf1", i, m, kk)
                 assert A("Bf1", i, n2 + m, k) == S("Bf1", i, n2 - 1 - m, kk)
         for j in range(n2):
-            # outflow in x^1: every face field copies its nearest owned
-            # x^1 index, 0 below and n1-1 above
+            # outflow in x^1: the x^1-normal field keeps its evolved ghosts
+            # and copies the outermost of them beyond; the others copy their
+            # nearest owned x^1 index
             for m in range(1, g + 1):
-                for f in ("Bf1", "Bf2", "Bf3"):
-                    want_lo = 0.0 if (f == "Bf2" and j == n2 - 1) else S(f, 0, j, k)
-                    want_hi = 0.0 if (f == "Bf2" and j == n2 - 1) else S(f, n1 - 1, j, k)
-                    assert A(f, -m, j, k) == want_lo, (f, m, j, k)
-                    assert A(f, n1 - 1 + m, j, k) == want_hi, (f, m, j, k)
+                lo, hi = -m, n1 - 1 + m
+                want_lo = S("Bf1", lo, j, k) if m <= flo else S("Bf1", -flo, j, k)
+                want_hi = S("Bf1", hi, j, k) if hi <= n1 + flo - 2 else S("Bf1", n1 + flo - 2, j, k)
+                assert A("Bf1", lo, j, k) == want_lo, (m, j, k)
+                assert A("Bf1", hi, j, k) == want_hi, (m, j, k)
+                for f in ("Bf2", "Bf3"):
+                    assert A(f, lo, j, k) == S(f, 0, j, k), (f, m, j, k)
+                    assert A(f, hi, j, k) == S(f, n1 - 1, j, k), (f, m, j, k)
     # periodic x^3: every ghost plane is the interior plane k mod n3
     for f in U:
         for kg in list(range(-g, 0)) + list(range(n3, n3 + g)):
