@@ -55,3 +55,27 @@ def test_planted_divergence_keeps_its_value_next_to_every_boundary(order):
     # axis, so L = 0 there and only the RK weights' rounding remains
     for a, b in zip((s.U["Bf2"][:, ng - 1, ng:-ng], s.U["Bf2"][:, ng + g.n[1] - 1, ng:-ng]), axis0):
         assert np.max(np.abs(a - b)) <= 4e-16 * np.max(np.abs(b)), np.max(np.abs(a - b))
+
+
+def test_planted_divergence_on_an_outflow_box():
+    """Outflow in all three directions (the x^3 boundary included, which the
+    torus does not have)."""
+    from dataclasses import replace
+    from workloads import box
+    g0, d = box.turbulent_box(12)
+    g = replace(g0, bc=(1,) * 6)
+    s = Solver(g)
+    s.curl_potential(d)
+    s.set_primitives(d)
+    rng = np.random.default_rng(43)
+    for nd, k in enumerate(FACE):
+        reg = s.face_region(nd)
+        s.U[k][reg] += 1e-6 * rng.normal(size=s.U[k][reg].shape)
+    from oracle.boundary import fill_faces
+    fill_faces(s.U, g, s.flo)
+    s.prim2cons()
+    d0 = s.div_b().copy()
+    s.rk_step(2e-3)
+    err = np.max(np.abs(s.div_b() - d0))
+    assert np.max(np.abs(d0)) > 1e-6
+    assert err < 1e-9 * np.max(np.abs(d0)), (err, np.max(np.abs(d0)))
