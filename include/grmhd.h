@@ -131,7 +131,9 @@ typedef struct {
                               of the two cells, in both zones beside the face
                               (conservative).  Off: the step is unchanged bit for
                               bit.  On: the update runs as two launches around the
-                              fix, plus a flag byte per zone                      */
+                              fix (two launches that exit at once when no zone is
+                              troubled); library-owned: a flag byte and a list
+                              entry (int32) per zone                              */
 } grmhd_grid_desc;
 
 typedef struct {
