@@ -354,13 +354,14 @@ def split_report(args):
 
 def torus_report(args):
     """Plain FP64 GRMHD torus (Kerr-Schild a = 0.9, tabulated metric, floors,
-    device CFL step): zone-updates/s and per-kernel times."""
+    device CFL step): zone-updates/s and per-kernel times (--recon and
+    --fallback as for torus-long)."""
     import torch
     from workloads.torus import torus
     from paper_1810_04597_amd.grid import Grid
     n1, n2, n3 = (int(x) for x in args.torus.split(","))
     g, d, tab = torus(n1, n2, n3)
-    G = Grid(g, tables=tab)
+    G = Grid(g, tables=tab, recon=args.recon, fallback=args.fallback)
     G.curl_potential(d)
     G.set_primitives(d)
     for _ in range(args.warmup):
@@ -397,7 +398,9 @@ def torus_report(args):
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
-           "config": {"workload": "Kerr-Schild a=0.9 torus %dx%dx%d, r 1.2-50, 2%% noise, beta 100, floors, device CFL" % (n1, n2, n3)},
+           "config": {"workload": "Kerr-Schild a=0.9 torus %dx%dx%d, r 1.2-50, 2%% noise, beta 100, floors, device CFL, %s%s"
+                                  % (n1, n2, n3, args.recon.upper(),
+                                     " with the lower-order fallback" if args.fallback else "")},
            "kernels": {k: {"avg_ms": v[0] / v[1], "launches": v[1]} for k, v in prof.items()},
            "diag": {k: dg[k] for k in ("t", "max_divb", "rho_min", "rho_max", "w_max", "n_floor_rho",
                                        "n_floor_p", "n_wcap", "n_c2p_fail", "newton_iters_sum",
@@ -710,9 +713,9 @@ def main():
     ap.add_argument("--torus", default="384,192,192")
     ap.add_argument("--every", type=int, default=250, help="torus-long: steps between diagnostics")
     ap.add_argument("--recon", default="mp5", choices=["mp5", "weno5", "plm"],
-                    help="torus-long: reconstruction")
+                    help="torus, torus-long: reconstruction")
     ap.add_argument("--fallback", action="store_true",
-                    help="torus-long: the lower-order fallback at troubled zones")
+                    help="torus, torus-long: the lower-order fallback at troubled zones")
     ap.add_argument("--mri-rho-cut", type=float, default=1e-2,
                     help="torus-long: density above which a zone counts as torus body")
     args = ap.parse_args()
