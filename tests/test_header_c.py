@@ -72,7 +72,7 @@ def test_header_is_c_and_links():
     env["LD_LIBRARY_PATH"] = os.pathsep.join([LIBDIR, "/opt/rocm/lib", env.get("LD_LIBRARY_PATH", "")])
     out = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=60)
     assert out.returncode == 0, (out.returncode, out.stderr)
-    sizes, verdict = out.stdout.strip().splitlines()[:2]
+    sizes, refusal = out.stdout.strip().splitlines()[:2]
     assert sizes.split() == ["184", "280", "272"]
-    ok, null, msg = verdict.split(" ", 2)
+    ok, null, msg = refusal.split(" ", 2)
     assert ok == "1" and null == "1" and "ng must be 4, 5 or 6" in msg
