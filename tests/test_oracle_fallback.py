@@ -194,3 +194,21 @@ def test_blast_on_the_corner_is_the_centred_blast_rolled():
     for k in HYDRO:
         rolled = np.roll(sc.interior(sc.U[k]), (4, 8, 8), axis=(0, 1, 2))
         assert np.array_equal(sk.interior(sk.U[k]), rolled), k
+
+
+def test_first_order_flux_through_the_polar_axis_is_zero():
+    """The first-order flux at the x^2 faces on the polar axis (sqrt(gamma)
+    = 0 there: the faces have no area) is 0, as the high-order one is; the
+    faces next to them carry flux."""
+    from workloads.torus import torus
+    g, d, tab = torus(24, 12, 12)
+    s = Solver(g, tab, fallback=True)
+    s.curl_potential(d)
+    s.set_primitives(d)
+    from oracle.boundary import fill_centred
+    fill_centred(s.P, s.grid)
+    f1 = s.first_order_face_fluxes(1)             # faces -1/2 .. n2-1/2 (stored -1 .. n2-1)
+    n2 = g.n[1]
+    for name, v in f1.items():
+        assert np.all(v[:, 0, :] == 0.0) and np.all(v[:, n2, :] == 0.0), name
+    assert np.max(np.abs(f1["D"][:, 1:n2, :])) > 0.0
