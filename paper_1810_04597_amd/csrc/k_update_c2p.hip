@@ -527,15 +527,33 @@ __global__ __launch_bounds__(256) void k_cfl(Geom G, const double* __restrict__ 
   if (threadIdx.x == 0) partials[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
-__global__ __launch_bounds__(256) void k_dt_final(const double* __restrict__ partials, int nb, double cfl,
-                                                  double* __restrict__ d_dt) {
-  __shared__ double sh[4];
-  double v = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 256) v = fmax(v, partials[b]);
-  const double w = wave_max(v);
+// One workgroup of DT_THREADS reduces the partials; each thread keeps
+// DT_ACC independent maxima so that DT_ACC loads are in flight at once
+// (a max is exact, so the order does not matter).
+constexpr int DT_THREADS = 1024, DT_ACC = 8;
+
+__global__ __launch_bounds__(DT_THREADS) void k_dt_final(const double* __restrict__ partials, int nb,
+                                                         double cfl, double* __restrict__ d_dt) {
+  __shared__ double sh[DT_THREADS / 64];
+  double v[DT_ACC];
+#pragma unroll
+  for (int u = 0; u < DT_ACC; ++u) v[u] = 0.0;
+  int b = threadIdx.x;
+  for (; b + (DT_ACC - 1) * DT_THREADS < nb; b += DT_ACC * DT_THREADS) {
+#pragma unroll
+    for (int u = 0; u < DT_ACC; ++u) v[u] = fmax(v[u], partials[b + u * DT_THREADS]);
+  }
+  for (; b < nb; b += DT_THREADS) v[0] = fmax(v[0], partials[b]);
+#pragma unroll
+  for (int u = 1; u < DT_ACC; ++u) v[0] = fmax(v[0], v[u]);
+  const double w = wave_max(v[0]);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = w;
   __syncthreads();
-  if (threadIdx.x == 0) d_dt[0] = cfl / fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  if (threadIdx.x == 0) {
+    double r = sh[0];
+    for (int q = 1; q < DT_THREADS / 64; ++q) r = fmax(r, sh[q]);
+    d_dt[0] = cfl / r;
+  }
 }
 
 // ------------------------------------------------------------------ curl of a potential
@@ -1019,7 +1037,7 @@ void launch_zero_u64(unsigned long long* p, int n, hipStream_t s) {
 }
 
 void launch_dt_final(const double* cfl_partials, int nb, double cfl, double* d_dt, hipStream_t s) {
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, cfl_partials, nb, cfl, d_dt);
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(DT_THREADS), 0, s, cfl_partials, nb, cfl, d_dt);
 }
 
 void launch_reduce_stats(const long long* partials, int nb, long long* out, hipStream_t s) {
@@ -1042,7 +1060,7 @@ void launch_cfl(const Geom& G, bool flat, const double* prim, const double* tab,
     hipLaunchKernelGGL(k_cfl<FlatMet<double>>, dim3(nb), dim3(256), 0, s, G, prim, tab, partials);
   else
     hipLaunchKernelGGL(k_cfl<TabMet<double>>, dim3(nb), dim3(256), 0, s, G, prim, tab, partials);
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, partials, (int)nb, cfl, d_dt);
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(DT_THREADS), 0, s, partials, (int)nb, cfl, d_dt);
 }
 
 void launch_curl(const Geom& G, const double* a1, const double* a2, const double* a3,
