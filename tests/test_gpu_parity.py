@@ -106,6 +106,31 @@ def test_cfl_dt_matches_oracle():
 
 
 @gpu
+def test_dt_reduction_over_a_ragged_block_count():
+    """136^3 box: 9826 per-block CFL partials, more than one round of the
+    final reduction's eight loads per thread over 1024 threads, plus a
+    remainder.  The device CFL step of the initial state equals the oracle's;
+    the step the last inversion of a step reduces for the next step equals a
+    fresh reduction of the same state by the CFL kernel (a second grid from
+    the same data, stepped the same way)."""
+    _torch()
+    from paper_1810_04597_amd.grid import Grid
+    n = 136
+    nblk = -(-n ** 3 // 256)
+    assert nblk > 8 * 1024 and nblk % (8 * 1024) != 0
+    g, d, s, G = _pair_box(n)
+    assert abs(G.compute_dt() / s.cfl_dt() - 1) < 1e-13
+    G2 = Grid(g)
+    G2.curl_potential(d)
+    G2.set_primitives(d)
+    G.rk_step(0.0)
+    G2.rk_step(0.0)
+    dt_fresh = G2.compute_dt()
+    dt_inv = G.rk_step(0.0, want_dt=True)
+    assert abs(dt_inv / dt_fresh - 1) < 1e-14, (dt_inv, dt_fresh)
+
+
+@gpu
 def test_ten_steps_config0_parity():
     """Turbulent SRMHD box 32^3, 10 SSP-RK3 steps with the device CFL step:
     every zone and field within 1e-10 relative of the oracle."""
