@@ -123,10 +123,12 @@ def _eval_direct_shape(phi, n, offs):
 def turbulent_box_shape(n1, n2, n3, seed=SEED, ng=5):
     """The turbulent box's continuous fields sampled on a periodic unit box
     with n1 x n2 x n3 zones (spacings 1/n_a): the same fields as
-    turbulent_box(n) when n1 = n2 = n3 = n.  Returns (grid, data)."""
+    turbulent_box(n) when n1 = n2 = n3 = n.  Any n_a >= 1: the ghost layers
+    of the potentials wrap as often as a thin direction needs (one zone: a
+    direction the fields do not vary along).  Returns (grid, data)."""
     from .grid import GridSpec, CART, BC_PERIODIC
     n = (n1, n2, n3)
-    assert min(n) >= ng
+    assert min(n) >= 1
     grid = GridSpec(n=n, ng=ng, coord=CART, x0=(0.0, 0.0, 0.0),
                     dx=tuple(1.0 / x for x in n), bc=(BC_PERIODIC,) * 6)
     ph = phases(seed)
