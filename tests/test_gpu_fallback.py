@@ -19,7 +19,9 @@ with the oracle's Solver(fallback=True), through the C ABI.
     images): parity with the oracle, and the centred run rolled by half the
     box bit for bit;
   * where nothing is troubled (the turbulent box) the option changes no bit
-    of the state, eager and graph-replayed, FP64 and FP32 forms.
+    of the state, eager and graph-replayed, FP64 and FP32 forms;
+  * with troubled zones in every step (the blast, the torus), steps replayed
+    from a captured graph equal eager steps bit for bit.
 """
 import numpy as np
 import pytest
@@ -206,3 +208,48 @@ def test_option_changes_nothing_without_troubled_zones(precision, order):
     for a in range(2):
         for k in out[False][a]:
             assert np.array_equal(out[False][a][k], out[True][a][k]), k
+
+
+@gpu
+@pytest.mark.parametrize("case", ["blast", "torus"])
+def test_fallback_in_graph_replays_equals_eager(case):
+    """With troubled zones in every step: device-dt steps replayed from a
+    captured graph equal eager steps bit for bit (the troubled-zone list is
+    filled in whatever order the atomics give, but each face value is formed
+    once and each zone gathers its own), every replay checked, with eager
+    work and synchronisations between the replays; the counters agree."""
+    torch = _torch()
+    from paper_1810_04597_amd.grid import Grid
+    if case == "blast":
+        from workloads import box
+        g, d = box.blast_box(16, b0=0.0)
+        kw = dict(recon="mp5")
+    else:
+        from workloads.torus import torus
+        g, d, tab = torus(48, 24, 24)
+        kw = dict(tables=tab, recon="weno5")
+    grids = []
+    for _ in range(2):
+        G = Grid(g, fallback=True, stream=torch.cuda.Stream(), **kw)
+        if case == "blast":
+            G.set_face_fields(d)
+        else:
+            G.curl_potential(d)
+        G.set_primitives(d)
+        grids.append(G)
+    Ge, Gg = grids
+    troubled = []
+    for rep in range(4):        # the first graph call steps eagerly, then capture and replays
+        Ge.rk_step(0.0)
+        Gg.rk_steps_graph(1)
+        Gg.synchronize()
+        de, dg = Ge.diagnostics(), Gg.diagnostics()
+        troubled.append(de["run_troubled"])
+        assert de["run_troubled"] == dg["run_troubled"], rep
+        ce, cg = Ge.to_numpy("cons"), Gg.to_numpy("cons")
+        for k in ce:
+            assert np.array_equal(ce[k], cg[k], equal_nan=True), (rep, k)
+    print("%s: accumulated troubled zones per step" % case, troubled)
+    assert troubled[0] > 0 and troubled[3] > troubled[0], troubled   # also during the replays
+    for G in grids:
+        G.close()
