@@ -1,7 +1,9 @@
 """Graph replay of the device-dt RK3 step (grmhd_rk_steps_graph): every
 replay is checked against eager steps bit for bit, with the program's own
 eager work and synchronisations between the replays; the graph is dropped and
-captured again when the launch sequence changes."""
+captured again when the launch sequence changes.  Box and torus, and every
+kernel form: FP32, fourth-order derivative on four ghost layers, MP7, WENO5,
+PLM, the learned guess's list pass (the fallback's: test_gpu_fallback.py)."""
 import numpy as np
 import pytest
 
@@ -104,6 +106,46 @@ def test_graph_after_state_change_and_split_change():
         E.rk_step()
     R.rk_steps_graph(2)
     _same(E, R)
+    E.close()
+    R.close()
+
+
+@gpu
+@pytest.mark.parametrize("variant", ["fp32", "d4_ng4", "mp7_ng6", "weno5", "plm", "learned_all"])
+def test_graph_replays_equal_eager_steps_variants(variant):
+    """The other kernel forms in a captured step (16^3 box): the FP32 form,
+    the fourth-order derivative on four ghost layers, MP7 on six, WENO5,
+    PLM, and the learned guess with every zone deferred to the network pass
+    (its list filled by atomics in any order; untrained weights): replays
+    equal eager steps bit for bit, with eager work between them."""
+    torch = _torch()
+    from workloads import box
+    from workloads.mlp_data import init_weights
+    from paper_1810_04597_amd import _lib as L
+    kw, ng = {}, 5
+    if variant == "fp32":
+        kw = dict(precision=1)
+    elif variant == "d4_ng4":
+        kw, ng = dict(deriv_order=4), 4
+    elif variant == "mp7_ng6":
+        kw, ng = dict(recon="mp7"), 6
+    elif variant in ("weno5", "plm"):
+        kw = dict(recon=variant)
+    else:
+        kw = dict(guess=L.GUESS_MLP)
+    g, d = box.turbulent_box(16, ng=ng)
+    E, R = _grids(g, d, **kw)
+    if variant == "learned_all":
+        w = L.mlp_pack(init_weights())
+        for G in (E, R):
+            G.mlp_set_weights(w, np.ones(32, np.float32))
+            G.set_learned_guess(0.0)
+    for rep in range(3):
+        E.rk_step()
+        R.rk_steps_graph(1)
+        _same(E, R)
+        float(torch.sum(R.cons))          # eager work on torch's stream
+        torch.cuda.synchronize()
     E.close()
     R.close()
 
