@@ -3,7 +3,8 @@ allocating path's grmhd_compute_dt, through the C ABI: two calls in a row,
 the second on a smaller grid that reuses the device scratch the first one
 wrote, each result equal bit for bit to compute_dt's (the same kernels reduce
 the same partials in the same order); a grid beyond the scratch's limit is
-refused before any launch."""
+refused before any launch; captured into a graph and replayed after state
+changes, it writes each state's step."""
 import numpy as np
 import pytest
 
@@ -65,3 +66,38 @@ def test_compute_dt_noalloc_refuses_grids_beyond_its_scratch():
     G.close()
     del G
     torch.cuda.empty_cache()
+
+
+@gpu
+def test_compute_dt_noalloc_in_a_captured_graph():
+    """What the call is for: captured into a graph (torch's graph capture on
+    the grid's own stream; the call launches kernels only) and replayed after
+    the state has changed, each replay writes the CFL step of the current
+    state, equal bit for bit to compute_dt's."""
+    torch = _torch()
+    from workloads import box
+    from paper_1810_04597_amd.grid import Grid
+    g, d = box.turbulent_box(48)
+    G = Grid(g, stream=torch.cuda.Stream())
+    G.curl_potential(d)
+    G.set_primitives(d)
+    out = torch.full((1,), -1.0, dtype=torch.float64, device=G.device)
+    G.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=G.stream, capture_error_mode="thread_local"):
+        G.compute_dt_noalloc(out)
+    seen = []
+    for rep in range(3):
+        out.fill_(-1.0)                       # eager work between the replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = float(out.item())
+        assert got == G.compute_dt(), rep
+        seen.append(got)
+        G.rk_step(0.0)                        # a new state for the next replay
+        G.synchronize()
+    print("captured noalloc dt per replay", seen)
+    assert len(set(seen)) == 3
+    del graph
+    G.close()
