@@ -1,7 +1,6 @@
 """The benchmark's roofline arithmetic on the host (no GPU): from a synthetic
 per-kernel profile of 10 steps at 256^3, the dominant kernel's figures and
 the step's, as they can be re-derived by hand."""
-
 import pytest
 
 import bench
